@@ -1,0 +1,400 @@
+"""Plain FP64 reference for the far-field ptychography hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only `tests/`, `__graft_entry__.smoke()` and the
+CPU-baseline leg of `bench.py` may import this module.  It shares no code,
+table or constant generator with the GPU library and imports nothing from it.
+
+Everything is complex128 / float64, uses `numpy.fft` with the unitary
+normalisation as the only library primitive, and loops over frames
+explicitly.  Each function names the passage of the paper it follows
+(Favre-Nicolin et al., "PyNX: high performance computing toolkit for coherent
+X-ray imaging based on operators", arXiv 2008.11511).  The paper names the
+operators and cites the algorithms but prints no ptychography equations
+beyond the exit wave of the ptychography-operator table; where it is silent
+the reading taken is stated in the docstring.
+
+Notation: J frames, K probe modes, N x N frames, object Ny x Nx.
+  obj     [Ny][Nx]        complex
+  probe   [K][N][N]       complex
+  offsets [J][2]          int   top-left corner (oy, ox) of each frame's window
+  iobs    [J][N][N]       float observed intensity, FFT order (q = 0 at [0, 0])
+  mask    [N][N] or None  uint8, 1 = bad detector pixel (shared by all frames)
+  psi     [J][K][N][N]    complex exit waves
+
+Pins (tests/test_oracle_*.py) tie every function to something other than
+itself: brute-force DFT sums, Parseval, idempotence of the modulus
+projection, least-squares solutions, fixed points at the truth, the
+scipy.stats Poisson log-pmf, and central finite differences.  The CG and DM
+*trajectories* over many cycles have no closed form: parity unpinned for the
+multi-cycle trajectories beyond each single step's pins.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "fft2", "ifft2", "offsets_from_positions", "views", "exit_waves",
+    "calc_intensity", "project_modulus", "fourier_project", "overlap_sums",
+    "overlap_denominators", "overlap_update", "ap_cycle", "dm_cycle",
+    "psi_init", "llk", "llk_terms", "ml_grad", "linesearch_coefs",
+    "CGState", "ml_cycle", "simulate_intensity", "UPDATE_OBJECT",
+    "UPDATE_PROBE", "DEFAULT_EPS", "DEFAULT_INERTIA",
+]
+
+UPDATE_OBJECT = 1
+UPDATE_PROBE = 2
+DEFAULT_EPS = 1e-20          # floor on the calculated intensity
+DEFAULT_INERTIA = 1e-2       # delta in alpha = delta * max(denominator)
+
+
+# --------------------------------------------------------------------------
+# Propagation (appendix table of ptychography operators: FT / IFT)
+# --------------------------------------------------------------------------
+
+def fft2(x: np.ndarray) -> np.ndarray:
+    """Unitary forward 2D DFT over the last two axes, sign -1, q=0 at [0,0].
+
+    The paper does not fix the normalisation; the unitary one keeps the
+    observed intensities in photons and makes the propagator its own
+    adjoint's inverse.
+    """
+    return np.fft.fft2(np.asarray(x, dtype=np.complex128), norm="ortho")
+
+
+def ifft2(x: np.ndarray) -> np.ndarray:
+    """Unitary inverse 2D DFT over the last two axes."""
+    return np.fft.ifft2(np.asarray(x, dtype=np.complex128), norm="ortho")
+
+
+# --------------------------------------------------------------------------
+# Scan positions and views (Section 4, PtychoData; operator ObjProbe2Psi)
+# --------------------------------------------------------------------------
+
+def offsets_from_positions(pos_yx: np.ndarray, n: int, obj_shape) -> np.ndarray:
+    """Integer top-left window corner of each scan position.
+
+    Positions are in pixels relative to the object centre (Ny/2, Nx/2).  The
+    window of frame j starts at floor(centre + p_j + 1/2) - N/2 along each
+    axis (round half up, never half to even).  A window that does not fit in
+    the object is an error, never clamped.
+    """
+    pos = np.asarray(pos_yx, dtype=np.float64)
+    ny, nx = obj_shape
+    centre = np.array([ny / 2.0, nx / 2.0])
+    o = np.floor(centre[None, :] + pos + 0.5).astype(np.int64) - n // 2
+    if o.size and (o.min() < 0 or (o[:, 0] > ny - n).any() or (o[:, 1] > nx - n).any()):
+        raise ValueError("scan position window outside the object")
+    return o.astype(np.int32)
+
+
+def views(obj: np.ndarray, offsets: np.ndarray, n: int) -> np.ndarray:
+    """Object patches under each frame window: [J][N][N]."""
+    return np.stack([np.asarray(obj)[oy:oy + n, ox:ox + n] for oy, ox in offsets])
+
+
+def exit_waves(obj: np.ndarray, probe: np.ndarray, offsets: np.ndarray) -> np.ndarray:
+    """Exit waves Psi_jk(r) = O(r + o_j) P_k(r) (ptychography operator table,
+    ObjProbe2Psi: the object times the probe shifted to position j)."""
+    probe = np.asarray(probe, dtype=np.complex128)
+    v = views(np.asarray(obj, dtype=np.complex128), offsets, probe.shape[-1])
+    return v[:, None, :, :] * probe[None, :, :, :]
+
+
+def psi_init(obj, probe, offsets) -> np.ndarray:
+    """DM starting exit waves: the current views (Psi^0 = Phi^0)."""
+    return exit_waves(obj, probe, offsets)
+
+
+# --------------------------------------------------------------------------
+# Modulus projection (operator ApplyAmplitude / PropagateApplyAmplitude)
+# --------------------------------------------------------------------------
+
+def calc_intensity(psi_hat: np.ndarray) -> np.ndarray:
+    """Calculated intensity: incoherent sum over probe modes, [J][N][N]."""
+    return (np.abs(psi_hat) ** 2).sum(axis=1)
+
+
+def project_modulus(psi_hat: np.ndarray, iobs: np.ndarray,
+                    mask: Optional[np.ndarray], eps: float = DEFAULT_EPS) -> np.ndarray:
+    """Replace the Fourier modulus by the observed amplitude.
+
+    With several incoherent probe modes all modes of a pixel share one scale
+    sqrt(Iobs / I), I = sum_k |Psi_k|^2 (floored at eps), so that the
+    projected modes sum to the observed intensity and keep their phases.
+    Bad (masked) pixels are left unchanged.
+    """
+    inten = calc_intensity(psi_hat)
+    scale = np.sqrt(np.asarray(iobs, dtype=np.float64) / np.maximum(inten, eps))
+    if mask is not None:
+        scale = np.where(np.asarray(mask)[None, :, :] != 0, 1.0, scale)
+    return psi_hat * scale[:, None, :, :]
+
+
+def fourier_project(psi: np.ndarray, iobs, mask, eps: float = DEFAULT_EPS) -> np.ndarray:
+    """IFT * ApplyAmplitude * FT on every frame and mode (far field)."""
+    return ifft2(project_modulus(fft2(psi), iobs, mask, eps))
+
+
+# --------------------------------------------------------------------------
+# Object / probe update (operator Psi2ObjProbe; inertia, Section 4)
+# --------------------------------------------------------------------------
+
+def overlap_sums(psi, obj, probe, offsets):
+    """Numerators and denominators of the overlap (least-squares) update.
+
+    numO(r) = sum_jk conj(P_k(r - o_j)) Psi_jk(r - o_j)
+    denO(r) = sum_jk |P_k(r - o_j)|^2
+    numP_k(r) = sum_j conj(O(r + o_j)) Psi_jk(r)
+    denP(r) = sum_j |O(r + o_j)|^2
+    numO and denO use the given probe, numP and denP the given object.
+    """
+    psi = np.asarray(psi, dtype=np.complex128)
+    obj = np.asarray(obj, dtype=np.complex128)
+    probe = np.asarray(probe, dtype=np.complex128)
+    n = probe.shape[-1]
+    num_o = np.zeros(obj.shape, dtype=np.complex128)
+    den_o = np.zeros(obj.shape, dtype=np.float64)
+    num_p = np.zeros(probe.shape, dtype=np.complex128)
+    den_p = np.zeros(probe.shape[1:], dtype=np.float64)
+    p_conj = np.conj(probe)
+    p_int = (np.abs(probe) ** 2).sum(axis=0)
+    for j, (oy, ox) in enumerate(offsets):
+        win = (slice(oy, oy + n), slice(ox, ox + n))
+        num_o[win] += (p_conj * psi[j]).sum(axis=0)
+        den_o[win] += p_int
+        ov = obj[win]
+        num_p += np.conj(ov)[None] * psi[j]
+        den_p += np.abs(ov) ** 2
+    return num_o, den_o, num_p, den_p
+
+
+def overlap_denominators(obj, probe, offsets):
+    """denO and denP alone (they do not depend on the exit waves)."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    probe = np.asarray(probe, dtype=np.complex128)
+    n = probe.shape[-1]
+    den_o = np.zeros(obj.shape, dtype=np.float64)
+    den_p = np.zeros(probe.shape[1:], dtype=np.float64)
+    p_int = (np.abs(probe) ** 2).sum(axis=0)
+    for oy, ox in offsets:
+        den_o[oy:oy + n, ox:ox + n] += p_int
+        den_p += np.abs(obj[oy:oy + n, ox:ox + n]) ** 2
+    return den_o, den_p
+
+
+def overlap_update(obj, probe, psi, offsets, update=UPDATE_OBJECT | UPDATE_PROBE,
+                   inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA):
+    """New object and probe from the exit waves (Psi2ObjProbe).
+
+    Both updates are computed from the same old object and probe (one Jacobi
+    step, a reading the paper leaves open).  The inertia of Section 4 enters
+    as a regularising weight alpha = delta * max(den) that pulls each pixel
+    towards its previous value:  O <- (numO + a_O O) / (denO + a_O).
+    A pixel whose denominator is exactly zero (never illuminated, no
+    inertia) keeps its value.
+    """
+    obj = np.asarray(obj, dtype=np.complex128)
+    probe = np.asarray(probe, dtype=np.complex128)
+    num_o, den_o, num_p, den_p = overlap_sums(psi, obj, probe, offsets)
+    new_obj, new_probe = obj.copy(), probe.copy()
+    if update & UPDATE_OBJECT:
+        a = inertia_obj * den_o.max()
+        d = den_o + a
+        new_obj = np.where(d > 0, (num_o + a * obj) / np.where(d > 0, d, 1.0), obj)
+    if update & UPDATE_PROBE:
+        a = inertia_probe * den_p.max()
+        d = (den_p + a)[None]
+        new_probe = np.where(d > 0, (num_p + a * probe) / np.where(d > 0, d, 1.0), probe)
+    return new_obj, new_probe
+
+
+# --------------------------------------------------------------------------
+# Projection algorithms (operators AP and DM; Section 4 algorithm list)
+# --------------------------------------------------------------------------
+
+def ap_cycle(obj, probe, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
+             inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
+             eps=DEFAULT_EPS):
+    """One alternating-projections cycle: views, Fourier projection of every
+    frame, then one object/probe update from all projected exit waves."""
+    phi = exit_waves(obj, probe, offsets)
+    psi = fourier_project(phi, iobs, mask, eps)
+    return overlap_update(obj, probe, psi, offsets, update, inertia_obj, inertia_probe)
+
+
+def dm_cycle(obj, probe, psi, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
+             inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
+             eps=DEFAULT_EPS):
+    """One difference-map cycle (beta = 1) on persistent exit waves.
+
+    Phi = views of the current object and probe (the overlap projection of
+    the previous cycle's Psi); Psi <- Psi + P_F(2 Phi - Psi) - Phi; then the
+    object and probe are updated from the new Psi.  Returns (obj, probe, psi).
+    """
+    phi = exit_waves(obj, probe, offsets)
+    psi = np.asarray(psi, dtype=np.complex128)
+    psi_new = psi + fourier_project(2.0 * phi - psi, iobs, mask, eps) - phi
+    o, p = overlap_update(obj, probe, psi_new, offsets, update, inertia_obj, inertia_probe)
+    return o, p, psi_new
+
+
+# --------------------------------------------------------------------------
+# Poisson log-likelihood (operator LLK; Section 4, noise models)
+# --------------------------------------------------------------------------
+
+def llk_terms(icalc, iobs, eps=DEFAULT_EPS):
+    """Per-pixel Poisson negative log-likelihood relative to a perfect fit:
+    I - Iobs + Iobs ln(Iobs / I), with 0 ln 0 = 0 and I floored at eps."""
+    i = np.maximum(np.asarray(icalc, dtype=np.float64), eps)
+    o = np.asarray(iobs, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(o > 0, o * np.log(o / i), 0.0)
+    return i - o + t
+
+
+def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS):
+    """(sum over unmasked pixels of all frames, number of those pixels)."""
+    inten = calc_intensity(fft2(exit_waves(obj, probe, offsets)))
+    terms = llk_terms(inten, iobs, eps)
+    if mask is not None:
+        good = np.broadcast_to(np.asarray(mask)[None] == 0, terms.shape)
+    else:
+        good = np.ones(terms.shape, dtype=bool)
+    return float(terms[good].sum()), int(good.sum())
+
+
+def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS):
+    """Gradient of the Poisson LLK w.r.t. object and probe.
+
+    Convention: g = dL/dRe(z) + i dL/dIm(z) (= 2 dL/dz*).  With
+    Psi^_jk = F(P_k O_j), I_j = sum_k |Psi^_jk|^2 and l'(I) = 1 - Iobs/I
+    (0 at bad pixels), the chain rule through the unitary F gives
+      psi_jk = F^-1(l'(I_j) Psi^_jk)
+      g_O = 2 sum_jk S_j^T (conj(P_k) psi_jk)
+      g_P_k = 2 sum_j conj(O_j) psi_jk
+    Returns (g_obj, g_probe, llk_sum).
+    """
+    obj = np.asarray(obj, dtype=np.complex128)
+    probe = np.asarray(probe, dtype=np.complex128)
+    n = probe.shape[-1]
+    phi_hat = fft2(exit_waves(obj, probe, offsets))
+    inten = np.maximum(calc_intensity(phi_hat), eps)
+    io = np.asarray(iobs, dtype=np.float64)
+    dl = 1.0 - io / inten
+    terms = llk_terms(inten, io, eps)
+    if mask is not None:
+        bad = np.asarray(mask)[None] != 0
+        dl = np.where(bad, 0.0, dl)
+        terms = np.where(bad, 0.0, terms)
+    psi = ifft2(dl[:, None] * phi_hat)
+    g_o = np.zeros(obj.shape, dtype=np.complex128)
+    g_p = np.zeros(probe.shape, dtype=np.complex128)
+    for j, (oy, ox) in enumerate(offsets):
+        win = (slice(oy, oy + n), slice(ox, ox + n))
+        g_o[win] += 2.0 * (np.conj(probe) * psi[j]).sum(axis=0)
+        g_p += 2.0 * np.conj(obj[win])[None] * psi[j]
+    return g_o, g_p, float(terms.sum())
+
+
+def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_EPS):
+    """First and second derivative of L(gamma) = LLK(O + g dO, P + g dP) at 0.
+
+    The exit wave along the line is A + gamma B + gamma^2 C with
+    A = F(P O_j), B = F(P dO_j + dP O_j), C = F(dP dO_j), so
+      I(gamma) = I0 + gamma I1 + gamma^2 I2 + O(gamma^3)
+      I1 = 2 Re sum_k conj(A_k) B_k,   I2 = sum_k |B_k|^2 + 2 Re sum_k conj(A_k) C_k
+      L'(0) = sum l'(I0) I1,  L''(0) = sum [l''(I0) I1^2 + 2 l'(I0) I2]
+    with l' = 1 - Iobs/I0, l'' = Iobs/I0^2, both 0 at bad pixels (the
+    quadratic line search of the Poisson ML conjugate gradient the paper
+    cites, Thibault & Guizar-Sicairos 2012).
+    """
+    a = fft2(exit_waves(obj, probe, offsets))
+    b = fft2(exit_waves(obj, dprobe, offsets) + exit_waves(dobj, probe, offsets))
+    c = fft2(exit_waves(dobj, dprobe, offsets))
+    i0 = np.maximum(calc_intensity(a), eps)
+    i1 = 2.0 * (np.conj(a) * b).real.sum(axis=1)
+    i2 = (np.abs(b) ** 2).sum(axis=1) + 2.0 * (np.conj(a) * c).real.sum(axis=1)
+    io = np.asarray(iobs, dtype=np.float64)
+    d1 = 1.0 - io / i0
+    d2 = io / (i0 * i0)
+    if mask is not None:
+        bad = np.asarray(mask)[None] != 0
+        d1 = np.where(bad, 0.0, d1)
+        d2 = np.where(bad, 0.0, d2)
+    return float((d1 * i1).sum()), float((d2 * i1 * i1 + 2.0 * d1 * i2).sum())
+
+
+# --------------------------------------------------------------------------
+# Conjugate-gradient ML cycle (operator ML)
+# --------------------------------------------------------------------------
+
+def _dot(a, b) -> float:
+    """Real inner product Re sum conj(a) b."""
+    return float(np.vdot(a, b).real)
+
+
+@dataclass
+class CGState:
+    """Search direction and previous gradient carried between ML cycles."""
+    d_obj: Optional[np.ndarray] = None
+    d_probe: Optional[np.ndarray] = None
+    g_obj: Optional[np.ndarray] = None
+    g_probe: Optional[np.ndarray] = None
+    zg: float = 0.0
+    history: list = field(default_factory=list)
+
+
+def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
+             update=UPDATE_OBJECT, eps=DEFAULT_EPS):
+    """One Polak-Ribiere (PR+) conjugate-gradient step on the Poisson LLK.
+
+    The probe block of the gradient is scaled by s = max(denO) / max(denP)
+    (a diagonal preconditioner that balances object and probe steps);
+    z = (g_O, s g_P); beta = max(0, <z_n, g_n - g_{n-1}> / <z_{n-1}, g_{n-1}>)
+    (0 on the first cycle); d = -z + beta d_prev; the step gamma = -L'(0)/L''(0)
+    from `linesearch_coefs` (0 when L''(0) <= 0).  Blocks not being updated
+    have zero gradient.  Returns (obj, probe) and updates `state` in place;
+    `state.history` receives the LLK at the start of the cycle.
+    """
+    obj = np.asarray(obj, dtype=np.complex128)
+    probe = np.asarray(probe, dtype=np.complex128)
+    g_o, g_p, lsum = ml_grad(obj, probe, offsets, iobs, mask, eps)
+    if not update & UPDATE_OBJECT:
+        g_o = np.zeros_like(g_o)
+    if not update & UPDATE_PROBE:
+        g_p = np.zeros_like(g_p)
+    den_o, den_p = overlap_denominators(obj, probe, offsets)
+    s = den_o.max() / den_p.max() if den_p.max() > 0 else 1.0
+    zg = _dot(g_o, g_o) + s * _dot(g_p, g_p)
+    if state.d_obj is None or state.zg <= 0.0:
+        beta = 0.0
+        d_o = -g_o
+        d_p = -s * g_p
+    else:
+        num = _dot(g_o, g_o - state.g_obj) + s * _dot(g_p, g_p - state.g_probe)
+        beta = max(0.0, num / state.zg)
+        d_o = -g_o + beta * state.d_obj
+        d_p = -s * g_p + beta * state.d_probe
+    l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps)
+    gamma = -l1 / l2 if (l2 > 0.0 and math.isfinite(l1) and math.isfinite(l2)) else 0.0
+    state.d_obj, state.d_probe = d_o, d_p
+    state.g_obj, state.g_probe = g_o, g_p
+    state.zg = zg
+    state.history.append(lsum)
+    return obj + gamma * d_o, probe + gamma * d_p
+
+
+# --------------------------------------------------------------------------
+# Forward model for simulation (Section 4, simulation functions)
+# --------------------------------------------------------------------------
+
+def simulate_intensity(obj, probe, offsets, chunk: int = 64) -> np.ndarray:
+    """Noise-free far-field intensities sum_k |F(P_k O_j)|^2, float64 [J][N][N]."""
+    out = []
+    for s in range(0, len(offsets), chunk):
+        out.append(calc_intensity(fft2(exit_waves(obj, probe, offsets[s:s + chunk]))))
+    return np.concatenate(out, axis=0)
