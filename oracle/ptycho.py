@@ -190,22 +190,26 @@ def overlap_update(obj, probe, psi, offsets, update=UPDATE_OBJECT | UPDATE_PROBE
                    inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA):
     """New object and probe from the exit waves (Psi2ObjProbe).
 
-    Both updates are computed from the same old object and probe (one Jacobi
-    step, a reading the paper leaves open).  The inertia of Section 4 enters
-    as a regularising weight alpha = delta * max(den) that pulls each pixel
-    towards its previous value:  O <- (numO + a_O O) / (denO + a_O).
-    A pixel whose denominator is exactly zero (never illuminated, no
-    inertia) keeps its value.
+    The object is updated first, from the current probe; the probe is then
+    updated from the *new* object (one Gauss-Seidel sweep; the paper does not
+    say).  Updating both from the same old pair instead lets each factor absorb
+    the same scale, so their product overshoots and the DM iteration diverges
+    (tests/test_oracle_pins.py shows it).  The inertia of Section 4 enters as
+    a regularising weight alpha = delta * max(den) that pulls each pixel
+    towards its previous value:  O <- (numO + a_O O) / (denO + a_O).  A pixel
+    whose denominator is exactly zero (never illuminated, no inertia) keeps
+    its value.
     """
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
-    num_o, den_o, num_p, den_p = overlap_sums(psi, obj, probe, offsets)
     new_obj, new_probe = obj.copy(), probe.copy()
     if update & UPDATE_OBJECT:
+        num_o, den_o, _, _ = overlap_sums(psi, obj, probe, offsets)
         a = inertia_obj * den_o.max()
         d = den_o + a
         new_obj = np.where(d > 0, (num_o + a * obj) / np.where(d > 0, d, 1.0), obj)
     if update & UPDATE_PROBE:
+        _, _, num_p, den_p = overlap_sums(psi, new_obj, probe, offsets)
         a = inertia_probe * den_p.max()
         d = (den_p + a)[None]
         new_probe = np.where(d > 0, (num_p + a * probe) / np.where(d > 0, d, 1.0), probe)

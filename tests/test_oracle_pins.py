@@ -222,9 +222,9 @@ def test_probe_update_is_least_squares():
     np.testing.assert_array_equal(o, obj)
 
 
-def test_update_is_jacobi_and_inertia_closed_form():
+def test_update_order_and_inertia_closed_form():
     # One frame, constant probe c: O_new = (conj(c) psi + a O)/( |c|^2 + a ),
-    # a = delta * |c|^2 (max of denO); probe from the OLD object.
+    # a = delta * |c|^2 (max of denO); the probe then uses the NEW object.
     n = 4
     c = 1.5 - 0.5j
     obj = crandn(6, 6)
@@ -234,14 +234,27 @@ def test_update_is_jacobi_and_inertia_closed_form():
     d = 0.25
     o, p = oracle.overlap_update(obj, probe, psi, offs, inertia_obj=d, inertia_probe=d)
     a = d * abs(c) ** 2
-    win = obj[1:5, 2:6]
-    np.testing.assert_allclose(o[1:5, 2:6], (np.conj(c) * psi[0, 0] + a * win) / (abs(c) ** 2 + a), rtol=1e-13)
+    win_new = (np.conj(c) * psi[0, 0] + a * obj[1:5, 2:6]) / (abs(c) ** 2 + a)
+    np.testing.assert_allclose(o[1:5, 2:6], win_new, rtol=1e-13)
     untouched = np.ones((6, 6), bool)
     untouched[1:5, 2:6] = False
     np.testing.assert_allclose(o[untouched], obj[untouched], rtol=1e-15)
-    den_p = abs(win) ** 2
+    den_p = abs(win_new) ** 2
     ap = d * den_p.max()
-    np.testing.assert_allclose(p[0], (np.conj(win) * psi[0, 0] + ap * c) / (den_p + ap), rtol=1e-13)
+    np.testing.assert_allclose(p[0], (np.conj(win_new) * psi[0, 0] + ap * c) / (den_p + ap), rtol=1e-12)
+
+
+def test_update_resolves_the_scale_ambiguity():
+    # Exit waves that are exactly c * (O P): the object absorbs c, the probe
+    # then stays put, so the product matches the exit waves (no overshoot).
+    n = 4
+    obj = crandn(8, 8)
+    probe = crandn(2, n, n)
+    offs = np.array([[0, 0], [2, 3], [4, 1], [3, 4]], np.int32)
+    c = 1.7 * np.exp(0.4j)
+    psi = c * oracle.exit_waves(obj, probe, offs)
+    o, p = oracle.overlap_update(obj, probe, psi, offs, inertia_obj=0.0, inertia_probe=0.0)
+    np.testing.assert_allclose(oracle.exit_waves(o, p, offs), psi, rtol=1e-10, atol=1e-12)
 
 
 # ----------------------------------------------------------------------------
@@ -436,3 +449,19 @@ def test_generator_shapes_and_scaling():
     np.testing.assert_allclose(inten.sum(axis=(1, 2)).mean(), 1e6, rtol=1e-10)
     m = synth.gap_mask(256, 0.02, 1)
     assert abs(m.mean() - 6 * 256 / 256 ** 2) < 1e-12
+
+
+def test_dm_stays_bounded_over_many_cycles():
+    """With the object-then-probe update the DM iteration on noisy data stays
+    bounded and does not lose likelihood (it diverged by orders of magnitude
+    when both factors were updated from the same old pair)."""
+    import cases
+    wl = cases.small("dm256", n=64, k=2, j=80, obj=(256, 256), step=6.0, mask_frac=0.03)
+    pb = cases.make_problem(wl, start="ml")
+    o, p = pb.obj0, pb.probe0
+    psi = oracle.psi_init(o, p, pb.offsets)
+    l0 = oracle.llk(o, p, pb.offsets, pb.iobs, pb.mask)[0]
+    for _ in range(30):
+        o, p, psi = oracle.dm_cycle(o, p, psi, pb.offsets, pb.iobs, pb.mask)
+    assert np.abs(o).max() < 3.0
+    assert oracle.llk(o, p, pb.offsets, pb.iobs, pb.mask)[0] < 2 * l0
