@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Benchmark of the far-field ptychography hot path on one MI355X.
+
+A step is one difference-map cycle (views x probe, far-field FFT, modulus
+projection with the gap mask, inverse FFT, DM combination, object update,
+probe update) over all 1000 frames of the DM workload: 256x256 frames, 3
+probe modes, object 1024x1024, 1e8 photons per frame, 2% gap mask.  The
+throughput is frames*cycles/s; a second leg times conjugate-gradient ML
+cycles (gradient + line search + step) on the ML workload (500 frames).
+
+Inputs are synthetic and built on the GPU: the seeded truth, probe modes,
+spiral positions and mask come from `synth`; the integer offsets and the
+noise-free intensities come from the library (its host offset routine and
+forward model), the Poisson draw from torch.  Everything is resident in HBM
+before the timed region.  The CPU baseline times the FP64 oracle on a
+bounded sample of the same scan (its own intensities from its own forward
+model) on the host cores.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2008_11511_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def build_workload(wl, torch, dev, start):
+    """Seeded inputs of one workload, resident on the GPU."""
+    import synth
+    import paper_2008_11511_amd as P
+    obj_t = synth.object_truth(wl.obj_shape, wl.seed)
+    probe_t = synth.probe_modes(wl.n, wl.n_modes, wl.seed)
+    pos = synth.spiral_positions(wl.n_frames, wl.step)
+    offs = P.offsets_from_positions(pos, wl.n, wl.obj_shape)
+    probe_t = probe_t * synth.probe_photon_scale(obj_t, probe_t, offs, wl.photons)
+    o_t = torch.from_numpy(obj_t.astype(np.complex64)).to(dev)
+    p_t = torch.from_numpy(probe_t.astype(np.complex64)).to(dev)
+    zero = torch.zeros((wl.n_frames, wl.n, wl.n), dtype=torch.float32, device=dev)
+    sim = P.Plan(offs, zero, None, wl.n_modes, wl.obj_shape)
+    inten = sim.icalc(o_t, p_t)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(wl.seed)
+    iobs = torch.poisson(inten.clamp_min(0), generator=gen).contiguous()
+    del sim, zero, inten
+    m = synth.gap_mask(wl.n, wl.mask_frac, wl.seed)
+    mask = torch.from_numpy(m).to(dev) if m is not None else None
+    if start == "ml":
+        o0 = synth.perturb_object(obj_t, wl.seed)
+        p0 = synth.perturb_probe(probe_t, wl.seed)
+    else:
+        o0 = synth.start_object(wl.obj_shape)
+        p0 = synth.start_probe(probe_t)
+    o0 = torch.from_numpy(o0.astype(np.complex64)).to(dev)
+    p0 = torch.from_numpy(p0.astype(np.complex64)).to(dev)
+    return offs, iobs, mask, o0, p0, (obj_t, probe_t, pos, m)
+
+
+def algorithmic_bytes(wl, nstacks, kind):
+    """Compulsory bytes per cycle of each kernel class (each input element read
+    once, each output written once): U = 8 N^2 (complex frame), W = 4 N^2."""
+    J, K, N = wl.n_frames, wl.n_modes, wl.n
+    U, W = 8 * N * N, 4 * N * N
+    ny, nx = wl.obj_shape
+    obj_sums = ny * nx * (8 + 4)
+    out = {}
+    if kind == "dm":
+        out["rows_fwd"] = J * ((2 * K + 1) * U)              # read Psi, view; write stack
+        out["cols"] = J * (2 * K * U + W)                    # read+write stack, read Iobs
+        out["rows_inv"] = J * ((3 * K + 1) * U)              # read stack, Psi, view; write Psi
+        out["gather_obj"] = J * K * U + 2 * obj_sums         # read Psi; object sums
+        out["probe_all"] = J * (K * U + U)                   # read Psi and views
+    return out
+
+
+def timed_dm(plan, o, p, psi, steps, warmup, torch):
+    plan.dm_cycle(o, p, psi, warmup, 3)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    t0 = time.perf_counter()
+    plan.dm_cycle(o, p, psi, steps, 3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    per = plan.timing_read()
+    plan.timing(False)
+    return dt, per
+
+
+def cpu_baseline(wl, truth, sample):
+    """FP64 oracle, one DM cycle over the first `sample` frames of the scan."""
+    import oracle
+    import synth
+    obj_t, probe_t, pos, m = truth
+    pos_s = pos[:sample]
+    offs = oracle.offsets_from_positions(pos_s, wl.n, wl.obj_shape)
+    inten = oracle.simulate_intensity(obj_t, probe_t, offs)
+    iobs = synth.poisson_counts(inten, wl.seed)
+    o0 = synth.start_object(wl.obj_shape)
+    p0 = synth.start_probe(probe_t)
+    psi = oracle.psi_init(o0, p0, offs)
+    t0 = time.perf_counter()
+    oracle.dm_cycle(o0, p0, psi, offs, iobs, m)
+    dt = time.perf_counter() - t0
+    return sample / dt, dt
+
+
+def traffic_for(kernel, launches_per_cycle):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        if t.get("source_sha") != source_sha():
+            return None
+        e = t["kernels"].get(kernel)
+        return None if e is None else e["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ml-steps", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=300, help="frames of the oracle CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ml", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part of "
+              f"this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2008_11511_amd as P
+    P.lib()                                    # the HIP library must be there
+    dev = torch.device("cuda:0")
+
+    wl = synth.workload("dm256")
+    log(f"building {wl.name}: {wl.n_frames} frames {wl.n}x{wl.n}, {wl.n_modes} modes")
+    offs, iobs, mask, o, p, truth = build_workload(wl, torch, dev, "apdm")
+    plan = P.Plan(offs, iobs, mask, wl.n_modes, wl.obj_shape)
+    psi = plan.psi_init(o, p)
+    stack = plan.stack
+    torch.cuda.synchronize()
+    log(f"plan stack={plan.stack}; warmup {args.warmup} + timed {args.steps} DM cycles")
+    dt, per = timed_dm(plan, o, p, psi, args.steps, args.warmup, torch)
+    llk = plan.llk(o, p).cpu().numpy()
+    value = wl.n_frames * args.steps / dt
+    log(f"DM: {dt / args.steps * 1e3:.3f} ms/cycle, {value:.0f} frames*cycles/s, llk/n={llk[0] / llk[1]:.4g}")
+
+    nstacks = math.ceil(wl.n_frames / plan.stack)
+    algo = algorithmic_bytes(wl, nstacks, "dm")
+    kernels = {}
+    for name, (ms, n) in per.items():
+        if n == 0:
+            continue
+        d = {"ms_total": ms, "launches": n, "avg_us": 1e3 * ms / n}
+        if name in algo:
+            bpl = algo[name] * args.steps / n
+            d["alg_bytes_per_launch"] = bpl
+            d["alg_GBs"] = bpl / (ms / n * 1e-3) / 1e9
+        kernels[name] = d
+    dom = max((k for k in kernels if k in algo), key=lambda k: kernels[k]["ms_total"])
+    dk = kernels[dom]
+    achieved = dk["alg_GBs"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for(dom, nstacks),
+                "alg_bytes_per_launch": dk["alg_bytes_per_launch"], "avg_launch_us": round(dk["avg_us"], 2)}
+    cycle_alg = sum(algo.values())
+    whole = {"alg_bytes_per_cycle": cycle_alg, "alg_GBs": cycle_alg / (dt / args.steps) / 1e9}
+    whole["frac"] = whole["alg_GBs"] / HBM_PEAK_GBS
+
+    ml = None
+    if not args.no_ml:
+        del psi, plan
+        torch.cuda.empty_cache()
+        wl2 = synth.workload("ml256")
+        log(f"building {wl2.name}: {wl2.n_frames} frames, ML leg ({args.ml_steps} CG cycles)")
+        offs2, iobs2, mask2, o2, p2, _ = build_workload(wl2, torch, dev, "ml")
+        plan2 = P.Plan(offs2, iobs2, mask2, wl2.n_modes, wl2.obj_shape)
+        st = plan2.ml_state()
+        hist = torch.zeros(args.ml_steps, dtype=torch.float64, device=dev)
+        plan2.ml_cycle(o2, p2, st, 2, 3, reset=True, hist=hist[:2].contiguous())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan2.ml_cycle(o2, p2, st, args.ml_steps, 3, reset=False, hist=hist)
+        torch.cuda.synchronize()
+        dt2 = time.perf_counter() - t0
+        h = hist.cpu().numpy()
+        ml = {"workload": "ml256", "frames": wl2.n_frames, "cycles": args.ml_steps,
+              "ms_per_cycle": round(dt2 / args.ml_steps * 1e3, 3),
+              "frames_cycles_per_s": round(wl2.n_frames * args.ml_steps / dt2, 1),
+              "llk_first": float(h[0]), "llk_last": float(h[-1])}
+        log(f"ML: {ml['ms_per_cycle']} ms/cycle, {ml['frames_cycles_per_s']} frames*cycles/s")
+        del plan2, st
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB device-to-device")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU baseline: FP64 oracle, one DM cycle over {args.cpu_sample} frames")
+        fcs, t = cpu_baseline(wl, truth, args.cpu_sample)
+        cores = 1
+        cpu = {"value": round(fcs, 3), "unit": "frames*cycles/s", "cores": cores, "kind": "oracle",
+               "sample": f"one DM cycle over the first {args.cpu_sample} of {wl.n_frames} frames of the same "
+                         f"scan (256x256, 3 modes), {t:.1f} s; numpy FFT single-threaded",
+               "host_cpus": len(os.sched_getaffinity(0))}
+        log(f"CPU oracle: {fcs:.2f} frames*cycles/s ({t:.1f} s)")
+
+    out = {
+        "metric": "frames*cycles/s (256^2 frames, 3 modes) & %HBM roofline",
+        "value": round(value, 1),
+        "unit": "frames*cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded truth, spiral scan, Poisson counts from the library's forward model)",
+        "config": {"workload": "dm256: DM cycles, 1000 frames 256x256, 3 probe modes, object 1024x1024, "
+                               "1e8 photons/frame, 2% gap mask",
+                   "frames": wl.n_frames, "frame": wl.n, "modes": wl.n_modes, "object": list(wl.obj_shape),
+                   "stack": stack, "algorithm": "DM (beta=1), object+probe update"},
+        "roofline": roofline,
+        "cycle_roofline": whole,
+        "kernels": kernels,
+        "ml": ml,
+        "cpu_baseline": cpu,
+        "paper_context": {"value": 22727, "unit": "frames*cycles/s",
+                          "note": "DM 44 ms/cycle, 1000 frames 256x256, 3 probe modes, object 1176x1188, "
+                                  "one NVIDIA V100 (Table 1); other hardware, context only"},
+        "source_sha": source_sha(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

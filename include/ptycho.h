@@ -1,0 +1,217 @@
+/*
+ * ptycho.h - C ABI of the far-field ptychography hot path for AMD MI355X
+ * (gfx950).
+ *
+ * The library implements the data-parallel core of operator-based
+ * ptychographic reconstruction as described in Favre-Nicolin et al., "PyNX:
+ * high performance computing toolkit for coherent X-ray imaging based on
+ * operators" (arXiv 2008.11511), Section 4 and the appendix table of
+ * ptychography operators: exit waves (ObjProbe2Psi), far-field propagation
+ * (FT / IFT), the modulus constraint (ApplyAmplitude), the object and probe
+ * update (Psi2ObjProbe), the AP and DM cycles, the Poisson log-likelihood
+ * (LLK) and the conjugate-gradient ML refinement built on its gradient.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Complex arrays are interleaved single precision (re, im) pairs, passed
+ *    as float*; "complex[n]" below means 2*n floats.  All arrays are
+ *    row-major and densely packed.
+ *  - obj   : complex[obj_ny][obj_nx]          object O
+ *    probe : complex[K][N][N]                 probe modes P_k
+ *    psi   : complex[J][K][N][N]              exit waves (DM state)
+ *    iobs  : float[J][N][N]                   observed counts, FFT order
+ *                                              (zero frequency at [0][0])
+ *    mask  : uint8[N][N]                      1 = bad detector pixel, shared
+ *                                              by all frames; NULL = none
+ *  - The 2D transforms are unitary, forward sign -1.
+ *  - Frame j covers obj[oy_j .. oy_j+N-1][ox_j .. ox_j+N-1] with integer
+ *    top-left offsets (oy_j, ox_j); exit wave Psi_jk[y][x] =
+ *    O[oy_j+y][ox_j+x] * P_k[y][x].
+ *  - "dev" pointers are device memory on the plan's device, owned by the
+ *    caller; the library never frees them.  "host" pointers are read during
+ *    the call only.
+ *  - Every GPU entry point enqueues its work on the plan's stream and
+ *    returns without synchronising (the paper's asynchronous-execution rule,
+ *    Section 2): outputs are valid once the caller synchronises that stream.
+ *    A plan must not be used from two host threads at once.  Two plans on
+ *    different streams may run concurrently.
+ *  - Errors: every function returns a ptycho_status.  Argument, size and
+ *    bounds errors are detected on the host before anything is enqueued, so
+ *    no state is modified.  A failed kernel launch returns PTYCHO_E_HIP.
+ *    ptycho_last_error() gives a message for the calling thread's last
+ *    failure.  Nothing throws across this interface.
+ */
+#ifndef PTYCHO_H
+#define PTYCHO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PTYCHO_OK = 0,
+    PTYCHO_E_INVALID = -1,      /* bad argument (null pointer, size, flag)   */
+    PTYCHO_E_BOUNDS = -2,       /* a frame window falls outside the object   */
+    PTYCHO_E_UNSUPPORTED = -3,  /* N not a supported power of two, K > 4      */
+    PTYCHO_E_HIP = -4,          /* HIP runtime / launch error                 */
+    PTYCHO_E_WORKSPACE = -5     /* workspace missing, too small or misaligned */
+} ptycho_status;
+
+/* Update flags for the cycle entry points. */
+#define PTYCHO_UPDATE_OBJECT 1u
+#define PTYCHO_UPDATE_PROBE  2u
+
+/* Problem description.  Supported: N in {16, 32, 64, 128, 256, 512},
+ * 1 <= K <= 4, J >= 1, obj_ny >= N, obj_nx >= N. */
+typedef struct {
+    int32_t n;              /* frame side N (power of two)                      */
+    int32_t n_modes;        /* incoherent probe modes K                         */
+    int32_t n_frames;       /* scan positions J                                 */
+    int32_t obj_ny;         /* object rows                                      */
+    int32_t obj_nx;         /* object columns                                   */
+    int32_t stack;          /* frames per launch; 0 = automatic (the paper's
+                               stack of frames, Section 4)                      */
+    float obj_inertia;      /* delta_O: alpha_O = delta_O * max(denO)           */
+    float probe_inertia;    /* delta_P: alpha_P = delta_P * max(denP)           */
+    float icalc_floor;      /* epsilon: calculated intensity floor              */
+    uint32_t flags;         /* reserved, must be 0                              */
+} ptycho_desc_t;
+
+typedef struct ptycho_plan_s *ptycho_plan_t;
+
+/* Scan positions -> integer window offsets (host only, no GPU work).
+ * pos_yx_host: double[J][2], pixels relative to the object centre
+ * (obj_ny/2, obj_nx/2).  offsets_out_host: int32[J][2] receives
+ * floor(centre + p + 0.5) - N/2 per axis (round half up).  Returns
+ * PTYCHO_E_BOUNDS, writing nothing, if any window leaves the object.
+ * (Section 4: PtychoData holds the probe translation positions; the exit
+ * wave of the ptychography-operator table shifts the probe by r_j.) */
+int ptycho_offsets_from_positions(const double *pos_yx_host, int32_t n_frames,
+                                  int32_t n, int32_t obj_ny, int32_t obj_nx,
+                                  int32_t *offsets_out_host);
+
+/* Device workspace needed by a plan for `desc`, in bytes (host only). */
+int ptycho_workspace_bytes(const ptycho_desc_t *desc, size_t *bytes_out);
+
+/* Create a plan.  offsets_host: int32[J][2] window offsets (checked against
+ * the object bounds).  iobs_dev / mask_dev: observed data and bad-pixel mask
+ * (mask may be NULL); the plan keeps these pointers, which must stay valid
+ * for the plan's life.  workspace_dev: at least ptycho_workspace_bytes()
+ * bytes, 256-byte aligned, owned by the caller, used exclusively by this
+ * plan.  stream: a hipStream_t (NULL = default stream).  The call copies the
+ * index tables to the workspace on `stream` and returns the handle in *out. */
+int ptycho_plan_create(const ptycho_desc_t *desc, const int32_t *offsets_host,
+                       const float *iobs_dev, const uint8_t *mask_dev,
+                       void *workspace_dev, size_t workspace_bytes,
+                       void *stream, ptycho_plan_t *out);
+
+/* Change the stream later calls enqueue on (hipStream_t). */
+int ptycho_plan_set_stream(ptycho_plan_t plan, void *stream);
+
+/* Frames per launch actually used by the plan. */
+int ptycho_plan_stack(ptycho_plan_t plan, int32_t *stack_out);
+
+/* Free the host-side plan.  Device buffers are untouched. */
+int ptycho_plan_destroy(ptycho_plan_t plan);
+
+/* n_cycles alternating-projection cycles (operator AP): for every frame and
+ * mode Psi = IFT * ApplyAmplitude * FT (O_j P_k); then the overlap update
+ * (Psi2ObjProbe) from all frames, object first, then the probe from the new
+ * object, each with inertia alpha = delta * max(den):
+ *   O <- (sum_jk conj(P_k) Psi_jk + alpha_O O) / (sum_jk |P_k|^2 + alpha_O)
+ *   P_k <- (sum_j conj(O_j) Psi_jk + alpha_P P_k) / (sum_j |O_j|^2 + alpha_P)
+ * (pixels with a zero denominator keep their value).
+ * update: PTYCHO_UPDATE_OBJECT | PTYCHO_UPDATE_PROBE.  obj, probe: in/out.
+ * psi_dev: complex[J][K][N][N] storage for the projected exit waves, needed
+ * (PTYCHO_E_INVALID otherwise) when the probe is updated, since the probe
+ * update runs after the object update over all frames; may be NULL for an
+ * object-only update.  On return it holds the last cycle's exit waves. */
+int ptycho_ap_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
+                    float *psi_dev, int32_t n_cycles, uint32_t update);
+
+/* n_cycles difference-map cycles (operator DM, beta = 1) on the persistent
+ * exit waves psi (in/out, complex[J][K][N][N]):
+ *   Psi <- Psi + IFT ApplyAmplitude FT (2 Phi - Psi) - Phi,  Phi = O_j P_k
+ * followed by the overlap update of obj / probe as in ptycho_ap_cycle
+ * (object, then probe from the new object). */
+int ptycho_dm_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
+                    float *psi_dev, int32_t n_cycles, uint32_t update);
+
+/* psi <- O_j P_k for every frame and mode (DM starting point). */
+int ptycho_psi_init(ptycho_plan_t plan, const float *obj_dev,
+                    const float *probe_dev, float *psi_dev);
+
+/* Poisson log-likelihood (operator LLK): llk_dev (double[2], device)
+ * receives { sum over unmasked pixels of all frames of
+ * I - Iobs + Iobs ln(Iobs / I), number of those pixels }, with
+ * I = sum_k |FT(O_j P_k)|^2 floored at icalc_floor, 0 ln 0 = 0. */
+int ptycho_llk(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
+               double *llk_dev);
+
+/* Gradient of that LLK (maximum-likelihood operator ML):
+ * g = dL/dRe + i dL/dIm, i.e. with psi_jk = IFT((1 - Iobs/I) FT(O_j P_k))
+ * (zero at bad pixels):
+ *   g_obj   = 2 sum_jk S_j^T (conj(P_k) psi_jk)       complex[obj_ny][obj_nx]
+ *   g_probe = 2 sum_j conj(O_j) psi_jk                 complex[K][N][N]
+ * llk_dev (nullable, double[2]) receives the LLK as ptycho_llk. */
+int ptycho_ml_grad(ptycho_plan_t plan, const float *obj_dev,
+                   const float *probe_dev, float *g_obj_dev,
+                   float *g_probe_dev, double *llk_dev);
+
+/* Line-search coefficients along (d_obj, d_probe): coef_dev (double[2],
+ * device) receives { L'(0), L''(0) } of L(g) = LLK(O + g dO, P + g dP), with
+ * L'' from the quadratic expansion of the intensity in g (Poisson ML
+ * conjugate gradient, the method the paper cites for ML). */
+int ptycho_ml_linesearch(ptycho_plan_t plan, const float *obj_dev,
+                         const float *probe_dev, const float *d_obj_dev,
+                         const float *d_probe_dev, double *coef_dev);
+
+/* Device state of the conjugate-gradient ML iteration, in bytes, for
+ * ptycho_ml_cycle (host only). */
+int ptycho_ml_state_bytes(ptycho_plan_t plan, size_t *bytes_out);
+
+/* n_cycles Polak-Ribiere conjugate-gradient ML cycles on the Poisson LLK,
+ * entirely on the device (no host synchronisation): gradient, preconditioned
+ * direction (probe block scaled by max(denO)/max(denP)), quadratic line
+ * search, step.  state_dev: ptycho_ml_state_bytes() bytes, 256-byte aligned;
+ * reset != 0 starts a new conjugate sequence (beta = 0).  llk_hist_dev
+ * (nullable, double[n_cycles]) receives the LLK at the start of each cycle. */
+int ptycho_ml_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
+                    void *state_dev, int32_t n_cycles, uint32_t update,
+                    int32_t reset, double *llk_hist_dev);
+
+/* Calculated intensity sum_k |FT(O_j P_k)|^2 of every frame into
+ * icalc_dev (float[J][N][N], FFT order); the forward model used to simulate
+ * data. */
+int ptycho_icalc(ptycho_plan_t plan, const float *obj_dev,
+                 const float *probe_dev, float *icalc_dev);
+
+/* Batched unitary 2D FFT of `count` complex N x N frames in place
+ * (direction -1 forward, +1 inverse), exposed for tests and the FFT
+ * bandwidth benchmark of the paper's appendix (FFT performance). */
+int ptycho_fft2(int32_t n, int32_t count, float *data_dev, int32_t direction,
+                void *stream);
+
+/* Per-kernel timing for diagnostics and benchmarks: with enable != 0 the
+ * plan records a HIP event pair on its stream around every later launch of
+ * each kernel class (0 forward row FFTs, 1 column FFT + Fourier-space step,
+ * 2 inverse row FFTs, 3 object gather, 4 per-stack probe gather, 5 all-frame
+ * probe gather, 6 normalisation, 7 other); enable = 0 stops recording.
+ * ptycho_plan_timing_read waits for the last recorded event and returns the
+ * summed milliseconds and the launch count of one class since timing was
+ * last enabled. */
+int ptycho_plan_timing(ptycho_plan_t plan, int32_t enable);
+int ptycho_plan_timing_read(ptycho_plan_t plan, int32_t cls, double *ms_total,
+                            int64_t *launches);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *ptycho_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTYCHO_H */

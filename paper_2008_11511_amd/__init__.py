@@ -1,0 +1,10 @@
+"""MI355X (gfx950) far-field ptychography hot path.
+
+The computation lives in the HIP library `libptycho.so` (C ABI in
+include/ptycho.h).  This package only marshals torch tensors (device memory
+and the current stream) into that ABI: `Plan` wraps a scan, `PoissonLLK` is
+the autograd Function over the hand-written adjoint, and `serve` runs the
+request loop for on-line reconstructions.
+"""
+from ._lib import PtychoError, UPDATE_OBJECT, UPDATE_PROBE, lib  # noqa: F401
+from .plan import Plan, offsets_from_positions, fft2  # noqa: F401

@@ -1,0 +1,258 @@
+// fft.hpp - device building blocks for batched complex64 power-of-two FFTs
+// on gfx950 (wave64).
+//
+// A length-N 1D transform is done by T = N/E threads that each hold E
+// elements in registers.  It runs as a sequence of self-sorting (Stockham)
+// passes of radix R_p (product = N): in each pass a thread performs E/R_p
+// radix-R_p butterflies on elements N/R_p apart, after a twiddle by
+// exp(sign 2 pi i r k / (R_p L)) (L = product of the earlier radices,
+// k = butterfly index mod L), and the results are exchanged through LDS
+// between passes.  The in-register radix-2/4/8/16 DFTs use compile-time
+// constant twiddles.  The inverse transform runs the radices in reverse
+// order, so that the element-to-register layout a forward transform leaves
+// behind is exactly the input layout of the inverse (the column kernel
+// chains forward -> modulus -> inverse without touching memory).
+//
+// The transforms here are unnormalised; callers fold the unitary 1/N of a
+// 2D transform into their own pointwise step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ptycho {
+
+// ---------------------------------------------------------------- complex --
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+
+// multiply by exp(DIR * i pi / 2): -i for the forward sign, +i for inverse
+template <int DIR>
+__device__ __forceinline__ float2 rot90(float2 a) {
+    if constexpr (DIR < 0) return make_float2(a.y, -a.x);
+    else return make_float2(-a.y, a.x);
+}
+
+// multiply by exp(DIR * 2 pi i * M / 16), M known at compile time
+template <int M, int DIR>
+__device__ __forceinline__ float2 tw16(float2 a) {
+    constexpr int m = M & 15;
+    // cos / sin of 2 pi m / 16
+    constexpr float C[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                             0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                             -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                             0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+    constexpr float S[16] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+                             1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                             0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                             -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f};
+    if constexpr (m == 0) {
+        return a;
+    } else if constexpr (m == 4) {
+        return rot90<DIR>(a);
+    } else if constexpr (m == 8) {
+        return make_float2(-a.x, -a.y);
+    } else if constexpr (m == 12) {
+        return rot90<-DIR>(a);
+    } else if constexpr (m == 2 || m == 6 || m == 10 || m == 14) {
+        // (+-1 +- i)/sqrt2: two adds and two multiplies
+        constexpr float c = C[m];
+        constexpr float s = (DIR < 0 ? -1.0f : 1.0f) * S[m];
+        return make_float2(c * a.x - s * a.y, c * a.y + s * a.x);
+    } else {
+        constexpr float c = C[m];
+        constexpr float s = (DIR < 0 ? -1.0f : 1.0f) * S[m];
+        return make_float2(c * a.x - s * a.y, c * a.y + s * a.x);
+    }
+}
+
+// In-register DFT of length R on u[0..R-1] (natural order in and out).
+template <int R, int DIR>
+struct Dft;
+
+template <int DIR>
+struct Dft<1, DIR> {
+    __device__ __forceinline__ static void run(float2 *) {}
+};
+
+template <int DIR>
+struct Dft<2, DIR> {
+    __device__ __forceinline__ static void run(float2 *u) {
+        float2 a = u[0];
+        u[0] = cadd(a, u[1]);
+        u[1] = csub(a, u[1]);
+    }
+};
+
+template <int DIR>
+struct Dft<4, DIR> {
+    __device__ __forceinline__ static void run(float2 *u) {
+        float2 t0 = cadd(u[0], u[2]);
+        float2 t1 = csub(u[0], u[2]);
+        float2 t2 = cadd(u[1], u[3]);
+        float2 t3 = rot90<DIR>(csub(u[1], u[3]));
+        u[0] = cadd(t0, t2);
+        u[2] = csub(t0, t2);
+        u[1] = cadd(t1, t3);
+        u[3] = csub(t1, t3);
+    }
+};
+
+// radix-2 split of an even-length DFT: even/odd halves, then combine
+template <int R, int DIR>
+struct Dft {
+    static_assert(R == 8 || R == 16, "radix");
+    __device__ __forceinline__ static void run(float2 *u) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = u[2 * i];
+            o[i] = u[2 * i + 1];
+        }
+        Dft<R / 2, DIR>::run(e);
+        Dft<R / 2, DIR>::run(o);
+        combine<0>(u, e, o);
+    }
+    template <int K>
+    __device__ __forceinline__ static void combine(float2 *u, const float2 *e, const float2 *o) {
+        if constexpr (K < R / 2) {
+            float2 t = tw16<K * (16 / R), DIR>(o[K]);
+            u[K] = cadd(e[K], t);
+            u[K + R / 2] = csub(e[K], t);
+            combine<K + 1>(u, e, o);
+        }
+    }
+};
+
+// ------------------------------------------------------- size configuration --
+// A transform plan: N points, E elements per thread (T = N/E threads per
+// transform) and the radices of the forward passes (the inverse runs them in
+// reverse).  Every radix divides E.
+template <int N, int E>
+struct FftCfg {
+    static constexpr int T = N / E;
+    static constexpr int R0 = (N == 16) ? 16 : (N == 32) ? 8 : (N == 64) ? 8 : (N == 128) ? (E == 16 ? 16 : 8)
+                            : (N == 256) ? (E == 16 ? 16 : 8) : 8;
+    static constexpr int R1 = (N == 16) ? 1 : (N == 32) ? 4 : (N == 64) ? 8 : (N == 128) ? (E == 16 ? 8 : 4)
+                            : (N == 256) ? (E == 16 ? 16 : 8) : 8;
+    static constexpr int R2 = (N == 128) ? (E == 16 ? 1 : 4) : (N == 256) ? (E == 16 ? 1 : 4) : (N == 512) ? 8 : 1;
+    static constexpr int P = (R1 == 1) ? 1 : (R2 == 1 ? 2 : 3);
+    static_assert(R0 * R1 * R2 == N, "radices must multiply to N");
+    static_assert(E % R0 == 0 && E % R1 == 0 && E % R2 == 0, "every radix must divide E");
+};
+
+template <int N, int E, int DIR, int P>
+struct Radix {
+    using C = FftCfg<N, E>;
+    static constexpr int fwd(int p) { return p == 0 ? C::R0 : (p == 1 ? C::R1 : C::R2); }
+    static constexpr int value = DIR < 0 ? fwd(P) : fwd(C::P - 1 - P);
+};
+
+template <int N, int E, int DIR> struct FirstRadix { static constexpr int value = Radix<N, E, DIR, 0>::value; };
+template <int N, int E, int DIR> struct LastRadix { static constexpr int value = Radix<N, E, DIR, FftCfg<N, E>::P - 1>::value; };
+
+// Index (along the transform) of register e of thread t: with R the radix of
+// the pass that reads (first) or writes (last) the registers,
+// u[b*R + r] <-> x[t + b*T + r*N/R].
+template <int N, int E, int R>
+__device__ __forceinline__ constexpr int elem_index(int t, int e) {
+    constexpr int T = N / E;
+    return t + (e / R) * T + (e % R) * (N / R);
+}
+template <int N, int E, int DIR>
+__device__ __forceinline__ int in_index(int t, int e) { return elem_index<N, E, FirstRadix<N, E, DIR>::value>(t, e); }
+template <int N, int E, int DIR>
+__device__ __forceinline__ int out_index(int t, int e) { return elem_index<N, E, LastRadix<N, E, DIR>::value>(t, e); }
+
+// Twiddle table exp(-2 pi i m / 1024), m = 0..1023, filled once per device.
+constexpr int TW_MAX = 1024;
+extern __device__ float2 g_twiddle[TW_MAX];
+
+template <int DIR>
+__device__ __forceinline__ float2 twiddle(int m_of_1024) {
+    float2 w = g_twiddle[m_of_1024];
+    if constexpr (DIR > 0) w.y = -w.y;
+    return w;
+}
+
+// All passes of one length-N transform held by thread t (0 <= t < N/E).
+// `Lds` provides ld(idx), st(idx, v) and sync() for this transform's
+// private N-element exchange buffer.
+template <int N, int E, int DIR, int P, int L, class Lds>
+__device__ __forceinline__ void fft_pass(float2 *u, int t, Lds &lds) {
+    using C = FftCfg<N, E>;
+    constexpr int T = N / E, R = Radix<N, E, DIR, P>::value;
+    if constexpr (P > 0) {
+#pragma unroll
+        for (int b = 0; b < E / R; ++b) {
+            const int i = t + b * T;
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[b * R + r] = lds.ld(i + r * (N / R));
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        if constexpr (L > 1) {
+            const int i = t + b * T;
+            const int k = i & (L - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                // exp(DIR 2 pi i r k / (R L)) = table[(r k * (1024 / (R L)))]
+                u[b * R + r] = cmul(u[b * R + r], twiddle<DIR>(r * k * (TW_MAX / (R * L))));
+            }
+        }
+        Dft<R, DIR>::run(u + b * R);
+    }
+    if constexpr (P + 1 < C::P) {
+        lds.sync();
+#pragma unroll
+        for (int b = 0; b < E / R; ++b) {
+            const int i = t + b * T;
+            const int k = i & (L - 1);
+            const int j = (i - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds.st(j + r * L, u[b * R + r]);
+        }
+        lds.sync();
+        fft_pass<N, E, DIR, P + 1, L * R>(u, t, lds);
+    }
+}
+
+template <int N, int E, int DIR, class Lds>
+__device__ __forceinline__ void fft1d(float2 *u, int t, Lds &lds) {
+    fft_pass<N, E, DIR, 0, 1>(u, t, lds);
+}
+
+// LDS exchange buffer for a transform along a contiguous row: element x of
+// row `row` lives at row*(N + N/16) + x + x/16 (one pad slot per 16).
+template <int N>
+struct RowLds {
+    float2 *base;
+    __device__ __forceinline__ RowLds(float2 *lds, int row) : base(lds + row * (N + N / 16)) {}
+    __device__ __forceinline__ float2 ld(int x) const { return base[x + (x >> 4)]; }
+    __device__ __forceinline__ void st(int x, float2 v) { base[x + (x >> 4)] = v; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
+    static constexpr int floats2_per_row = N + N / 16;
+};
+
+// LDS exchange buffer for a transform along a column: element y of local
+// column `col` lives at y*(CB + 1) + col.
+template <int N, int CB>
+struct ColLds {
+    float2 *base;
+    __device__ __forceinline__ ColLds(float2 *lds, int col) : base(lds + col) {}
+    __device__ __forceinline__ float2 ld(int y) const { return base[y * (CB + 1)]; }
+    __device__ __forceinline__ void st(int y, float2 v) { base[y * (CB + 1)] = v; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
+    static constexpr int floats2 = N * (CB + 1);
+};
+
+}  // namespace ptycho

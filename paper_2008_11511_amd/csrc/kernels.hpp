@@ -1,0 +1,651 @@
+// kernels.hpp - gfx950 kernels of the far-field ptychography hot path.
+//
+// One cycle over a stack of S frames runs as
+//   rows_fwd : object view x probe (or 2*Phi - Psi for DM), 1D FFT along x
+//              of every row of every mode -> stack scratch
+//   cols     : 1D FFT along y of every column of every mode, the Fourier-space
+//              step (modulus projection, ML gradient weighting, LLK, line
+//              search terms), and the inverse 1D FFT along y, in registers
+//   rows_inv : inverse 1D FFT along x and the real-space epilogue (AP: keep
+//              the projected exit wave; DM: Psi + P_F(2Phi - Psi) - Phi)
+//   gather_obj / gather_probe : overlap-update numerators and denominators,
+//              each output pixel summed by exactly one thread in a fixed
+//              frame order (no atomics, bitwise reproducible)
+// and, once per cycle, max-reductions and the normalisation with inertia.
+#pragma once
+
+#include "fft.hpp"
+
+namespace ptycho {
+
+// ------------------------------------------------------------- geometry ---
+// Row transforms: 16 elements per thread from N = 128 up (fewer LDS passes),
+// RB rows per 256-thread block.
+template <int N>
+struct RowGeom {
+    static constexpr int E = (N >= 128 || N == 16) ? 16 : 8, T = N / E, RB = 256 / T, THREADS = 256;
+    static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? RB * (N + N / 16) : 1;
+};
+// Column transforms keep all K modes in registers at once, so they use 8
+// elements per thread (16 at N = 16), CB adjacent columns per block (a
+// 128-byte row segment at CB = 16).
+template <int N>
+struct ColGeom {
+    static constexpr int E = (N == 16) ? 16 : 8, T = N / E;
+    static constexpr int CB = (N == 512) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
+    static constexpr int THREADS = CB * T;
+    static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * (CB + 1) : 1;
+};
+
+// Object tile of the atomic-free object gather.
+constexpr int OTILE_Y = 16, OTILE_X = 64;
+
+// ------------------------------------------------------------ arguments ---
+struct StackArgs {
+    int Ny, Nx, K, S, s0;
+    const int2 *offs;            // [J] (oy, ox)
+    const int *order;            // slot -> frame
+    const float2 *obj, *probe;
+    const float2 *dobj, *dprobe; // line-search direction
+    const float2 *psi;           // DM state read  [J][K][N][N]
+    float2 *psi_out;             // DM state write [J][K][N][N]
+    float2 *scr;                 // stack scratch [S][sets*K][N][N]
+    const float *iobs;           // [J][N][N]
+    const unsigned char *mask;   // [N][N] or null
+    float *icalc;                // [J][N][N] (icalc op)
+    double *red;                 // per-block partial sums of this launch
+    float eps;
+};
+
+struct GatherArgs {
+    int N, K, Ny, Nx, ntx, S, s0, ent0;
+    const int2 *offs;
+    const int *order;
+    const int *ent_tile, *ent_fptr, *ent_fr;
+    const float2 *obj, *probe;
+    const float2 *psi;           // scratch [S][K][N][N] or state [J][K][N][N]
+    float2 *numO;
+    float *denO;
+    float2 *numP;
+    float *denP;
+};
+
+// --------------------------------------------------------- reductions -----
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_down(v, o, 64));
+    return v;
+}
+// Fixed-order block sum; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[16];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) r += sh[i];
+    return r;
+}
+__device__ __forceinline__ float block_max(float v) {
+    __shared__ float shm[16];
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) shm[w] = v;
+    __syncthreads();
+    float r = 0.0f;
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) r = fmaxf(r, shm[i]);
+    return r;   // valid in every thread
+}
+
+// Poisson term I - Iobs + Iobs ln(Iobs/I) computed as I f(t), t = (Iobs-I)/I,
+// f(t) = (1+t) log1p(t) - t, with the series t^2/2 - t^3/6 + t^4/12 for
+// |t| < 1e-2 so that fp32 keeps its relative accuracy near a perfect fit.
+__device__ __forceinline__ float llk_term(float inten, float iob) {
+    if (iob <= 0.0f) return inten;
+    const float t = (iob - inten) / inten;
+    float f;
+    if (fabsf(t) < 1e-2f) f = t * t * (0.5f - t * (1.0f / 6.0f - t * (1.0f / 12.0f)));
+    else f = (1.0f + t) * log1pf(t) - t;
+    return inten * f;
+}
+
+// ============================================================ row passes ===
+enum RowIn { IN_PHI = 0, IN_DM = 1, IN_LS = 2, IN_DATA = 3 };
+
+// Forward row FFT of the stack's exit waves.  Block = RB consecutive rows of
+// the flattened (slot, y) row index; thread = (row, t).
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
+    using G = RowGeom<N>;
+    constexpr int E = G::E, T = G::T, RB = G::RB;
+    __shared__ float2 lds[G::LDS_F2];
+    const int tid = threadIdx.x, rr = tid / T, t = tid % T;
+    const int g = blockIdx.x * RB + rr;
+    const bool active = g < a.S * N;
+    const int gg = active ? g : a.S * N - 1;
+    const int s = gg / N, y = gg % N;
+    const int j = a.order[a.s0 + s];
+    const int2 o = a.offs[j];
+    const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
+    RowLds<N> L(lds, rr);
+
+    float2 ov[E], dv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int x = in_index<N, E, -1>(t, e);
+        ov[e] = a.obj[orow + x];
+        if constexpr (MODE == IN_LS) dv[e] = a.dobj[orow + x];
+    }
+    constexpr int SETS = (MODE == IN_LS) ? 3 : 1;
+    for (int k = 0; k < a.K; ++k) {
+        const float2 *prow = a.probe + ((size_t)k * N + y) * N;
+        const float2 *drow = (MODE == IN_LS) ? a.dprobe + ((size_t)k * N + y) * N : nullptr;
+#pragma unroll
+        for (int set = 0; set < SETS; ++set) {
+            float2 u[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int x = in_index<N, E, -1>(t, e);
+                const float2 p = prow[x];
+                if constexpr (MODE == IN_LS) {
+                    const float2 dp = drow[x];
+                    if (set == 0) u[e] = cmul(ov[e], p);
+                    else if (set == 1) u[e] = cadd(cmul(dv[e], p), cmul(ov[e], dp));
+                    else u[e] = cmul(dv[e], dp);
+                } else if constexpr (MODE == IN_DM) {
+                    const float2 phi = cmul(ov[e], p);
+                    const float2 ps = a.psi[(((size_t)j * a.K + k) * N + y) * N + x];
+                    u[e] = make_float2(2.0f * phi.x - ps.x, 2.0f * phi.y - ps.y);
+                } else {
+                    u[e] = cmul(ov[e], p);
+                }
+            }
+            fft1d<N, E, -1>(u, t, L);
+            float2 *dst = a.scr + (((size_t)s * SETS * a.K + set * a.K + k) * N + y) * N;
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) dst[out_index<N, E, -1>(t, e)] = u[e];
+            }
+        }
+    }
+}
+
+enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2 };
+
+// Inverse row FFT of the stack scratch and the real-space epilogue.
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
+    using G = RowGeom<N>;
+    constexpr int E = G::E, T = G::T, RB = G::RB;
+    __shared__ float2 lds[G::LDS_F2];
+    const int tid = threadIdx.x, rr = tid / T, t = tid % T;
+    const int g = blockIdx.x * RB + rr;
+    const bool active = g < a.S * N;
+    const int gg = active ? g : a.S * N - 1;
+    const int s = gg / N, y = gg % N;
+    const int j = a.order[a.s0 + s];
+    const int2 o = a.offs[j];
+    const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
+    RowLds<N> L(lds, rr);
+
+    float2 ov[E];
+    if constexpr (MODE == OUT_DM) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) ov[e] = a.obj[orow + out_index<N, E, +1>(t, e)];
+    }
+    for (int k = 0; k < a.K; ++k) {
+        float2 *src = a.scr + (((size_t)s * a.K + k) * N + y) * N;
+        float2 u[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) u[e] = src[in_index<N, E, +1>(t, e)];
+        fft1d<N, E, +1>(u, t, L);
+        if (!active) continue;
+        if constexpr (MODE == OUT_SCR) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) src[out_index<N, E, +1>(t, e)] = u[e];
+        } else if constexpr (MODE == OUT_STORE) {
+            float2 *dst = a.psi_out + (((size_t)j * a.K + k) * N + y) * N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dst[out_index<N, E, +1>(t, e)] = u[e];
+        } else {
+            const float2 *prow = a.probe + ((size_t)k * N + y) * N;
+            const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int x = out_index<N, E, +1>(t, e);
+                const float2 phi = cmul(ov[e], prow[x]);
+                const float2 ps = a.psi[prow_psi + x];
+                a.psi_out[prow_psi + x] = make_float2(ps.x + u[e].x - phi.x, ps.y + u[e].y - phi.y);
+            }
+        }
+    }
+}
+
+// ========================================================== column pass ===
+enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4 };
+
+// Column FFTs of all K modes held together in registers, the Fourier-space
+// step and (project / grad) the inverse column FFTs, written back in place.
+template <int N, int K, int OP>
+__global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a) {
+    using G = ColGeom<N>;
+    constexpr int E = G::E, CB = G::CB;
+    extern __shared__ float2 lds_dyn[];
+    const int tid = threadIdx.x, cl = tid % CB, t = tid / CB;
+    const int g = blockIdx.x * CB + cl;
+    const bool active = g < a.S * N;
+    const int gg = active ? g : a.S * N - 1;
+    const int s = gg / N, c = gg % N;
+    const int j = a.order[a.s0 + s];
+    ColLds<N, CB> L(lds_dyn, cl);
+    constexpr float inv_n2 = 1.0f / ((float)N * (float)N);
+
+    float2 u[K][E];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float2 *src = a.scr + ((size_t)(s * K + k) * N) * N + c;
+#pragma unroll
+        for (int e = 0; e < E; ++e) u[k][e] = src[(size_t)in_index<N, E, -1>(t, e) * N];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) fft1d<N, E, -1>(u[k], t, L);
+
+    const float *io = a.iobs + (size_t)j * N * N + c;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = out_index<N, E, -1>(t, e);
+        float inten = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) inten += cnorm(u[k][e]);
+        inten *= inv_n2;
+        const bool bad = a.mask != nullptr && a.mask[q * N + c] != 0;
+        const float iob = io[(size_t)q * N];
+        float sc;
+        if constexpr (OP == OP_PROJECT) {
+            sc = bad ? inv_n2 : sqrtf(iob / fmaxf(inten, a.eps)) * inv_n2;
+        } else {
+            const float ifl = fmaxf(inten, a.eps);
+            sc = bad ? 0.0f : (1.0f - iob / ifl) * inv_n2;
+            if (!bad && active) acc += (double)llk_term(ifl, iob);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) u[k][e] = cscale(u[k][e], sc);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) fft1d<N, E, +1>(u[k], t, L);
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            float2 *dst = a.scr + ((size_t)(s * K + k) * N) * N + c;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dst[(size_t)out_index<N, E, +1>(t, e) * N] = u[k][e];
+        }
+    }
+    if constexpr (OP == OP_GRAD) {
+        const double r = block_sum(acc);
+        if (threadIdx.x == 0) a.red[blockIdx.x] = r;
+    }
+}
+
+// Column FFTs one mode at a time for the read-only Fourier-space steps:
+// LLK, calculated intensity, and the line-search terms I0, I1, I2.
+template <int N, int OP>
+__global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
+    using G = ColGeom<N>;
+    constexpr int E = G::E, CB = G::CB;
+    extern __shared__ float2 lds_dyn[];
+    const int tid = threadIdx.x, cl = tid % CB, t = tid / CB;
+    const int g = blockIdx.x * CB + cl;
+    const bool active = g < a.S * N;
+    const int gg = active ? g : a.S * N - 1;
+    const int s = gg / N, c = gg % N;
+    const int j = a.order[a.s0 + s];
+    ColLds<N, CB> L(lds_dyn, cl);
+    constexpr float inv_n2 = 1.0f / ((float)N * (float)N);
+    constexpr int SETS = (OP == OP_LS) ? 3 : 1;
+
+    float i0[E], i1[E], i2[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) i0[e] = i1[e] = i2[e] = 0.0f;
+    for (int k = 0; k < a.K; ++k) {
+        float2 u[SETS][E];
+#pragma unroll
+        for (int set = 0; set < SETS; ++set) {
+            const float2 *src = a.scr + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + c;
+#pragma unroll
+            for (int e = 0; e < E; ++e) u[set][e] = src[(size_t)in_index<N, E, -1>(t, e) * N];
+            fft1d<N, E, -1>(u[set], t, L);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            i0[e] += cnorm(u[0][e]);
+            if constexpr (OP == OP_LS) {
+                const float2 ab = cmulc(u[0][e], u[1][e]);
+                const float2 ac = cmulc(u[0][e], u[2][e]);
+                i1[e] += 2.0f * ab.x;
+                i2[e] += cnorm(u[1][e]) + 2.0f * ac.x;
+            }
+        }
+    }
+    const float *io = a.iobs + (size_t)j * N * N + c;
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = out_index<N, E, -1>(t, e);
+        const float inten = i0[e] * inv_n2;
+        if constexpr (OP == OP_ICALC) {
+            if (active) a.icalc[((size_t)j * N + q) * N + c] = inten;
+        } else {
+            const bool bad = a.mask != nullptr && a.mask[q * N + c] != 0;
+            if (bad || !active) continue;
+            const float iob = io[(size_t)q * N];
+            const float ifl = fmaxf(inten, a.eps);
+            if constexpr (OP == OP_LLK) {
+                acc0 += (double)llk_term(ifl, iob);
+            } else {
+                const float d1 = 1.0f - iob / ifl;
+                const float d2 = (iob / ifl) / ifl;
+                const float j1 = i1[e] * inv_n2, j2 = i2[e] * inv_n2;
+                acc0 += (double)(d1 * j1);
+                acc1 += (double)(d2 * j1 * j1 + 2.0f * d1 * j2);
+            }
+        }
+    }
+    if constexpr (OP == OP_LLK) {
+        const double r = block_sum(acc0);
+        if (threadIdx.x == 0) a.red[blockIdx.x] = r;
+    } else if constexpr (OP == OP_LS) {
+        const double r0 = block_sum(acc0);
+        const double r1 = block_sum(acc1);
+        if (threadIdx.x == 0) {
+            a.red[2 * blockIdx.x] = r0;
+            a.red[2 * blockIdx.x + 1] = r1;
+        }
+    }
+}
+
+// ============================================================== gathers ===
+// Object numerator/denominator for one (stack, object tile): every object
+// pixel of the tile is summed by one thread over the stack's frames that
+// cover the tile, in ascending slot order; the result is added to the
+// running per-cycle sums (read-modify-write, one writer per pixel).
+template <int K, bool FROM_SCR>
+__global__ __launch_bounds__(256) void k_gather_obj(GatherArgs a) {
+    const int ent = a.ent0 + blockIdx.x;
+    const int tile = a.ent_tile[ent];
+    const int ty = tile / a.ntx, tx = tile % a.ntx;
+    const int col = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    const int px = tx * OTILE_X + col;
+    constexpr int PY = OTILE_Y / 4;
+    float2 acc[PY];
+    float den[PY];
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        acc[i] = make_float2(0.0f, 0.0f);
+        den[i] = 0.0f;
+    }
+    const int N = a.N;
+    const size_t fsz = (size_t)N * N;
+    for (int f = a.ent_fptr[ent]; f < a.ent_fptr[ent + 1]; ++f) {
+        const int s = a.ent_fr[f];
+        const int j = a.order[a.s0 + s];
+        const int2 o = a.offs[j];
+        const int x = px - o.y;
+        if (x < 0 || x >= N) continue;
+        const float2 *ps = a.psi + (size_t)(FROM_SCR ? s : j) * K * fsz;
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            const int y = ty * OTILE_Y + r0 + 4 * i - o.x;
+            if (y < 0 || y >= N) continue;
+            const size_t pix = (size_t)y * N + x;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float2 p = a.probe[k * fsz + pix];
+                const float2 v = ps[k * fsz + pix];
+                const float2 cv = cmulc(p, v);
+                acc[i].x += cv.x;
+                acc[i].y += cv.y;
+                den[i] += cnorm(p);
+            }
+        }
+    }
+    if (px >= a.Nx) return;
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        const int py = ty * OTILE_Y + r0 + 4 * i;
+        if (py >= a.Ny) continue;
+        const size_t op = (size_t)py * a.Nx + px;
+        const float2 n0 = a.numO[op];
+        a.numO[op] = make_float2(n0.x + acc[i].x, n0.y + acc[i].y);
+        a.denO[op] += den[i];
+    }
+}
+
+// Probe numerator/denominator: one thread per (probe pixel, mode), summing
+// over the stack's frames in slot order; the denominator is formed by the
+// mode-0 threads.
+template <bool FROM_SCR>
+__global__ __launch_bounds__(256) void k_gather_probe(GatherArgs a) {
+    const int N = a.N;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    if (idx >= N * N) return;
+    const int y = idx / N, x = idx % N;
+    const size_t fsz = (size_t)N * N;
+    float2 acc = make_float2(0.0f, 0.0f);
+    float den = 0.0f;
+    for (int s = 0; s < a.S; ++s) {
+        const int j = a.order[a.s0 + s];
+        const int2 o = a.offs[j];
+        const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
+        const float2 v = a.psi[((size_t)(FROM_SCR ? s : j) * a.K + k) * fsz + idx];
+        const float2 cv = cmulc(ov, v);
+        acc.x += cv.x;
+        acc.y += cv.y;
+        den += cnorm(ov);
+    }
+    const size_t pp = (size_t)k * fsz + idx;
+    const float2 n0 = a.numP[pp];
+    a.numP[pp] = make_float2(n0.x + acc.x, n0.y + acc.y);
+    if (k == 0) a.denP[idx] += den;
+}
+
+// Probe numerator/denominator over ALL frames from stored exit waves
+// [J][K][N][N], taken after the object update (so with the new object).
+// One thread per (probe pixel, mode); the frames are split into gridDim.z
+// chunks of consecutive frame indices whose partial sums are added in chunk
+// order by k_probe_reduce.
+struct ProbeAllArgs {
+    int N, K, J, Nx;
+    const int2 *offs;
+    const float2 *obj;
+    const float2 *psi;
+    float2 *part_num;   // [C][K][N*N]
+    float *part_den;    // [C][N*N]
+};
+
+__global__ __launch_bounds__(256) void k_gather_probe_all(ProbeAllArgs a) {
+    const int N = a.N;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y, c = blockIdx.z, C = gridDim.z;
+    if (idx >= N * N) return;
+    const int y = idx / N, x = idx % N;
+    const size_t fsz = (size_t)N * N;
+    const int j0 = (int)((long)c * a.J / C), j1 = (int)((long)(c + 1) * a.J / C);
+    float2 acc = make_float2(0.0f, 0.0f);
+    float den = 0.0f;
+    for (int j = j0; j < j1; ++j) {
+        const int2 o = a.offs[j];
+        const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
+        const float2 v = a.psi[((size_t)j * a.K + k) * fsz + idx];
+        const float2 cv = cmulc(ov, v);
+        acc.x += cv.x;
+        acc.y += cv.y;
+        den += cnorm(ov);
+    }
+    a.part_num[((size_t)c * a.K + k) * fsz + idx] = acc;
+    if (k == 0) a.part_den[(size_t)c * fsz + idx] = den;
+}
+
+__global__ __launch_bounds__(256) void k_probe_reduce(const float2 *part_num, const float *part_den, int C, int K,
+                                                      long n2, float2 *numP, float *denP) {
+    const long np = n2 * K;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+        float2 s = make_float2(0.0f, 0.0f);
+        for (int c = 0; c < C; ++c) {
+            const float2 v = part_num[(size_t)c * np + i];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        numP[i] = s;
+        if (i < n2) {
+            float d = 0.0f;
+            for (int c = 0; c < C; ++c) d += part_den[(size_t)c * n2 + i];
+            denP[i] = d;
+        }
+    }
+}
+
+// ====================================================== normalisation ===
+// Per-block maxima of the object and probe denominators.
+__global__ __launch_bounds__(256) void k_max_partial(const float *denO, long nO, const float *denP,
+                                                     long nP, float *part) {
+    float mo = 0.0f, mp = 0.0f;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < nO; i += (long)gridDim.x * 256)
+        mo = fmaxf(mo, denO[i]);
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < nP; i += (long)gridDim.x * 256)
+        mp = fmaxf(mp, denP[i]);
+    mo = block_max(mo);
+    mp = block_max(mp);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = mo;
+        part[gridDim.x + blockIdx.x] = mp;
+    }
+}
+
+__device__ __forceinline__ void reduce_partials(const float *part, int npart, float &mo, float &mp) {
+    float a = 0.0f, b = 0.0f;
+    for (int i = threadIdx.x; i < npart; i += blockDim.x) {
+        a = fmaxf(a, part[i]);
+        b = fmaxf(b, part[npart + i]);
+    }
+    mo = block_max(a);
+    mp = block_max(b);
+}
+
+// O <- (numO + a O)/(denO + a), a = dO * max(denO); same for every probe mode.
+__global__ __launch_bounds__(256) void k_normalize(float2 *obj, const float2 *numO, const float *denO,
+                                                   long nO, float2 *probe, const float2 *numP,
+                                                   const float *denP, int n2, int K, const float *part,
+                                                   int npart, float dO, float dP, unsigned upd) {
+    float mo, mp;
+    reduce_partials(part, npart, mo, mp);
+    const float ao = dO * mo, ap = dP * mp;
+    if (upd & 1u) {
+        for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < nO; i += (long)gridDim.x * 256) {
+            const float d = denO[i] + ao;
+            if (d > 0.0f) {
+                const float2 n = numO[i], o = obj[i];
+                const float r = 1.0f / d;
+                obj[i] = make_float2((n.x + ao * o.x) * r, (n.y + ao * o.y) * r);
+            }
+        }
+    }
+    if (upd & 2u) {
+        const long np = (long)n2 * K;
+        for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+            const float d = denP[i % n2] + ap;
+            if (d > 0.0f) {
+                const float2 n = numP[i], p = probe[i];
+                const float r = 1.0f / d;
+                probe[i] = make_float2((n.x + ap * p.x) * r, (n.y + ap * p.y) * r);
+            }
+        }
+    }
+}
+
+// ======================================================== small kernels ===
+__global__ __launch_bounds__(256) void k_zero(float4 *p, long n16) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n16; i += (long)gridDim.x * 256)
+        p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// psi[j][k] = O_j * P_k for all frames (DM start).
+__global__ __launch_bounds__(256) void k_psi_init(const float2 *obj, const float2 *probe, const int2 *offs,
+                                                  float2 *psi, int N, int K, int Nx, long total) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const long n2 = (long)N * N;
+        const int pix = (int)(i % n2);
+        const long jk = i / n2;
+        const int k = (int)(jk % K);
+        const int j = (int)(jk / K);
+        const int y = pix / N, x = pix % N;
+        const int2 o = offs[j];
+        psi[i] = cmul(obj[(size_t)(o.x + y) * Nx + o.y + x], probe[(size_t)k * n2 + pix]);
+    }
+}
+
+// Sum of `n` partials (fixed order, one block) into out[0] (+= if accumulate).
+__global__ __launch_bounds__(256) void k_sum_partials(const double *red, long n, int stride, double *out,
+                                                      int accumulate) {
+    double v = 0.0;
+    for (long i = threadIdx.x; i < n; i += 256) v += red[i * stride];
+    v = block_sum(v);
+    if (threadIdx.x == 0) out[0] = accumulate ? out[0] + v : v;
+}
+
+// Plain batched FFT along rows / columns (standalone 2D transform).
+template <int N, int DIR>
+__global__ __launch_bounds__(256) void k_fft_rows(float2 *data, long rows) {
+    using G = RowGeom<N>;
+    constexpr int E = G::E, T = G::T, RB = G::RB;
+    __shared__ float2 lds[G::LDS_F2];
+    const int tid = threadIdx.x, rr = tid / T, t = tid % T;
+    const long g = (long)blockIdx.x * RB + rr;
+    const bool active = g < rows;
+    float2 *row = data + (size_t)(active ? g : rows - 1) * N;
+    RowLds<N> L(lds, rr);
+    float2 u[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = row[in_index<N, E, DIR>(t, e)];
+    fft1d<N, E, DIR>(u, t, L);
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) row[out_index<N, E, DIR>(t, e)] = u[e];
+    }
+}
+
+template <int N, int DIR>
+__global__ __launch_bounds__(ColGeom<N>::THREADS) void k_fft_cols(float2 *data, long count, float scale) {
+    using G = ColGeom<N>;
+    constexpr int E = G::E, CB = G::CB;
+    extern __shared__ float2 lds_dyn[];
+    const int tid = threadIdx.x, cl = tid % CB, t = tid / CB;
+    const long g = (long)blockIdx.x * CB + cl;
+    const bool active = g < count * N;
+    const long gg = active ? g : count * N - 1;
+    const long f = gg / N;
+    const int c = (int)(gg % N);
+    float2 *col = data + (size_t)f * N * N + c;
+    ColLds<N, CB> L(lds_dyn, cl);
+    float2 u[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = col[(size_t)in_index<N, E, DIR>(t, e) * N];
+    fft1d<N, E, DIR>(u, t, L);
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) col[(size_t)out_index<N, E, DIR>(t, e) * N] = cscale(u[e], scale);
+    }
+}
+
+}  // namespace ptycho

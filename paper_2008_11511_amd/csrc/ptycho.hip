@@ -1,0 +1,910 @@
+// ptycho.hip - host side of the C ABI declared in include/ptycho.h.
+//
+// A plan holds the index tables of one scan (integer offsets, the frame
+// order in which stacks are formed, and for every stack the list of object
+// tiles it touches with, per tile, the covering frames), carved from the
+// caller's workspace together with the stack scratch, the per-cycle overlap
+// sums and the reduction partials.  Every entry point validates on the host,
+// then enqueues kernels on the plan's stream and returns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ptycho.h"
+#include "kernels.hpp"
+#include "mlcg.hpp"
+
+namespace ptycho {
+__device__ float2 g_twiddle[TW_MAX];
+}
+
+using namespace ptycho;
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string g_err;
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess) return fail(PTYCHO_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+#define LAUNCHCHK()                                                                            \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess) return fail(PTYCHO_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *ptycho_last_error(void) { return g_err.c_str(); }
+
+// --------------------------------------------------------------- twiddles --
+static std::mutex g_tw_mu;
+static std::vector<int> g_tw_done;
+
+static int ensure_twiddles() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    if ((int)g_tw_done.size() <= dev) g_tw_done.resize(dev + 1, 0);
+    if (g_tw_done[dev]) return PTYCHO_OK;
+    std::vector<float2> h(TW_MAX);
+    for (int m = 0; m < TW_MAX; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)TW_MAX;
+        h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), h.data(), sizeof(float2) * TW_MAX));
+    HIPCHK(hipDeviceSynchronize());
+    g_tw_done[dev] = 1;
+    return PTYCHO_OK;
+}
+
+// ------------------------------------------------------------- sizes -------
+static bool supported_n(int n) {
+    return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512;
+}
+
+template <class F>
+static int with_n(int n, F &&f) {
+    switch (n) {
+        case 16: return f(std::integral_constant<int, 16>());
+        case 32: return f(std::integral_constant<int, 32>());
+        case 64: return f(std::integral_constant<int, 64>());
+        case 128: return f(std::integral_constant<int, 128>());
+        case 256: return f(std::integral_constant<int, 256>());
+        case 512: return f(std::integral_constant<int, 512>());
+        default: return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
+    }
+}
+template <class F>
+static int with_k(int k, F &&f) {
+    switch (k) {
+        case 1: return f(std::integral_constant<int, 1>());
+        case 2: return f(std::integral_constant<int, 2>());
+        case 3: return f(std::integral_constant<int, 3>());
+        case 4: return f(std::integral_constant<int, 4>());
+        default: return fail(PTYCHO_E_UNSUPPORTED, "unsupported number of probe modes");
+    }
+}
+
+static int col_cb(int n) {
+    return with_n(n, [](auto nn) { return ColGeom<decltype(nn)::value>::CB; });
+}
+static int row_rb(int n) {
+    return with_n(n, [](auto nn) { return RowGeom<decltype(nn)::value>::RB; });
+}
+
+static constexpr size_t ALIGN = 256;
+static size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+static constexpr int NPART = 512;       // blocks of the max-reduction
+static constexpr int NSCAL = 64;        // device scalars
+
+struct Layout {
+    int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
+    size_t nent_max, nfr_max, nred;
+    size_t off_offs, off_order, off_ent_tile, off_ent_fptr, off_ent_fr, off_scr, off_numO, off_denO,
+        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, total;
+};
+
+// Frame chunks of the all-frame probe gather: enough blocks to fill the
+// chip (about 4096), never more chunks than frames.
+static int probe_chunks(const ptycho_desc_t &d) {
+    const long blocks = (long)((d.n * d.n + 255) / 256) * d.n_modes;
+    long c = (4096 + blocks - 1) / blocks;
+    c = std::max(1L, std::min(c, 32L));
+    return (int)std::min<long>(c, d.n_frames);
+}
+
+static int auto_stack(const ptycho_desc_t &d) {
+    if (d.stack > 0) return std::min(d.stack, d.n_frames);
+    const double per = (double)d.n_modes * d.n * d.n * 8.0;
+    int s = (int)std::floor((96.0 * 1024 * 1024) / per);
+    s = std::max(1, std::min(s, d.n_frames));
+    return s;
+}
+
+static Layout layout_for(const ptycho_desc_t &d) {
+    Layout L{};
+    const int J = d.n_frames, N = d.n, K = d.n_modes;
+    L.S = auto_stack(d);
+    L.nstacks = (J + L.S - 1) / L.S;
+    L.S_ls = std::max(1, L.S / 3);
+    L.nstacks_ls = (J + L.S_ls - 1) / L.S_ls;
+    const int cb = col_cb(N);
+    L.maxb = (int)(((long)L.S * N + cb - 1) / cb);
+    L.maxb_ls = (int)(((long)L.S_ls * N + cb - 1) / cb);
+    const long ty = (N + OTILE_Y - 1) / OTILE_Y + 1, tx = (N + OTILE_X - 1) / OTILE_X + 1;
+    L.nfr_max = (size_t)J * ty * tx;
+    const long ntiles = (long)((d.obj_ny + OTILE_Y - 1) / OTILE_Y) * ((d.obj_nx + OTILE_X - 1) / OTILE_X);
+    L.nent_max = std::min((size_t)L.nstacks * ntiles, L.nfr_max);
+    L.nred = std::max((size_t)L.nstacks * L.maxb, (size_t)L.nstacks_ls * L.maxb_ls * 2);
+    L.pchunks = probe_chunks(d);
+    const size_t n2 = (size_t)N * N, no = (size_t)d.obj_ny * d.obj_nx;
+    size_t o = 0;
+    L.off_offs = o; o = up(o + sizeof(int2) * J);
+    L.off_order = o; o = up(o + sizeof(int) * J);
+    L.off_ent_tile = o; o = up(o + sizeof(int) * L.nent_max);
+    L.off_ent_fptr = o; o = up(o + sizeof(int) * (L.nent_max + 1));
+    L.off_ent_fr = o; o = up(o + sizeof(int) * L.nfr_max);
+    L.off_scr = o; o = up(o + sizeof(float2) * (size_t)std::max(L.S, 3 * L.S_ls) * K * n2);
+    L.off_numO = o; o = up(o + sizeof(float2) * no);
+    L.off_denO = o; o = up(o + sizeof(float) * no);
+    L.off_numP = o; o = up(o + sizeof(float2) * K * n2);
+    L.off_denP = o; o = up(o + sizeof(float) * n2);
+    L.off_pnum = o; o = up(o + sizeof(float2) * (size_t)L.pchunks * K * n2);
+    L.off_pden = o; o = up(o + sizeof(float) * (size_t)L.pchunks * n2);
+    L.off_part = o; o = up(o + sizeof(float) * 2 * NPART);
+    L.off_red = o; o = up(o + sizeof(double) * L.nred);
+    L.off_scal = o; o = up(o + sizeof(double) * NSCAL);
+    L.total = o;
+    return L;
+}
+
+// Per-kernel-class timing with HIP events on the plan's stream.
+enum { TC_ROWS_FWD = 0, TC_COLS = 1, TC_ROWS_INV = 2, TC_GATHER_OBJ = 3, TC_GATHER_PROBE = 4,
+       TC_PROBE_ALL = 5, TC_NORMALIZE = 6, TC_OTHER = 7, TC_N = 8 };
+
+struct TimingLog {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> cls;   // class of event pair i (events 2i, 2i+1)
+    size_t used = 0;        // pairs recorded
+};
+
+struct ptycho_plan_s {
+    ptycho_desc_t d;
+    TimingLog timing;
+    Layout L;
+    hipStream_t stream;
+    const float *iobs;
+    const uint8_t *mask;
+    char *ws;
+    int2 *offs;
+    int *order;
+    int *ent_tile, *ent_fptr, *ent_fr;
+    float2 *scr, *numO, *numP, *pnum;
+    float *denO, *denP, *pden, *part;
+    double *red, *scal;
+    int ntx, nty;
+    long n_obs;
+    std::vector<int> h_stack_ent;   // [nstacks+1] first entry of every stack
+    // host copies kept alive for the asynchronous uploads
+    std::vector<int2> h_offs;
+    std::vector<int> h_order, h_tile, h_fptr, h_fr;
+};
+
+// Records an event pair around the launches made while it is alive.
+struct Timed {
+    ptycho_plan_s *p;
+    int c;
+    size_t pair;
+    Timed(ptycho_plan_s *p_, int c_) : p(p_), c(c_), pair(0) {
+        TimingLog &t = p->timing;
+        if (!t.on) return;
+        pair = t.used++;
+        while (t.pool.size() < 2 * t.used) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { t.on = false; return; }
+            t.pool.push_back(e);
+        }
+        if (t.cls.size() < t.used) t.cls.resize(t.used);
+        t.cls[pair] = c;
+        (void)hipEventRecord(t.pool[2 * pair], p->stream);
+    }
+    ~Timed() {
+        TimingLog &t = p->timing;
+        if (t.on) (void)hipEventRecord(t.pool[2 * pair + 1], p->stream);
+    }
+};
+
+// ---------------------------------------------------------------- validate --
+static int check_desc(const ptycho_desc_t *d) {
+    if (!d) return fail(PTYCHO_E_INVALID, "null descriptor");
+    if (!supported_n(d->n)) return fail(PTYCHO_E_UNSUPPORTED, "frame size must be 16, 32, 64, 128, 256 or 512");
+    if (d->n_modes < 1 || d->n_modes > 4) return fail(PTYCHO_E_UNSUPPORTED, "probe modes must be 1..4");
+    if (d->n_frames < 1) return fail(PTYCHO_E_INVALID, "n_frames must be >= 1");
+    if (d->obj_ny < d->n || d->obj_nx < d->n) return fail(PTYCHO_E_INVALID, "object smaller than a frame");
+    if ((long)d->obj_ny * d->obj_nx > (1L << 31) - 1) return fail(PTYCHO_E_INVALID, "object too large");
+    if (d->stack < 0) return fail(PTYCHO_E_INVALID, "negative stack");
+    if (!(d->obj_inertia >= 0.0f) || !(d->probe_inertia >= 0.0f)) return fail(PTYCHO_E_INVALID, "negative inertia");
+    if (!(d->icalc_floor > 0.0f)) return fail(PTYCHO_E_INVALID, "icalc_floor must be > 0");
+    if (d->flags != 0) return fail(PTYCHO_E_INVALID, "flags must be 0");
+    return PTYCHO_OK;
+}
+
+// ------------------------------------------------------------- host entries --
+extern "C" int ptycho_offsets_from_positions(const double *pos, int32_t J, int32_t n, int32_t ny, int32_t nx,
+                                             int32_t *out) {
+    if (!pos || !out) return fail(PTYCHO_E_INVALID, "null pointer");
+    if (J < 0 || n < 1 || ny < n || nx < n) return fail(PTYCHO_E_INVALID, "bad sizes");
+    std::vector<int32_t> tmp((size_t)J * 2);
+    const double cy = ny / 2.0, cx = nx / 2.0;
+    for (int32_t j = 0; j < J; ++j) {
+        const double fy = std::floor(cy + pos[2 * j] + 0.5), fx = std::floor(cx + pos[2 * j + 1] + 0.5);
+        if (!std::isfinite(fy) || !std::isfinite(fx)) return fail(PTYCHO_E_BOUNDS, "non-finite position");
+        const double oy = fy - (double)(n / 2), ox = fx - (double)(n / 2);
+        if (oy < 0 || ox < 0 || oy > ny - n || ox > nx - n)
+            return fail(PTYCHO_E_BOUNDS, "scan position window outside the object (frame " + std::to_string(j) + ")");
+        tmp[2 * j] = (int32_t)oy;
+        tmp[2 * j + 1] = (int32_t)ox;
+    }
+    std::memcpy(out, tmp.data(), sizeof(int32_t) * tmp.size());
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_workspace_bytes(const ptycho_desc_t *d, size_t *bytes) {
+    int st = check_desc(d);
+    if (st) return st;
+    if (!bytes) return fail(PTYCHO_E_INVALID, "null output");
+    *bytes = layout_for(*d).total;
+    return PTYCHO_OK;
+}
+
+static uint32_t spread_bits(uint32_t v) {
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets, const float *iobs,
+                                  const uint8_t *mask, void *ws, size_t ws_bytes, void *stream,
+                                  ptycho_plan_t *out) {
+    int st = check_desc(d);
+    if (st) return st;
+    if (!offsets || !iobs || !out) return fail(PTYCHO_E_INVALID, "null pointer");
+    const Layout L = layout_for(*d);
+    if (!ws) return fail(PTYCHO_E_WORKSPACE, "null workspace");
+    if (((uintptr_t)ws) % ALIGN) return fail(PTYCHO_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < L.total) return fail(PTYCHO_E_WORKSPACE, "workspace too small");
+    const int J = d->n_frames, N = d->n;
+    for (int j = 0; j < J; ++j) {
+        const int oy = offsets[2 * j], ox = offsets[2 * j + 1];
+        if (oy < 0 || ox < 0 || oy > d->obj_ny - N || ox > d->obj_nx - N)
+            return fail(PTYCHO_E_BOUNDS, "frame window outside the object (frame " + std::to_string(j) + ")");
+    }
+    st = ensure_twiddles();
+    if (st) return st;
+
+    auto *p = new ptycho_plan_s();
+    p->d = *d;
+    p->L = L;
+    p->stream = (hipStream_t)stream;
+    p->iobs = iobs;
+    p->mask = mask;
+    p->ws = (char *)ws;
+    p->offs = (int2 *)(p->ws + L.off_offs);
+    p->order = (int *)(p->ws + L.off_order);
+    p->ent_tile = (int *)(p->ws + L.off_ent_tile);
+    p->ent_fptr = (int *)(p->ws + L.off_ent_fptr);
+    p->ent_fr = (int *)(p->ws + L.off_ent_fr);
+    p->scr = (float2 *)(p->ws + L.off_scr);
+    p->numO = (float2 *)(p->ws + L.off_numO);
+    p->denO = (float *)(p->ws + L.off_denO);
+    p->numP = (float2 *)(p->ws + L.off_numP);
+    p->denP = (float *)(p->ws + L.off_denP);
+    p->pnum = (float2 *)(p->ws + L.off_pnum);
+    p->pden = (float *)(p->ws + L.off_pden);
+    p->part = (float *)(p->ws + L.off_part);
+    p->red = (double *)(p->ws + L.off_red);
+    p->scal = (double *)(p->ws + L.off_scal);
+    p->ntx = (d->obj_nx + OTILE_X - 1) / OTILE_X;
+    p->nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
+
+    // frame order: Morton (Z) order of the window corners, so that every
+    // stack covers a compact patch of the object
+    p->h_offs.resize(J);
+    std::vector<std::pair<uint64_t, int>> key(J);
+    for (int j = 0; j < J; ++j) {
+        p->h_offs[j] = make_int2(offsets[2 * j], offsets[2 * j + 1]);
+        const uint32_t z = spread_bits((uint32_t)offsets[2 * j]) << 1 | spread_bits((uint32_t)offsets[2 * j + 1]);
+        key[j] = {((uint64_t)z << 32) | (uint32_t)j, j};
+    }
+    std::sort(key.begin(), key.end());
+    p->h_order.resize(J);
+    for (int j = 0; j < J; ++j) p->h_order[j] = key[j].second;
+
+    // per stack: touched object tiles (ascending) and, per tile, the slots
+    // of the covering frames (ascending)
+    const int ntiles = p->ntx * p->nty;
+    std::vector<std::vector<int>> per_tile(ntiles);
+    std::vector<int> touched;
+    p->h_stack_ent.assign(L.nstacks + 1, 0);
+    p->h_fptr.clear();
+    p->h_fptr.push_back(0);
+    for (int sidx = 0; sidx < L.nstacks; ++sidx) {
+        const int s0 = sidx * L.S, sn = std::min(L.S, J - s0);
+        touched.clear();
+        for (int s = 0; s < sn; ++s) {
+            const int2 o = p->h_offs[p->h_order[s0 + s]];
+            const int ty0 = o.x / OTILE_Y, ty1 = (o.x + N - 1) / OTILE_Y;
+            const int tx0 = o.y / OTILE_X, tx1 = (o.y + N - 1) / OTILE_X;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    auto &v = per_tile[ty * p->ntx + tx];
+                    if (v.empty()) touched.push_back(ty * p->ntx + tx);
+                    v.push_back(s);
+                }
+        }
+        std::sort(touched.begin(), touched.end());
+        for (int t : touched) {
+            p->h_tile.push_back(t);
+            auto &v = per_tile[t];
+            p->h_fr.insert(p->h_fr.end(), v.begin(), v.end());
+            p->h_fptr.push_back((int)p->h_fr.size());
+            v.clear();
+        }
+        p->h_stack_ent[sidx + 1] = (int)p->h_tile.size();
+    }
+    if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max) {
+        delete p;
+        return fail(PTYCHO_E_WORKSPACE, "internal: tile lists exceed their bound");
+    }
+    long good = (long)N * N;
+    if (mask) {
+        std::vector<uint8_t> hm((size_t)N * N);
+        hipError_t e = hipMemcpy(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            delete p;
+            return fail(PTYCHO_E_HIP, std::string("mask copy: ") + hipGetErrorString(e));
+        }
+        good = 0;
+        for (uint8_t v : hm) good += (v == 0);
+    }
+    p->n_obs = good * J;
+
+    auto up_copy = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->stream);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up_copy(p->offs, p->h_offs.data(), sizeof(int2) * J);
+    if (e == hipSuccess) e = up_copy(p->order, p->h_order.data(), sizeof(int) * J);
+    if (e == hipSuccess) e = up_copy(p->ent_tile, p->h_tile.data(), sizeof(int) * p->h_tile.size());
+    if (e == hipSuccess) e = up_copy(p->ent_fptr, p->h_fptr.data(), sizeof(int) * p->h_fptr.size());
+    if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int) * p->h_fr.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(PTYCHO_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+    }
+    *out = p;
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_set_stream(ptycho_plan_t p, void *stream) {
+    if (!p) return fail(PTYCHO_E_INVALID, "null plan");
+    p->stream = (hipStream_t)stream;
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_stack(ptycho_plan_t p, int32_t *s) {
+    if (!p || !s) return fail(PTYCHO_E_INVALID, "null pointer");
+    *s = p->L.S;
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_destroy(ptycho_plan_t p) {
+    if (p)
+        for (hipEvent_t e : p->timing.pool) (void)hipEventDestroy(e);
+    delete p;
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_timing(ptycho_plan_t p, int32_t enable) {
+    if (!p) return fail(PTYCHO_E_INVALID, "null plan");
+    p->timing.on = enable != 0;
+    if (enable) p->timing.used = 0;
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_timing_read(ptycho_plan_t p, int32_t cls, double *ms_total, int64_t *launches) {
+    if (!p || !ms_total || !launches) return fail(PTYCHO_E_INVALID, "null pointer");
+    if (cls < 0 || cls >= TC_N) return fail(PTYCHO_E_INVALID, "bad timing class");
+    TimingLog &t = p->timing;
+    double tot = 0.0;
+    int64_t n = 0;
+    if (t.used) HIPCHK(hipEventSynchronize(t.pool[2 * t.used - 1]));
+    for (size_t i = 0; i < t.used; ++i) {
+        if (t.cls[i] != cls) continue;
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, t.pool[2 * i], t.pool[2 * i + 1]));
+        tot += ms;
+        ++n;
+    }
+    *ms_total = tot;
+    *launches = n;
+    return PTYCHO_OK;
+}
+
+// ----------------------------------------------------------------- passes --
+static int grid_for(long n) { return (int)std::max(1L, std::min((n + 255) / 256, 4096L)); }
+
+static int zero_async(void *ptr, size_t bytes, hipStream_t s) {
+    // plain fill kernel (no memset nodes, so the work can be graph-captured)
+    if (bytes % 16) return fail(PTYCHO_E_INVALID, "internal: zero size");
+    const long n16 = (long)(bytes / 16);
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(n16)), dim3(256), 0, s, (float4 *)ptr, n16);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+static StackArgs stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, const float *probe) {
+    StackArgs a{};
+    a.Ny = p->d.obj_ny;
+    a.Nx = p->d.obj_nx;
+    a.K = p->d.n_modes;
+    a.S = sn;
+    a.s0 = s0;
+    a.offs = p->offs;
+    a.order = p->order;
+    a.obj = (const float2 *)obj;
+    a.probe = (const float2 *)probe;
+    a.scr = p->scr;
+    a.iobs = p->iobs;
+    a.mask = p->mask;
+    a.eps = p->d.icalc_floor;
+    return a;
+}
+
+static GatherArgs gather_args(ptycho_plan_s *p, int sidx, int s0, int sn, const float *obj, const float *probe,
+                              const float2 *psi) {
+    GatherArgs g{};
+    g.N = p->d.n;
+    g.K = p->d.n_modes;
+    g.Ny = p->d.obj_ny;
+    g.Nx = p->d.obj_nx;
+    g.ntx = p->ntx;
+    g.S = sn;
+    g.s0 = s0;
+    g.ent0 = p->h_stack_ent[sidx];
+    g.offs = p->offs;
+    g.order = p->order;
+    g.ent_tile = p->ent_tile;
+    g.ent_fptr = p->ent_fptr;
+    g.ent_fr = p->ent_fr;
+    g.obj = (const float2 *)obj;
+    g.probe = (const float2 *)probe;
+    g.psi = psi;
+    g.numO = p->numO;
+    g.denO = p->denO;
+    g.numP = p->numP;
+    g.denP = p->denP;
+    return g;
+}
+
+// Kernels whose dynamic LDS exceeds 64 KiB must opt in once per process.
+template <class KernelT>
+static hipError_t set_dyn_lds(KernelT kern, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int N>
+static int rows_blocks(int sn) {
+    return (int)(((long)sn * N + RowGeom<N>::RB - 1) / RowGeom<N>::RB);
+}
+template <int N>
+static int cols_blocks(int sn) {
+    return (int)(((long)sn * N + ColGeom<N>::CB - 1) / ColGeom<N>::CB);
+}
+
+template <int N, int K, int OP>
+static void launch_cols_joint(const StackArgs &a, hipStream_t s) {
+    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2;
+    static const hipError_t attr = set_dyn_lds(k_cols_joint<N, K, OP>, lds);
+    (void)attr;
+    hipLaunchKernelGGL((k_cols_joint<N, K, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
+}
+template <int N, int OP>
+static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
+    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2;
+    static const hipError_t attr = set_dyn_lds(k_cols_seq<N, OP>, lds);
+    (void)attr;
+    hipLaunchKernelGGL((k_cols_seq<N, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
+}
+
+template <int K>
+static void launch_gather_obj(const GatherArgs &g, int nent, bool from_scr, hipStream_t s) {
+    if (nent <= 0) return;
+    if (from_scr) hipLaunchKernelGGL((k_gather_obj<K, true>), dim3(nent), dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gather_obj<K, false>), dim3(nent), dim3(256), 0, s, g);
+}
+static void launch_gather_probe(const GatherArgs &g, bool from_scr, hipStream_t s) {
+    dim3 grid((g.N * g.N + 255) / 256, g.K);
+    if (from_scr) hipLaunchKernelGGL((k_gather_probe<true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gather_probe<false>), grid, dim3(256), 0, s, g);
+}
+
+// Which sums a projection pass accumulates.
+enum { ACC_OBJ = 1, ACC_PROBE = 2 };
+
+static int zero_sums(ptycho_plan_s *p, unsigned acc) {
+    const size_t no = (size_t)p->d.obj_ny * p->d.obj_nx, n2 = (size_t)p->d.n * p->d.n;
+    int st = PTYCHO_OK;
+    if (acc & ACC_OBJ) {
+        st = zero_async(p->numO, up(sizeof(float2) * no), p->stream);
+        if (!st) st = zero_async(p->denO, up(sizeof(float) * no), p->stream);
+    }
+    if (!st && (acc & ACC_PROBE)) {
+        st = zero_async(p->numP, up(sizeof(float2) * p->d.n_modes * n2), p->stream);
+        if (!st) st = zero_async(p->denP, up(sizeof(float) * n2), p->stream);
+    }
+    return st;
+}
+
+// One pass over all stacks: forward rows, column op, inverse rows and the
+// per-stack gathers.  kind: 0 = AP projection, 1 = DM, 2 = ML gradient.
+// Exit waves go to `psi` (all frames) when it is given, else stay in the
+// stack scratch.  acc selects the per-stack gathers (object; probe only for
+// the gradient, whose two sums are taken at the same point).
+template <int N, int K>
+static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind,
+                        unsigned acc) {
+    const int J = p->d.n_frames, S = p->L.S;
+    hipStream_t s = p->stream;
+    const bool store = (psi != nullptr);
+    for (int sidx = 0; sidx < p->L.nstacks; ++sidx) {
+        const int s0 = sidx * S, sn = std::min(S, J - s0);
+        StackArgs a = stack_args(p, s0, sn, obj, probe);
+        a.psi = (const float2 *)psi;
+        a.psi_out = (float2 *)psi;
+        a.red = p->red + (size_t)sidx * p->L.maxb;
+        const dim3 rg(rows_blocks<N>(sn));
+        {
+            Timed tm(p, TC_ROWS_FWD);
+            if (kind == 1) hipLaunchKernelGGL((k_rows_fwd<N, IN_DM>), rg, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), rg, dim3(256), 0, s, a);
+        }
+        {
+            Timed tm(p, TC_COLS);
+            if (kind == 2) launch_cols_joint<N, K, OP_GRAD>(a, s);
+            else launch_cols_joint<N, K, OP_PROJECT>(a, s);
+        }
+        {
+            Timed tm(p, TC_ROWS_INV);
+            if (kind == 1) hipLaunchKernelGGL((k_rows_inv<N, OUT_DM>), rg, dim3(256), 0, s, a);
+            else if (store) hipLaunchKernelGGL((k_rows_inv<N, OUT_STORE>), rg, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_rows_inv<N, OUT_SCR>), rg, dim3(256), 0, s, a);
+        }
+        const bool from_scr = !store;
+        GatherArgs g = gather_args(p, sidx, s0, sn, obj, probe, from_scr ? p->scr : (const float2 *)psi);
+        if (acc & ACC_OBJ) {
+            Timed tm(p, TC_GATHER_OBJ);
+            launch_gather_obj<K>(g, p->h_stack_ent[sidx + 1] - p->h_stack_ent[sidx], from_scr, s);
+        }
+        if (acc & ACC_PROBE) {
+            Timed tm(p, TC_GATHER_PROBE);
+            launch_gather_probe(g, from_scr, s);
+        }
+        LAUNCHCHK();
+    }
+    return PTYCHO_OK;
+}
+
+// Probe sums over all frames from stored exit waves, with the current
+// (already updated) object; deterministic chunked reduction.
+static int probe_pass(ptycho_plan_s *p, const float *obj, const float *psi) {
+    ProbeAllArgs a{};
+    a.N = p->d.n;
+    a.K = p->d.n_modes;
+    a.J = p->d.n_frames;
+    a.Nx = p->d.obj_nx;
+    a.offs = p->offs;
+    a.obj = (const float2 *)obj;
+    a.psi = (const float2 *)psi;
+    a.part_num = p->pnum;
+    a.part_den = p->pden;
+    const long n2 = (long)a.N * a.N;
+    dim3 grid((unsigned)((n2 + 255) / 256), a.K, p->L.pchunks);
+    Timed tm(p, TC_PROBE_ALL);
+    hipLaunchKernelGGL(k_gather_probe_all, grid, dim3(256), 0, p->stream, a);
+    hipLaunchKernelGGL(k_probe_reduce, dim3(grid_for(n2 * a.K)), dim3(256), 0, p->stream, p->pnum, p->pden,
+                       p->L.pchunks, a.K, n2, p->numP, p->denP);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+static int normalize(ptycho_plan_s *p, float *obj, float *probe, unsigned upd) {
+    const long no = (long)p->d.obj_ny * p->d.obj_nx, n2 = (long)p->d.n * p->d.n;
+    Timed tm(p, TC_NORMALIZE);
+    hipLaunchKernelGGL(k_max_partial, dim3(NPART), dim3(256), 0, p->stream, p->denO, (upd & 1u) ? no : 0L,
+                       p->denP, (upd & 2u) ? n2 : 0L, p->part);
+    const long work = std::max((upd & 1u) ? no : 0L, (upd & 2u) ? n2 * p->d.n_modes : 0L);
+    hipLaunchKernelGGL(k_normalize, dim3(grid_for(work)), dim3(256), 0, p->stream,
+                       (float2 *)obj, p->numO, p->denO, no, (float2 *)probe, p->numP, p->denP, (int)n2,
+                       p->d.n_modes, p->part, NPART, p->d.obj_inertia, p->d.probe_inertia, upd);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+static int check_plan_ptrs(ptycho_plan_t p, const void *a, const void *b) {
+    if (!p) return fail(PTYCHO_E_INVALID, "null plan");
+    if (!a || !b) return fail(PTYCHO_E_INVALID, "null object or probe");
+    return PTYCHO_OK;
+}
+
+// AP (kind 0) or DM (kind 1) cycles: projection with the per-stack object
+// sums, object normalisation, then the probe sums over all frames with the
+// new object and the probe normalisation.
+static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int n_cycles, uint32_t upd, int kind) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (n_cycles < 0) return fail(PTYCHO_E_INVALID, "negative cycle count");
+    if (upd & ~3u) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    if (kind == 1 && !psi) return fail(PTYCHO_E_INVALID, "null psi");
+    if (kind == 0 && (upd & 2u) && !psi)
+        return fail(PTYCHO_E_INVALID, "an AP probe update needs exit-wave storage (psi)");
+    return with_n(p->d.n, [&](auto nn) {
+        constexpr int N = decltype(nn)::value;
+        return with_k(p->d.n_modes, [&](auto kk) {
+            constexpr int K = decltype(kk)::value;
+            for (int c = 0; c < n_cycles; ++c) {
+                int s2 = PTYCHO_OK;
+                if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
+                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, upd & 1u);
+                if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
+                if (!s2 && (upd & 2u)) s2 = probe_pass(p, obj, psi);
+                if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);
+                if (s2) return s2;
+            }
+            return (int)PTYCHO_OK;
+        });
+    });
+}
+
+extern "C" int ptycho_ap_cycle(ptycho_plan_t p, float *obj, float *probe, float *psi, int32_t n_cycles,
+                               uint32_t upd) {
+    return run_cycles(p, obj, probe, psi, n_cycles, upd, 0);
+}
+
+extern "C" int ptycho_dm_cycle(ptycho_plan_t p, float *obj, float *probe, float *psi, int32_t n_cycles,
+                               uint32_t upd) {
+    return run_cycles(p, obj, probe, psi, n_cycles, upd, 1);
+}
+
+extern "C" int ptycho_psi_init(ptycho_plan_t p, const float *obj, const float *probe, float *psi) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!psi) return fail(PTYCHO_E_INVALID, "null psi");
+    const long total = (long)p->d.n_frames * p->d.n_modes * p->d.n * p->d.n;
+    hipLaunchKernelGGL(k_psi_init, dim3(grid_for(total)), dim3(256), 0, p->stream, (const float2 *)obj,
+                       (const float2 *)probe, p->offs, (float2 *)psi, p->d.n, p->d.n_modes, p->d.obj_nx, total);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+// Read-only forward passes: LLK, icalc, line search.
+template <int N, int OP>
+static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, const float *dobj,
+                        const float *dprobe, float *icalc) {
+    const bool ls = (OP == OP_LS);
+    const int J = p->d.n_frames, S = ls ? p->L.S_ls : p->L.S;
+    const int nst = ls ? p->L.nstacks_ls : p->L.nstacks;
+    const int maxb = ls ? p->L.maxb_ls : p->L.maxb;
+    hipStream_t s = p->stream;
+    for (int sidx = 0; sidx < nst; ++sidx) {
+        const int s0 = sidx * S, sn = std::min(S, J - s0);
+        StackArgs a = stack_args(p, s0, sn, obj, probe);
+        a.dobj = (const float2 *)dobj;
+        a.dprobe = (const float2 *)dprobe;
+        a.icalc = icalc;
+        a.red = p->red + (size_t)sidx * maxb * (ls ? 2 : 1);
+        if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS>), dim3(rows_blocks<N>(sn)), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), dim3(rows_blocks<N>(sn)), dim3(256), 0, s, a);
+        launch_cols_seq<N, OP>(a, s);
+        LAUNCHCHK();
+    }
+    return PTYCHO_OK;
+}
+
+static int zero_red(ptycho_plan_s *p) { return zero_async(p->red, up(sizeof(double) * p->L.nred), p->stream); }
+
+// llk_dev[0] = sum of the reduction partials, llk_dev[1] = number of good pixels
+__global__ void k_store_count(double *dst, double v) { dst[0] = v; }
+
+int ptycho_llk_into(ptycho_plan_t p, const float *obj, const float *probe, double *llk) {
+    int st = zero_red(p);
+    if (st) return st;
+    st = with_n(p->d.n, [&](auto nn) { return forward_pass<decltype(nn)::value, OP_LLK>(p, obj, probe, nullptr, nullptr, nullptr); });
+    if (st) return st;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
+    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, p->stream, llk + 1, (double)p->n_obs);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_llk(ptycho_plan_t p, const float *obj, const float *probe, double *llk) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!llk) return fail(PTYCHO_E_INVALID, "null llk output");
+    return ptycho_llk_into(p, obj, probe, llk);
+}
+
+extern "C" int ptycho_icalc(ptycho_plan_t p, const float *obj, const float *probe, float *icalc) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!icalc) return fail(PTYCHO_E_INVALID, "null icalc output");
+    return with_n(p->d.n, [&](auto nn) {
+        return forward_pass<decltype(nn)::value, OP_ICALC>(p, obj, probe, nullptr, nullptr, icalc);
+    });
+}
+
+// Gradient pass: sums in numO/numP (and denominators), LLK partials in red.
+static int grad_pass(ptycho_plan_s *p, const float *obj, const float *probe) {
+    int st = zero_sums(p, ACC_OBJ | ACC_PROBE);
+    if (!st) st = zero_red(p);
+    if (st) return st;
+    return with_n(p->d.n, [&](auto nn) {
+        constexpr int N = decltype(nn)::value;
+        return with_k(p->d.n_modes, [&](auto kk) {
+            return project_pass<N, decltype(kk)::value>(p, obj, probe, nullptr, 2, ACC_OBJ | ACC_PROBE);
+        });
+    });
+}
+
+extern "C" int ptycho_ml_grad(ptycho_plan_t p, const float *obj, const float *probe, float *g_obj, float *g_probe,
+                              double *llk) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!g_obj || !g_probe) return fail(PTYCHO_E_INVALID, "null gradient output");
+    st = grad_pass(p, obj, probe);
+    if (st) return st;
+    const long no = (long)p->d.obj_ny * p->d.obj_nx, np = (long)p->d.n_modes * p->d.n * p->d.n;
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(no)), dim3(256), 0, p->stream, (float2 *)g_obj, p->numO, no, 2.0f);
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(np)), dim3(256), 0, p->stream, (float2 *)g_probe, p->numP, np, 2.0f);
+    if (llk) {
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
+        hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, p->stream, llk + 1, (double)p->n_obs);
+    }
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+static int ls_pass(ptycho_plan_s *p, const float *obj, const float *probe, const float *dobj, const float *dprobe,
+                   double *coef) {
+    int st = zero_red(p);
+    if (st) return st;
+    st = with_n(p->d.n, [&](auto nn) {
+        return forward_pass<decltype(nn)::value, OP_LS>(p, obj, probe, dobj, dprobe, nullptr);
+    });
+    if (st) return st;
+    const long n = (long)p->L.nred / 2;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, n, 2, coef, 0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red + 1, n, 2, coef + 1, 0);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_ml_linesearch(ptycho_plan_t p, const float *obj, const float *probe, const float *dobj,
+                                    const float *dprobe, double *coef) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!dobj || !dprobe || !coef) return fail(PTYCHO_E_INVALID, "null direction or output");
+    return ls_pass(p, obj, probe, dobj, dprobe, coef);
+}
+
+// ------------------------------------------------------------ CG ML cycle --
+static size_t ml_state_bytes(const ptycho_desc_t &d) {
+    const size_t no = (size_t)d.obj_ny * d.obj_nx, np = (size_t)d.n_modes * d.n * d.n;
+    return up(sizeof(double) * CG_NSCAL) + 2 * up(sizeof(float2) * no) + 2 * up(sizeof(float2) * np) +
+           up(sizeof(double) * 4 * CG_NPART);
+}
+
+extern "C" int ptycho_ml_state_bytes(ptycho_plan_t p, size_t *bytes) {
+    if (!p || !bytes) return fail(PTYCHO_E_INVALID, "null pointer");
+    *bytes = ml_state_bytes(p->d);
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *state, int32_t n_cycles,
+                               uint32_t upd, int32_t reset, double *hist) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!state) return fail(PTYCHO_E_INVALID, "null state");
+    if (((uintptr_t)state) % ALIGN) return fail(PTYCHO_E_WORKSPACE, "state not 256-byte aligned");
+    if (n_cycles < 0) return fail(PTYCHO_E_INVALID, "negative cycle count");
+    if (upd & ~3u) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    const size_t no = (size_t)p->d.obj_ny * p->d.obj_nx, np = (size_t)p->d.n_modes * p->d.n * p->d.n;
+    char *b = (char *)state;
+    double *scal = (double *)b;
+    b += up(sizeof(double) * CG_NSCAL);
+    float2 *d_o = (float2 *)b;
+    b += up(sizeof(float2) * no);
+    float2 *g_o = (float2 *)b;
+    b += up(sizeof(float2) * no);
+    float2 *d_p = (float2 *)b;
+    b += up(sizeof(float2) * np);
+    float2 *g_p = (float2 *)b;
+    b += up(sizeof(float2) * np);
+    double *cpart = (double *)b;
+    hipStream_t s = p->stream;
+    if (reset) {
+        hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, s, scal);
+        LAUNCHCHK();
+    }
+    const long n2 = (long)p->d.n * p->d.n;
+    for (int c = 0; c < n_cycles; ++c) {
+        // 1. gradient (sums in numO/numP), LLK, denominators
+        st = grad_pass(p, obj, probe);
+        if (st) return st;
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, p->red, (long)p->L.nred, 1, scal + CG_LLK, 0);
+        hipLaunchKernelGGL(k_max_partial, dim3(NPART), dim3(256), 0, s, p->denO, (long)no, p->denP, n2, p->part);
+        // 2. inner products for beta, then the new direction
+        hipLaunchKernelGGL(k_cg_dots, dim3(CG_NPART), dim3(256), 0, s, p->numO, g_o, (long)no, p->numP, g_p,
+                           (long)np, upd, cpart);
+        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, cpart, p->part, NPART, scal, hist ? hist + c : nullptr);
+        hipLaunchKernelGGL(k_cg_direction, dim3(grid_for((long)std::max(no, np))), dim3(256), 0, s, p->numO, g_o, d_o,
+                           (long)no, p->numP, g_p, d_p, (long)np, upd, scal);
+        // 3. line search along d, then the step
+        st = ls_pass(p, obj, probe, (const float *)d_o, (const float *)d_p, scal + CG_L1);
+        if (st) return st;
+        hipLaunchKernelGGL(k_cg_step, dim3(grid_for((long)std::max(no, np))), dim3(256), 0, s, (float2 *)obj, d_o,
+                           (long)no, (float2 *)probe, d_p, (long)np, upd, scal);
+        LAUNCHCHK();
+    }
+    return PTYCHO_OK;
+}
+
+// ------------------------------------------------------------ plain FFT ---
+extern "C" int ptycho_fft2(int32_t n, int32_t count, float *data, int32_t dir, void *stream) {
+    if (!supported_n(n)) return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
+    if (count < 0 || (dir != -1 && dir != 1)) return fail(PTYCHO_E_INVALID, "bad count or direction");
+    if (count == 0) return PTYCHO_OK;
+    if (!data) return fail(PTYCHO_E_INVALID, "null data");
+    int st = ensure_twiddles();
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    return with_n(n, [&](auto nn) {
+        constexpr int N = decltype(nn)::value;
+        const long rows = (long)count * N;
+        const int rb = (int)((rows + RowGeom<N>::RB - 1) / RowGeom<N>::RB);
+        const int cbk = (int)((rows + ColGeom<N>::CB - 1) / ColGeom<N>::CB);
+        const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2;
+        const float scale = 1.0f / (float)N;
+        if (dir < 0) {
+            static const hipError_t attr = set_dyn_lds(k_fft_cols<N, -1>, lds);
+            (void)attr;
+            hipLaunchKernelGGL((k_fft_rows<N, -1>), dim3(rb), dim3(256), 0, s, (float2 *)data, rows);
+            hipLaunchKernelGGL((k_fft_cols<N, -1>), dim3(cbk), dim3(ColGeom<N>::THREADS), lds, s, (float2 *)data,
+                               (long)count, scale);
+        } else {
+            static const hipError_t attr = set_dyn_lds(k_fft_cols<N, 1>, lds);
+            (void)attr;
+            hipLaunchKernelGGL((k_fft_rows<N, 1>), dim3(rb), dim3(256), 0, s, (float2 *)data, rows);
+            hipLaunchKernelGGL((k_fft_cols<N, 1>), dim3(cbk), dim3(ColGeom<N>::THREADS), lds, s, (float2 *)data,
+                               (long)count, scale);
+        }
+        LAUNCHCHK();
+        return (int)PTYCHO_OK;
+    });
+}

