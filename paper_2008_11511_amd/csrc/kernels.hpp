@@ -32,10 +32,20 @@ struct RowGeom {
 template <int N>
 struct ColGeom {
     static constexpr int E = (N == 16) ? 16 : 8, T = N / E;
-    static constexpr int CB = (N == 512) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
+    static constexpr int CB = (N >= 256) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
     static constexpr int THREADS = CB * T;
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * (CB + 1) : 1;
 };
+
+// Blocks are dispatched to the 8 XCDs round-robin (block i on XCD i % 8), each
+// XCD with its own L2.  This remap gives every XCD a contiguous range of
+// logical blocks, so neighbouring column blocks that share 128-byte lines
+// (and neighbouring rows of one frame) are served by the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int full = nb & ~7;
+    if (b >= full) return b;
+    return (b & 7) * (full >> 3) + (b >> 3);
+}
 
 // Object tile of the atomic-free object gather.
 constexpr int OTILE_Y = 16, OTILE_X = 64;
@@ -122,14 +132,16 @@ __device__ __forceinline__ float llk_term(float inten, float iob) {
 enum RowIn { IN_PHI = 0, IN_DM = 1, IN_LS = 2, IN_DATA = 3 };
 
 // Forward row FFT of the stack's exit waves.  Block = RB consecutive rows of
-// the flattened (slot, y) row index; thread = (row, t).
+// the flattened (slot, y) row index of one probe mode (blockIdx.y); thread =
+// (row, t).  The object view is re-read per mode from the caches.
 template <int N, int MODE>
 __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     using G = RowGeom<N>;
     constexpr int E = G::E, T = G::T, RB = G::RB;
     __shared__ float2 lds[G::LDS_F2];
     const int tid = threadIdx.x, rr = tid / T, t = tid % T;
-    const int g = blockIdx.x * RB + rr;
+    const int k = blockIdx.y;
+    const int g = xcd_block(blockIdx.x, gridDim.x) * RB + rr;
     const bool active = g < a.S * N;
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, y = gg % N;
@@ -137,95 +149,82 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     const int2 o = a.offs[j];
     const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
     RowLds<N> L(lds, rr);
-
-    float2 ov[E], dv[E];
+    constexpr int SETS = (MODE == IN_LS) ? 3 : 1;
+    const float2 *prow = a.probe + ((size_t)k * N + y) * N;
+    const float2 *drow = (MODE == IN_LS) ? a.dprobe + ((size_t)k * N + y) * N : nullptr;
+    float2 u[SETS][E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int x = in_index<N, E, -1>(t, e);
-        ov[e] = a.obj[orow + x];
-        if constexpr (MODE == IN_LS) dv[e] = a.dobj[orow + x];
+        const float2 ov = a.obj[orow + x];
+        const float2 p = prow[x];
+        if constexpr (MODE == IN_LS) {
+            const float2 dv = a.dobj[orow + x];
+            const float2 dp = drow[x];
+            u[0][e] = cmul(ov, p);
+            u[1][e] = cadd(cmul(dv, p), cmul(ov, dp));
+            u[2][e] = cmul(dv, dp);
+        } else if constexpr (MODE == IN_DM) {
+            const float2 phi = cmul(ov, p);
+            const float2 ps = a.psi[(((size_t)j * a.K + k) * N + y) * N + x];
+            u[0][e] = make_float2(2.0f * phi.x - ps.x, 2.0f * phi.y - ps.y);
+        } else {
+            u[0][e] = cmul(ov, p);
+        }
     }
-    constexpr int SETS = (MODE == IN_LS) ? 3 : 1;
-    for (int k = 0; k < a.K; ++k) {
-        const float2 *prow = a.probe + ((size_t)k * N + y) * N;
-        const float2 *drow = (MODE == IN_LS) ? a.dprobe + ((size_t)k * N + y) * N : nullptr;
 #pragma unroll
-        for (int set = 0; set < SETS; ++set) {
-            float2 u[E];
+    for (int set = 0; set < SETS; ++set) {
+        fft1d<N, E, -1>(u[set], t, L);
+        float2 *dst = a.scr + (((size_t)s * SETS * a.K + set * a.K + k) * N + y) * N;
+        if (active) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int x = in_index<N, E, -1>(t, e);
-                const float2 p = prow[x];
-                if constexpr (MODE == IN_LS) {
-                    const float2 dp = drow[x];
-                    if (set == 0) u[e] = cmul(ov[e], p);
-                    else if (set == 1) u[e] = cadd(cmul(dv[e], p), cmul(ov[e], dp));
-                    else u[e] = cmul(dv[e], dp);
-                } else if constexpr (MODE == IN_DM) {
-                    const float2 phi = cmul(ov[e], p);
-                    const float2 ps = a.psi[(((size_t)j * a.K + k) * N + y) * N + x];
-                    u[e] = make_float2(2.0f * phi.x - ps.x, 2.0f * phi.y - ps.y);
-                } else {
-                    u[e] = cmul(ov[e], p);
-                }
-            }
-            fft1d<N, E, -1>(u, t, L);
-            float2 *dst = a.scr + (((size_t)s * SETS * a.K + set * a.K + k) * N + y) * N;
-            if (active) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) dst[out_index<N, E, -1>(t, e)] = u[e];
-            }
+            for (int e = 0; e < E; ++e) dst[out_index<N, E, -1>(t, e)] = u[set][e];
         }
     }
 }
 
 enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2 };
 
-// Inverse row FFT of the stack scratch and the real-space epilogue.
+// Inverse row FFT of the stack scratch and the real-space epilogue, one probe
+// mode per blockIdx.y.
 template <int N, int MODE>
 __global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
     using G = RowGeom<N>;
     constexpr int E = G::E, T = G::T, RB = G::RB;
     __shared__ float2 lds[G::LDS_F2];
     const int tid = threadIdx.x, rr = tid / T, t = tid % T;
-    const int g = blockIdx.x * RB + rr;
+    const int k = blockIdx.y;
+    const int g = xcd_block(blockIdx.x, gridDim.x) * RB + rr;
     const bool active = g < a.S * N;
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, y = gg % N;
     const int j = a.order[a.s0 + s];
-    const int2 o = a.offs[j];
-    const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
     RowLds<N> L(lds, rr);
 
-    float2 ov[E];
-    if constexpr (MODE == OUT_DM) {
+    float2 *src = a.scr + (((size_t)s * a.K + k) * N + y) * N;
+    float2 u[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) ov[e] = a.obj[orow + out_index<N, E, +1>(t, e)];
-    }
-    for (int k = 0; k < a.K; ++k) {
-        float2 *src = a.scr + (((size_t)s * a.K + k) * N + y) * N;
-        float2 u[E];
+    for (int e = 0; e < E; ++e) u[e] = src[in_index<N, E, +1>(t, e)];
+    fft1d<N, E, +1>(u, t, L);
+    if (!active) return;
+    if constexpr (MODE == OUT_SCR) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) u[e] = src[in_index<N, E, +1>(t, e)];
-        fft1d<N, E, +1>(u, t, L);
-        if (!active) continue;
-        if constexpr (MODE == OUT_SCR) {
+        for (int e = 0; e < E; ++e) src[out_index<N, E, +1>(t, e)] = u[e];
+    } else if constexpr (MODE == OUT_STORE) {
+        float2 *dst = a.psi_out + (((size_t)j * a.K + k) * N + y) * N;
 #pragma unroll
-            for (int e = 0; e < E; ++e) src[out_index<N, E, +1>(t, e)] = u[e];
-        } else if constexpr (MODE == OUT_STORE) {
-            float2 *dst = a.psi_out + (((size_t)j * a.K + k) * N + y) * N;
+        for (int e = 0; e < E; ++e) dst[out_index<N, E, +1>(t, e)] = u[e];
+    } else {
+        const int2 o = a.offs[j];
+        const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
+        const float2 *prow = a.probe + ((size_t)k * N + y) * N;
+        const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
 #pragma unroll
-            for (int e = 0; e < E; ++e) dst[out_index<N, E, +1>(t, e)] = u[e];
-        } else {
-            const float2 *prow = a.probe + ((size_t)k * N + y) * N;
-            const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int x = out_index<N, E, +1>(t, e);
-                const float2 phi = cmul(ov[e], prow[x]);
-                const float2 ps = a.psi[prow_psi + x];
-                a.psi_out[prow_psi + x] = make_float2(ps.x + u[e].x - phi.x, ps.y + u[e].y - phi.y);
-            }
+        for (int e = 0; e < E; ++e) {
+            const int x = out_index<N, E, +1>(t, e);
+            const float2 phi = cmul(a.obj[orow + x], prow[x]);
+            const float2 ps = a.psi[prow_psi + x];
+            a.psi_out[prow_psi + x] = make_float2(ps.x + u[e].x - phi.x, ps.y + u[e].y - phi.y);
         }
     }
 }
@@ -241,7 +240,8 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     constexpr int E = G::E, CB = G::CB;
     extern __shared__ float2 lds_dyn[];
     const int tid = threadIdx.x, cl = tid % CB, t = tid / CB;
-    const int g = blockIdx.x * CB + cl;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int g = blk * CB + cl;
     const bool active = g < a.S * N;
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, c = gg % N;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     }
     if constexpr (OP == OP_GRAD) {
         const double r = block_sum(acc);
-        if (threadIdx.x == 0) a.red[blockIdx.x] = r;
+        if (threadIdx.x == 0) a.red[blk] = r;
     }
 }
 
@@ -305,7 +305,8 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     constexpr int E = G::E, CB = G::CB;
     extern __shared__ float2 lds_dyn[];
     const int tid = threadIdx.x, cl = tid % CB, t = tid / CB;
-    const int g = blockIdx.x * CB + cl;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int g = blk * CB + cl;
     const bool active = g < a.S * N;
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, c = gg % N;
@@ -363,13 +364,13 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     }
     if constexpr (OP == OP_LLK) {
         const double r = block_sum(acc0);
-        if (threadIdx.x == 0) a.red[blockIdx.x] = r;
+        if (threadIdx.x == 0) a.red[blk] = r;
     } else if constexpr (OP == OP_LS) {
         const double r0 = block_sum(acc0);
         const double r1 = block_sum(acc1);
         if (threadIdx.x == 0) {
-            a.red[2 * blockIdx.x] = r0;
-            a.red[2 * blockIdx.x + 1] = r1;
+            a.red[2 * blk] = r0;
+            a.red[2 * blk + 1] = r1;
         }
     }
 }
@@ -428,6 +429,73 @@ __global__ __launch_bounds__(256) void k_gather_obj(GatherArgs a) {
         const float2 n0 = a.numO[op];
         a.numO[op] = make_float2(n0.x + acc[i].x, n0.y + acc[i].y);
         a.denO[op] += den[i];
+    }
+}
+
+// Object numerator/denominator over ALL frames from stored exit waves
+// [J][K][N][N]: one block per object tile (every tile of the object, so the
+// sums are written, never accumulated), frames in ascending index order.
+struct ObjAllArgs {
+    int N, K, Ny, Nx, ntx;
+    const int2 *offs;
+    const int *tptr, *tfr;        // tile -> covering frames (CSR)
+    const float2 *probe;
+    const float2 *psi;
+    float2 *numO;
+    float *denO;
+};
+
+template <int K>
+__global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
+    const int tile = blockIdx.x;
+    const int ty = tile / a.ntx, tx = tile % a.ntx;
+    const int col = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    const int px = tx * OTILE_X + col;
+    constexpr int PY = OTILE_Y / 4;
+    float2 acc[PY];
+    float den[PY];
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        acc[i] = make_float2(0.0f, 0.0f);
+        den[i] = 0.0f;
+    }
+    const int N = a.N;
+    const size_t fsz = (size_t)N * N;
+    const int f1 = a.tptr[tile + 1];
+    for (int f = a.tptr[tile]; f < f1; ++f) {
+        const int j = a.tfr[f];
+        const int2 o = a.offs[j];
+        const int x = px - o.y;
+        if (x < 0 || x >= N) continue;
+        const float2 *ps = a.psi + (size_t)j * K * fsz;
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            const int y = ty * OTILE_Y + r0 + 4 * i - o.x;
+            if (y < 0 || y >= N) continue;
+            const size_t pix = (size_t)y * N + x;
+            float2 v[K], p[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                p[k] = a.probe[k * fsz + pix];
+                v[k] = ps[k * fsz + pix];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float2 cv = cmulc(p[k], v[k]);
+                acc[i].x += cv.x;
+                acc[i].y += cv.y;
+                den[i] += cnorm(p[k]);
+            }
+        }
+    }
+    if (px >= a.Nx) return;
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        const int py = ty * OTILE_Y + r0 + 4 * i;
+        if (py >= a.Ny) continue;
+        const size_t op = (size_t)py * a.Nx + px;
+        a.numO[op] = acc[i];
+        a.denO[op] = den[i];
     }
 }
 

@@ -109,7 +109,7 @@ static constexpr int NSCAL = 64;        // device scalars
 struct Layout {
     int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
     size_t nent_max, nfr_max, nred;
-    size_t off_offs, off_order, off_ent_tile, off_ent_fptr, off_ent_fr, off_scr, off_numO, off_denO,
+    size_t off_offs, off_order, off_ent_tile, off_ent_fptr, off_ent_fr, off_all_tptr, off_all_fr, off_scr, off_numO, off_denO,
         off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, total;
 };
 
@@ -153,6 +153,8 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.off_ent_tile = o; o = up(o + sizeof(int) * L.nent_max);
     L.off_ent_fptr = o; o = up(o + sizeof(int) * (L.nent_max + 1));
     L.off_ent_fr = o; o = up(o + sizeof(int) * L.nfr_max);
+    L.off_all_tptr = o; o = up(o + sizeof(int) * (ntiles + 1));
+    L.off_all_fr = o; o = up(o + sizeof(int) * L.nfr_max);
     L.off_scr = o; o = up(o + sizeof(float2) * (size_t)std::max(L.S, 3 * L.S_ls) * K * n2);
     L.off_numO = o; o = up(o + sizeof(float2) * no);
     L.off_denO = o; o = up(o + sizeof(float) * no);
@@ -188,7 +190,7 @@ struct ptycho_plan_s {
     char *ws;
     int2 *offs;
     int *order;
-    int *ent_tile, *ent_fptr, *ent_fr;
+    int *ent_tile, *ent_fptr, *ent_fr, *all_tptr, *all_fr;
     float2 *scr, *numO, *numP, *pnum;
     float *denO, *denP, *pden, *part;
     double *red, *scal;
@@ -197,7 +199,7 @@ struct ptycho_plan_s {
     std::vector<int> h_stack_ent;   // [nstacks+1] first entry of every stack
     // host copies kept alive for the asynchronous uploads
     std::vector<int2> h_offs;
-    std::vector<int> h_order, h_tile, h_fptr, h_fr;
+    std::vector<int> h_order, h_tile, h_fptr, h_fr, h_all_tptr, h_all_fr;
 };
 
 // Records an event pair around the launches made while it is alive.
@@ -307,6 +309,8 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     p->ent_tile = (int *)(p->ws + L.off_ent_tile);
     p->ent_fptr = (int *)(p->ws + L.off_ent_fptr);
     p->ent_fr = (int *)(p->ws + L.off_ent_fr);
+    p->all_tptr = (int *)(p->ws + L.off_all_tptr);
+    p->all_fr = (int *)(p->ws + L.off_all_fr);
     p->scr = (float2 *)(p->ws + L.off_scr);
     p->numO = (float2 *)(p->ws + L.off_numO);
     p->denO = (float *)(p->ws + L.off_denO);
@@ -365,7 +369,26 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
         }
         p->h_stack_ent[sidx + 1] = (int)p->h_tile.size();
     }
-    if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max) {
+    // all frames: tile -> covering frames in ascending frame index
+    {
+        std::vector<int> cnt(ntiles + 1, 0);
+        for (int j = 0; j < J; ++j) {
+            const int2 o = p->h_offs[j];
+            for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
+                for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx) cnt[ty * p->ntx + tx + 1]++;
+        }
+        for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+        p->h_all_tptr = cnt;
+        p->h_all_fr.assign(cnt[ntiles], 0);
+        std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+        for (int j = 0; j < J; ++j) {
+            const int2 o = p->h_offs[j];
+            for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
+                for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx)
+                    p->h_all_fr[fill[ty * p->ntx + tx]++] = j;
+        }
+    }
+    if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max || p->h_all_fr.size() > L.nfr_max) {
         delete p;
         return fail(PTYCHO_E_WORKSPACE, "internal: tile lists exceed their bound");
     }
@@ -392,6 +415,8 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     if (e == hipSuccess) e = up_copy(p->ent_tile, p->h_tile.data(), sizeof(int) * p->h_tile.size());
     if (e == hipSuccess) e = up_copy(p->ent_fptr, p->h_fptr.data(), sizeof(int) * p->h_fptr.size());
     if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int) * p->h_fr.size());
+    if (e == hipSuccess) e = up_copy(p->all_tptr, p->h_all_tptr.data(), sizeof(int) * p->h_all_tptr.size());
+    if (e == hipSuccess) e = up_copy(p->all_fr, p->h_all_fr.data(), sizeof(int) * p->h_all_fr.size());
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         delete p;
@@ -579,7 +604,7 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         a.psi = (const float2 *)psi;
         a.psi_out = (float2 *)psi;
         a.red = p->red + (size_t)sidx * p->L.maxb;
-        const dim3 rg(rows_blocks<N>(sn));
+        const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
             if (kind == 1) hipLaunchKernelGGL((k_rows_fwd<N, IN_DM>), rg, dim3(256), 0, s, a);
@@ -608,6 +633,28 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         }
         LAUNCHCHK();
     }
+    return PTYCHO_OK;
+}
+
+// Object sums over all frames from stored exit waves (written, not added).
+template <int K>
+static int object_pass(ptycho_plan_s *p, const float *probe, const float *psi) {
+    ObjAllArgs a{};
+    a.N = p->d.n;
+    a.K = K;
+    a.Ny = p->d.obj_ny;
+    a.Nx = p->d.obj_nx;
+    a.ntx = p->ntx;
+    a.offs = p->offs;
+    a.tptr = p->all_tptr;
+    a.tfr = p->all_fr;
+    a.probe = (const float2 *)probe;
+    a.psi = (const float2 *)psi;
+    a.numO = p->numO;
+    a.denO = p->denO;
+    Timed tm(p, TC_GATHER_OBJ);
+    hipLaunchKernelGGL((k_gather_obj_all<K>), dim3(p->ntx * p->nty), dim3(256), 0, p->stream, a);
+    LAUNCHCHK();
     return PTYCHO_OK;
 }
 
@@ -668,10 +715,14 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
         constexpr int N = decltype(nn)::value;
         return with_k(p->d.n_modes, [&](auto kk) {
             constexpr int K = decltype(kk)::value;
+            // with stored exit waves the object sums are taken once over all
+            // frames; without (AP, object only) per stack from the scratch
+            const bool stored = (psi != nullptr);
             for (int c = 0; c < n_cycles; ++c) {
                 int s2 = PTYCHO_OK;
-                if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
-                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, upd & 1u);
+                if ((upd & 1u) && !stored) s2 = zero_sums(p, ACC_OBJ);
+                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, stored ? 0u : (upd & 1u));
+                if (!s2 && (upd & 1u) && stored) s2 = object_pass<K>(p, probe, psi);
                 if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
                 if (!s2 && (upd & 2u)) s2 = probe_pass(p, obj, psi);
                 if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);
@@ -719,8 +770,9 @@ static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         a.dprobe = (const float2 *)dprobe;
         a.icalc = icalc;
         a.red = p->red + (size_t)sidx * maxb * (ls ? 2 : 1);
-        if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS>), dim3(rows_blocks<N>(sn)), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), dim3(rows_blocks<N>(sn)), dim3(256), 0, s, a);
+        const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
+        if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS>), rg, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), rg, dim3(256), 0, s, a);
         launch_cols_seq<N, OP>(a, s);
         LAUNCHCHK();
     }
