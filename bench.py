@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300, help="frames of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ml", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests of the served mixed workload (0 = skip; 64 = the full trace)")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -226,6 +229,29 @@ def main():
         log(f"ML: {ml['ms_per_cycle']} ms/cycle, {ml['frames_cycles_per_s']} frames*cycles/s")
         del plan2, st
 
+    serve = None
+    if args.serve_requests > 0:
+        from paper_2008_11511_amd.serve import serve_trace
+        torch.cuda.empty_cache()
+        log(f"serving: {args.serve_requests} requests at {args.serve_rate} req/s, 30 DM + 20 ML each, "
+            f"continuous batching")
+        con, s_con = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=0)
+        log(f"continuous: {s_con}")
+        log("serving: same trace, sequential plain solves (one request resident at a time)")
+        seq, s_seq = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=0, sequential=True)
+        log(f"sequential: {s_seq}")
+        same = all(np.array_equal(a.result["obj"], b.result["obj"]) and
+                   np.array_equal(a.result["probe"], b.result["probe"]) for a, b in zip(con, seq))
+        serve = {"workload": f"{args.serve_requests} requests, Poisson arrivals at {args.serve_rate}/s, frames "
+                             f"128/256/512, 200-2000 positions, 1 or 3 modes, 30 DM + 20 ML cycles each",
+                 "continuous": s_con, "sequential": s_seq,
+                 "p50_speedup": round(s_seq["p50_latency_s"] / s_con["p50_latency_s"], 3),
+                 "p99_speedup": round(s_seq["p99_latency_s"] / s_con["p99_latency_s"], 3),
+                 "results_identical": bool(same),
+                 "mean_final_llk_per_pixel": round(float(np.mean([r.result["llk"] for r in con])), 4)}
+        del con, seq
+        torch.cuda.empty_cache()
+
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
         b = torch.empty_like(a)
@@ -267,6 +293,7 @@ def main():
         "cycle_roofline": whole,
         "kernels": kernels,
         "ml": ml,
+        "serve": serve,
         "cpu_baseline": cpu,
         "paper_context": {"value": 22727, "unit": "frames*cycles/s",
                           "note": "DM 44 ms/cycle, 1000 frames 256x256, 3 probe modes, object 1176x1188, "

@@ -8,3 +8,4 @@ request loop for on-line reconstructions.
 """
 from ._lib import PtychoError, UPDATE_OBJECT, UPDATE_PROBE, lib  # noqa: F401
 from .plan import Plan, offsets_from_positions, fft2  # noqa: F401
+from .autograd import PoissonLLK, poisson_llk  # noqa: F401

@@ -226,14 +226,15 @@ def perturb_probe(probe: np.ndarray, seed: int, amp: float = 0.1) -> np.ndarray:
 
 def serve_requests(n_requests: int = 64, rate: float = 2.0, seed: int = 0,
                    sizes: Sequence[int] = (128, 256, 512),
-                   frames: tuple = (200, 2000), modes: Sequence[int] = (1, 3)):
+                   frames: tuple = (200, 2000), modes: Sequence[int] = (1, 3),
+                   min_side: int = 1024):
     """Arrival trace for a served mixed workload.
 
     Poisson arrivals at `rate` req/s; frame side uniform over `sizes`; scan
     positions uniform in `frames`; probe modes uniform over `modes`.  Objects
     are sized to hold the spiral: side = max(1024, roundup64(2*ceil(r_max) +
     N + 16)), step 12 px, 1e8 photons per frame, 2% gap mask as in the DM
-    256x256 workload.
+    256x256 workload (`min_side` replaces 1024 for small test traces).
     """
     rng = make_rng(BASE_SEED * 100 + 4 + seed, "serve")
     t = 0.0
@@ -246,7 +247,7 @@ def serve_requests(n_requests: int = 64, rate: float = 2.0, seed: int = 0,
         step = 12.0
         rmax = step * math.sqrt(max(j - 1, 0))
         side = 2 * int(math.ceil(rmax)) + n + 16
-        side = max(1024, ((side + 63) // 64) * 64)
+        side = max(min_side, ((side + 63) // 64) * 64)
         wl = Workload(f"req{i}", n, k, j, (side, side), step, 1e8, 0.02,
                       "dm+ml", (30, 20), BASE_SEED * 100 + 4 + 1000 * seed + i)
         reqs.append((t, wl))

@@ -298,3 +298,39 @@ def test_ml_cycles_match_oracle(dev):
     np.testing.assert_allclose(h, cg.history, rtol=1e-4)
     assert rel_l2(host(o), ro) < 1e-3
     assert rel_l2(host(p), rp) < 1e-3
+
+
+# ------------------------------------------------------------ autograd ----
+def test_poisson_llk_autograd_matches_finite_differences_and_oracle(dev):
+    """torch.autograd over the hand-written adjoint: gradients against central
+    finite differences (h = 1e-3 of the RMS value) of the FP64 oracle LLK at
+    20 object and 20 probe pixels, and against the full oracle gradient."""
+    import paper_2008_11511_amd as P
+    wl = small("ml256", n=64, k=2, j=30, obj=(192, 192), step=4.0, mask_frac=0.03)
+    pb = make_problem(wl, start="ml")
+    say("autograd PoissonLLK")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    o.requires_grad_(True)
+    p.requires_grad_(True)
+    loss = P.poisson_llk(o, p, plan)
+    loss.backward()
+    go, gp = host(o.grad), host(p.grad)
+    ro, rp, rl = oracle.ml_grad(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask)
+    assert abs(float(loss.detach().cpu()) - rl) < 1e-4 * abs(rl)
+    assert rel_l2(go, ro) < 1e-4 and rel_l2(gp, rp) < 1e-4
+    # torch's own convention check: d|z|^2 = 2z
+    z = torch.tensor([1.0 + 2.0j], dtype=torch.complex64, requires_grad=True)
+    (z.abs() ** 2).sum().backward()
+    assert torch.allclose(z.grad, 2 * z.detach())
+    rng = np.random.default_rng(7)
+    f_o = lambda x: oracle.llk(x, pb.probe0, pb.offsets, pb.iobs, pb.mask)[0]
+    f_p = lambda x: oracle.llk(pb.obj0, x, pb.offsets, pb.iobs, pb.mask)[0]
+    for x0, g, f in ((pb.obj0, go, f_o), (pb.probe0, gp, f_p)):
+        h = 1e-3 * np.sqrt((abs(x0) ** 2).mean())
+        cand = np.flatnonzero(abs(g) > 1e-3 * abs(g).max())
+        for i in rng.choice(cand, 20, replace=False):
+            e = np.zeros(x0.shape, complex)
+            e.flat[i] = h
+            fd = complex((f(x0 + e) - f(x0 - e)) / (2 * h), (f(x0 + 1j * e) - f(x0 - 1j * e)) / (2 * h))
+            assert abs(g.flat[i] - fd) <= 1e-3 * abs(g).max(), (i, g.flat[i], fd)
