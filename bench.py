@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300, help="frames of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ml", action="store_true")
+    ap.add_argument("--large-cycles", default="2,5",
+                    help="AP,DM cycles timed on the 4000 x 512^2 x 4-mode scan (the full chain is 20,50; "
+                         "0,0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the served mixed workload (0 = skip; 64 = the full trace)")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
@@ -229,6 +232,50 @@ def main():
         log(f"ML: {ml['ms_per_cycle']} ms/cycle, {ml['frames_cycles_per_s']} frames*cycles/s")
         del plan2, st
 
+    large = None
+    n_ap, n_dm = (int(x) for x in args.large_cycles.split(","))
+    if n_ap + n_dm > 0:
+        torch.cuda.empty_cache()
+        wl3 = synth.workload("apdm512")
+        log(f"building {wl3.name}: {wl3.n_frames} frames {wl3.n}x{wl3.n}, {wl3.n_modes} modes, object "
+            f"{wl3.obj_shape[0]}x{wl3.obj_shape[1]}")
+        offs3, iobs3, mask3, o3, p3, _ = build_workload(wl3, torch, dev, "apdm")
+        plan3 = P.Plan(offs3, iobs3, mask3, wl3.n_modes, wl3.obj_shape)
+        psi3 = torch.empty((wl3.n_frames, wl3.n_modes, wl3.n, wl3.n), dtype=torch.complex64, device=dev)
+        plan3.ap_cycle(o3, p3, 1, 3, psi=psi3)                       # warm-up
+        torch.cuda.synchronize()
+        plan3.timing(True)
+        t0 = time.perf_counter()
+        plan3.ap_cycle(o3, p3, n_ap, 3, psi=psi3)
+        torch.cuda.synchronize()
+        t_ap = time.perf_counter() - t0
+        plan3.psi_init(o3, p3, psi3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan3.dm_cycle(o3, p3, psi3, n_dm, 3)
+        torch.cuda.synchronize()
+        t_dm = time.perf_counter() - t0
+        per3 = plan3.timing_read()
+        plan3.timing(False)
+        algo3 = algorithmic_bytes(wl3, 0, "dm")
+        k3 = {}
+        for name, (ms, n) in per3.items():
+            if n:
+                k3[name] = {"avg_us": round(1e3 * ms / n, 2), "launches": n}
+                if name in ("cols", "gather_obj", "probe_all"):
+                    # these classes run with the same bytes in AP and DM cycles
+                    bpl = algo3[name] * (n_ap + n_dm) / n
+                    k3[name]["alg_GBs"] = round(bpl / (ms / n * 1e-3) / 1e9, 1)
+        large = {"workload": "apdm512: 4000 frames 512x512, 4 modes, object 4096x4096, 1e9 photons/frame, 3% mask",
+                 "ap_cycles": n_ap, "dm_cycles": n_dm,
+                 "ap_ms_per_cycle": round(t_ap / max(n_ap, 1) * 1e3, 2) if n_ap else None,
+                 "dm_ms_per_cycle": round(t_dm / max(n_dm, 1) * 1e3, 2) if n_dm else None,
+                 "dm_frames_cycles_per_s": round(wl3.n_frames * n_dm / t_dm, 1) if n_dm else None,
+                 "stack": plan3.stack, "kernels": k3}
+        log(f"large: AP {large['ap_ms_per_cycle']} ms/cycle, DM {large['dm_ms_per_cycle']} ms/cycle")
+        del plan3, psi3, iobs3, o3, p3
+        torch.cuda.empty_cache()
+
     serve = None
     if args.serve_requests > 0:
         from paper_2008_11511_amd.serve import serve_trace
@@ -293,6 +340,7 @@ def main():
         "cycle_roofline": whole,
         "kernels": kernels,
         "ml": ml,
+        "large": large,
         "serve": serve,
         "cpu_baseline": cpu,
         "paper_context": {"value": 22727, "unit": "frames*cycles/s",
