@@ -149,6 +149,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--ml-steps", type=int, default=10)
+    ap.add_argument("--stack", type=int, default=0, help="frames per launch (0 = the library's choice)")
     ap.add_argument("--cpu-sample", type=int, default=300, help="frames of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ml", action="store_true")
@@ -175,7 +176,7 @@ def main():
     wl = synth.workload("dm256")
     log(f"building {wl.name}: {wl.n_frames} frames {wl.n}x{wl.n}, {wl.n_modes} modes")
     offs, iobs, mask, o, p, truth = build_workload(wl, torch, dev, "apdm")
-    plan = P.Plan(offs, iobs, mask, wl.n_modes, wl.obj_shape)
+    plan = P.Plan(offs, iobs, mask, wl.n_modes, wl.obj_shape, stack=args.stack)
     psi = plan.psi_init(o, p)
     stack = plan.stack
     torch.cuda.synchronize()

@@ -172,15 +172,38 @@ __device__ __forceinline__ int in_index(int t, int e) { return elem_index<N, E, 
 template <int N, int E, int DIR>
 __device__ __forceinline__ int out_index(int t, int e) { return elem_index<N, E, LastRadix<N, E, DIR>::value>(t, e); }
 
-// Twiddle table exp(-2 pi i m / 1024), m = 0..1023, filled once per device.
+// Twiddle table exp(-2 pi i m / 1024), m = 0..1023, filled once per device
+// (read-only for kernels, so loads can be shared between probe modes).
 constexpr int TW_MAX = 1024;
-extern __device__ float2 g_twiddle[TW_MAX];
+extern __constant__ float2 g_twiddle[TW_MAX];
 
 template <int DIR>
 __device__ __forceinline__ float2 twiddle(int m_of_1024) {
     float2 w = g_twiddle[m_of_1024];
     if constexpr (DIR > 0) w.y = -w.y;
     return w;
+}
+
+// w[r] = w1^r for r = 1..R-1 from one table load, by a balanced product tree
+// (at most 4 multiplications deep).
+template <int R, int DIR>
+__device__ __forceinline__ void twiddle_powers(int m_of_1024, float2 *w) {
+    w[1] = twiddle<DIR>(m_of_1024);
+    if constexpr (R > 2) {
+        w[2] = cmul(w[1], w[1]);
+        w[3] = cmul(w[2], w[1]);
+    }
+    if constexpr (R > 4) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (R > 8) {
+        w[8] = cmul(w[4], w[4]);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    }
 }
 
 // All passes of one length-N transform held by thread t (0 <= t < N/E).
@@ -203,11 +226,11 @@ __device__ __forceinline__ void fft_pass(float2 *u, int t, Lds &lds) {
         if constexpr (L > 1) {
             const int i = t + b * T;
             const int k = i & (L - 1);
+            // exp(DIR 2 pi i r k / (R L)) = (table[k * 1024 / (R L)])^r
+            float2 w[R];
+            twiddle_powers<R, DIR>(k * (TW_MAX / (R * L)), w);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                // exp(DIR 2 pi i r k / (R L)) = table[(r k * (1024 / (R L)))]
-                u[b * R + r] = cmul(u[b * R + r], twiddle<DIR>(r * k * (TW_MAX / (R * L))));
-            }
+            for (int r = 1; r < R; ++r) u[b * R + r] = cmul(u[b * R + r], w[r]);
         }
         Dft<R, DIR>::run(u + b * R);
     }
@@ -231,6 +254,60 @@ __device__ __forceinline__ void fft1d(float2 *u, int t, Lds &lds) {
     fft_pass<N, E, DIR, 0, 1>(u, t, lds);
 }
 
+// K independent transforms (one per probe mode) held by the same thread, run
+// pass by pass together: one barrier pair and one set of twiddles per pass
+// serve all K.  lds[k] is the exchange buffer of transform k.
+template <int N, int E, int DIR, int P, int L, int K, class Lds>
+__device__ __forceinline__ void fftk_pass(float2 (&u)[K][E], int t, Lds *lds) {
+    using C = FftCfg<N, E>;
+    constexpr int T = N / E, R = Radix<N, E, DIR, P>::value;
+    if constexpr (P > 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int b = 0; b < E / R; ++b) {
+                const int i = t + b * T;
+#pragma unroll
+                for (int r = 0; r < R; ++r) u[k][b * R + r] = lds[k].ld(i + r * (N / R));
+            }
+    }
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        if constexpr (L > 1) {
+            const int i = t + b * T;
+            const int q = i & (L - 1);
+            float2 w[R];
+            twiddle_powers<R, DIR>(q * (TW_MAX / (R * L)), w);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int r = 1; r < R; ++r) u[k][b * R + r] = cmul(u[k][b * R + r], w[r]);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) Dft<R, DIR>::run(u[k] + b * R);
+    }
+    if constexpr (P + 1 < C::P) {
+        lds[0].sync();
+#pragma unroll
+        for (int b = 0; b < E / R; ++b) {
+            const int i = t + b * T;
+            const int q = i & (L - 1);
+            const int j = (i - q) * R + q;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[k].st(j + r * L, u[k][b * R + r]);
+        }
+        lds[0].sync();
+        fftk_pass<N, E, DIR, P + 1, L * R, K>(u, t, lds);
+    }
+}
+
+template <int N, int E, int DIR, int K, class Lds>
+__device__ __forceinline__ void fftk(float2 (&u)[K][E], int t, Lds *lds) {
+    fftk_pass<N, E, DIR, 0, 1, K>(u, t, lds);
+}
+
 // LDS exchange buffer for a transform along a contiguous row: element x of
 // row `row` lives at row*(N + N/16) + x + x/16 (one pad slot per 16).
 template <int N>
@@ -244,15 +321,24 @@ struct RowLds {
 };
 
 // LDS exchange buffer for a transform along a column: element y of local
-// column `col` lives at y*(CB + 1) + col.
+// column `col` lives at row v(y), column col, rows CB float2 wide.  v permutes
+// y within aligned groups of G = 32/CB rows (the rows one 64-bank cycle
+// holds) by an XOR of higher bits, so that lanes whose rows differ by 1, 4 or
+// 8 - the strides of the radix-8/4 passes - hit distinct bank groups.
 template <int N, int CB>
 struct ColLds {
+    static constexpr int G = (CB >= 32) ? 1 : 32 / CB;
     float2 *base;
+    ColLds() = default;
     __device__ __forceinline__ ColLds(float2 *lds, int col) : base(lds + col) {}
-    __device__ __forceinline__ float2 ld(int y) const { return base[y * (CB + 1)]; }
-    __device__ __forceinline__ void st(int y, float2 v) { base[y * (CB + 1)] = v; }
+    __device__ __forceinline__ static int row(int y) {
+        if constexpr (G == 1) return y;
+        else return (y & ~(G - 1)) | ((y ^ (y >> 2) ^ (y >> 3)) & (G - 1));
+    }
+    __device__ __forceinline__ float2 ld(int y) const { return base[row(y) * CB]; }
+    __device__ __forceinline__ void st(int y, float2 v) { base[row(y) * CB] = v; }
     __device__ __forceinline__ void sync() const { __syncthreads(); }
-    static constexpr int floats2 = N * (CB + 1);
+    static constexpr int floats2 = N * CB;
 };
 
 }  // namespace ptycho

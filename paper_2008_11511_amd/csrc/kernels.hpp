@@ -34,7 +34,7 @@ struct ColGeom {
     static constexpr int E = (N == 16) ? 16 : 8, T = N / E;
     static constexpr int CB = (N >= 256) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
     static constexpr int THREADS = CB * T;
-    static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * (CB + 1) : 1;
+    static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * CB : 1;   // one transform buffer
 };
 
 // Blocks are dispatched to the 8 XCDs round-robin (block i on XCD i % 8), each
@@ -205,6 +205,13 @@ __global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
     float2 u[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = src[in_index<N, E, +1>(t, e)];
+    // DM: the old exit waves come from HBM; load them before the barriers
+    float2 psv[MODE == OUT_DM ? E : 1];
+    const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
+    if constexpr (MODE == OUT_DM) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) psv[e] = a.psi[prow_psi + out_index<N, E, +1>(t, e)];
+    }
     fft1d<N, E, +1>(u, t, L);
     if (!active) return;
     if constexpr (MODE == OUT_SCR) {
@@ -218,12 +225,11 @@ __global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
         const int2 o = a.offs[j];
         const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
         const float2 *prow = a.probe + ((size_t)k * N + y) * N;
-        const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int x = out_index<N, E, +1>(t, e);
             const float2 phi = cmul(a.obj[orow + x], prow[x]);
-            const float2 ps = a.psi[prow_psi + x];
+            const float2 ps = psv[e];
             a.psi_out[prow_psi + x] = make_float2(ps.x + u[e].x - phi.x, ps.y + u[e].y - phi.y);
         }
     }
@@ -246,7 +252,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, c = gg % N;
     const int j = a.order[a.s0 + s];
-    ColLds<N, CB> L(lds_dyn, cl);
+    ColLds<N, CB> L[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) L[k] = ColLds<N, CB>(lds_dyn + k * G::LDS_F2, cl);
     constexpr float inv_n2 = 1.0f / ((float)N * (float)N);
 
     float2 u[K][E];
@@ -256,20 +264,28 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
 #pragma unroll
         for (int e = 0; e < E; ++e) u[k][e] = src[(size_t)in_index<N, E, -1>(t, e) * N];
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) fft1d<N, E, -1>(u[k], t, L);
-
+    // the data of the pixels this thread will own after the transform are
+    // loaded now: loads cannot move across the transform's barriers
     const float *io = a.iobs + (size_t)j * N * N + c;
-    double acc = 0.0;
+    float iobv[E];
+    bool badv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = out_index<N, E, -1>(t, e);
+        iobv[e] = io[(size_t)q * N];
+        badv[e] = a.mask != nullptr && a.mask[q * N + c] != 0;
+    }
+    fftk<N, E, -1, K>(u, t, L);
+
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
         float inten = 0.0f;
 #pragma unroll
         for (int k = 0; k < K; ++k) inten += cnorm(u[k][e]);
         inten *= inv_n2;
-        const bool bad = a.mask != nullptr && a.mask[q * N + c] != 0;
-        const float iob = io[(size_t)q * N];
+        const bool bad = badv[e];
+        const float iob = iobv[e];
         float sc;
         if constexpr (OP == OP_PROJECT) {
             sc = bad ? inv_n2 : sqrtf(iob / fmaxf(inten, a.eps)) * inv_n2;
@@ -281,8 +297,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
 #pragma unroll
         for (int k = 0; k < K; ++k) u[k][e] = cscale(u[k][e], sc);
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) fft1d<N, E, +1>(u[k], t, L);
+    fftk<N, E, +1, K>(u, t, L);
     if (active) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -437,8 +452,8 @@ __global__ __launch_bounds__(256) void k_gather_obj(GatherArgs a) {
 // sums are written, never accumulated), frames in ascending index order.
 struct ObjAllArgs {
     int N, K, Ny, Nx, ntx;
-    const int2 *offs;
-    const int *tptr, *tfr;        // tile -> covering frames (CSR)
+    const int *tptr;              // tile -> range of covering frames (CSR)
+    const int4 *tent;             // (frame, oy, ox, 0) per entry
     const float2 *probe;
     const float2 *psi;
     float2 *numO;
@@ -461,32 +476,39 @@ __global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
     }
     const int N = a.N;
     const size_t fsz = (size_t)N * N;
-    const int f1 = a.tptr[tile + 1];
-    for (int f = a.tptr[tile]; f < f1; ++f) {
-        const int j = a.tfr[f];
-        const int2 o = a.offs[j];
-        const int x = px - o.y;
-        if (x < 0 || x >= N) continue;
-        const float2 *ps = a.psi + (size_t)j * K * fsz;
+    const int f0 = a.tptr[tile], f1 = a.tptr[tile + 1];
+    int4 nxt = f0 < f1 ? a.tent[f0] : make_int4(0, 0, 0, 0);
+    for (int f = f0; f < f1; ++f) {
+        const int4 e = nxt;
+        if (f + 1 < f1) nxt = a.tent[f + 1];          // next entry in flight early
+        // branch-free body: out-of-window pixels read a clamped in-window
+        // address and are weighted 0, so all loads of a frame issue at once
+        const int x = px - e.z;
+        const bool xin = (unsigned)x < (unsigned)N;
+        const int xc = min(max(x, 0), N - 1);
+        const float2 *ps = a.psi + (size_t)e.x * K * fsz;
+        float2 v[PY][K], p[PY][K];
+        float m[PY];
 #pragma unroll
         for (int i = 0; i < PY; ++i) {
-            const int y = ty * OTILE_Y + r0 + 4 * i - o.x;
-            if (y < 0 || y >= N) continue;
-            const size_t pix = (size_t)y * N + x;
-            float2 v[K], p[K];
+            const int y = ty * OTILE_Y + r0 + 4 * i - e.y;
+            m[i] = (xin && (unsigned)y < (unsigned)N) ? 1.0f : 0.0f;
+            const size_t pix = (size_t)min(max(y, 0), N - 1) * N + xc;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                p[k] = a.probe[k * fsz + pix];
-                v[k] = ps[k * fsz + pix];
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float2 cv = cmulc(p[k], v[k]);
-                acc[i].x += cv.x;
-                acc[i].y += cv.y;
-                den[i] += cnorm(p[k]);
+                p[i][k] = a.probe[k * fsz + pix];
+                v[i][k] = ps[k * fsz + pix];
             }
         }
+#pragma unroll
+        for (int i = 0; i < PY; ++i)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float2 cv = cmulc(p[i][k], v[i][k]);
+                acc[i].x += m[i] * cv.x;
+                acc[i].y += m[i] * cv.y;
+                den[i] += m[i] * cnorm(p[i][k]);
+            }
     }
     if (px >= a.Nx) return;
 #pragma unroll
@@ -544,7 +566,7 @@ struct ProbeAllArgs {
 
 __global__ __launch_bounds__(256) void k_gather_probe_all(ProbeAllArgs a) {
     const int N = a.N;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     const int k = blockIdx.y, c = blockIdx.z, C = gridDim.z;
     if (idx >= N * N) return;
     const int y = idx / N, x = idx % N;

@@ -21,7 +21,7 @@
 #include "mlcg.hpp"
 
 namespace ptycho {
-__device__ float2 g_twiddle[TW_MAX];
+__constant__ float2 g_twiddle[TW_MAX];
 }
 
 using namespace ptycho;
@@ -154,7 +154,7 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.off_ent_fptr = o; o = up(o + sizeof(int) * (L.nent_max + 1));
     L.off_ent_fr = o; o = up(o + sizeof(int) * L.nfr_max);
     L.off_all_tptr = o; o = up(o + sizeof(int) * (ntiles + 1));
-    L.off_all_fr = o; o = up(o + sizeof(int) * L.nfr_max);
+    L.off_all_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
     L.off_scr = o; o = up(o + sizeof(float2) * (size_t)std::max(L.S, 3 * L.S_ls) * K * n2);
     L.off_numO = o; o = up(o + sizeof(float2) * no);
     L.off_denO = o; o = up(o + sizeof(float) * no);
@@ -190,7 +190,8 @@ struct ptycho_plan_s {
     char *ws;
     int2 *offs;
     int *order;
-    int *ent_tile, *ent_fptr, *ent_fr, *all_tptr, *all_fr;
+    int *ent_tile, *ent_fptr, *ent_fr, *all_tptr;
+    int4 *all_ent;
     float2 *scr, *numO, *numP, *pnum;
     float *denO, *denP, *pden, *part;
     double *red, *scal;
@@ -199,7 +200,8 @@ struct ptycho_plan_s {
     std::vector<int> h_stack_ent;   // [nstacks+1] first entry of every stack
     // host copies kept alive for the asynchronous uploads
     std::vector<int2> h_offs;
-    std::vector<int> h_order, h_tile, h_fptr, h_fr, h_all_tptr, h_all_fr;
+    std::vector<int> h_order, h_tile, h_fptr, h_fr, h_all_tptr;
+    std::vector<int4> h_all_ent;
 };
 
 // Records an event pair around the launches made while it is alive.
@@ -310,7 +312,7 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     p->ent_fptr = (int *)(p->ws + L.off_ent_fptr);
     p->ent_fr = (int *)(p->ws + L.off_ent_fr);
     p->all_tptr = (int *)(p->ws + L.off_all_tptr);
-    p->all_fr = (int *)(p->ws + L.off_all_fr);
+    p->all_ent = (int4 *)(p->ws + L.off_all_fr);
     p->scr = (float2 *)(p->ws + L.off_scr);
     p->numO = (float2 *)(p->ws + L.off_numO);
     p->denO = (float *)(p->ws + L.off_denO);
@@ -379,16 +381,16 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
         }
         for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
         p->h_all_tptr = cnt;
-        p->h_all_fr.assign(cnt[ntiles], 0);
+        p->h_all_ent.assign(cnt[ntiles], make_int4(0, 0, 0, 0));
         std::vector<int> fill(cnt.begin(), cnt.end() - 1);
         for (int j = 0; j < J; ++j) {
             const int2 o = p->h_offs[j];
             for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
                 for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx)
-                    p->h_all_fr[fill[ty * p->ntx + tx]++] = j;
+                    p->h_all_ent[fill[ty * p->ntx + tx]++] = make_int4(j, o.x, o.y, 0);
         }
     }
-    if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max || p->h_all_fr.size() > L.nfr_max) {
+    if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max || p->h_all_ent.size() > L.nfr_max) {
         delete p;
         return fail(PTYCHO_E_WORKSPACE, "internal: tile lists exceed their bound");
     }
@@ -416,7 +418,7 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     if (e == hipSuccess) e = up_copy(p->ent_fptr, p->h_fptr.data(), sizeof(int) * p->h_fptr.size());
     if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int) * p->h_fr.size());
     if (e == hipSuccess) e = up_copy(p->all_tptr, p->h_all_tptr.data(), sizeof(int) * p->h_all_tptr.size());
-    if (e == hipSuccess) e = up_copy(p->all_fr, p->h_all_fr.data(), sizeof(int) * p->h_all_fr.size());
+    if (e == hipSuccess) e = up_copy(p->all_ent, p->h_all_ent.data(), sizeof(int4) * p->h_all_ent.size());
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         delete p;
@@ -545,7 +547,7 @@ static int cols_blocks(int sn) {
 
 template <int N, int K, int OP>
 static void launch_cols_joint(const StackArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2;
+    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * K;
     static const hipError_t attr = set_dyn_lds(k_cols_joint<N, K, OP>, lds);
     (void)attr;
     hipLaunchKernelGGL((k_cols_joint<N, K, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
@@ -645,9 +647,8 @@ static int object_pass(ptycho_plan_s *p, const float *probe, const float *psi) {
     a.Ny = p->d.obj_ny;
     a.Nx = p->d.obj_nx;
     a.ntx = p->ntx;
-    a.offs = p->offs;
     a.tptr = p->all_tptr;
-    a.tfr = p->all_fr;
+    a.tent = p->all_ent;
     a.probe = (const float2 *)probe;
     a.psi = (const float2 *)psi;
     a.numO = p->numO;
