@@ -89,7 +89,7 @@ def algorithmic_bytes(wl, nstacks, kind):
     if kind == "dm":
         out["rows_fwd"] = J * ((2 * K + 1) * U)              # read Psi, view; write stack
         out["cols"] = J * (2 * K * U + W)                    # read+write stack, read Iobs
-        out["rows_inv"] = J * ((3 * K + 1) * U)              # read stack, Psi, view; write Psi
+        out["rows_inv"] = J * ((2 * K + 1) * U)              # read stack and view; write Psi
         out["gather_obj"] = J * K * U + 2 * obj_sums         # read Psi; object sums
         out["probe_all"] = J * (K * U + U)                   # read Psi and views
     return out

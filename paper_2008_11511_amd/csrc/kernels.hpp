@@ -205,13 +205,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
     float2 u[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = src[in_index<N, E, +1>(t, e)];
-    // DM: the old exit waves come from HBM; load them before the barriers
-    float2 psv[MODE == OUT_DM ? E : 1];
     const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
-    if constexpr (MODE == OUT_DM) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) psv[e] = a.psi[prow_psi + out_index<N, E, +1>(t, e)];
-    }
     fft1d<N, E, +1>(u, t, L);
     if (!active) return;
     if constexpr (MODE == OUT_SCR) {
@@ -229,14 +223,17 @@ __global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
         for (int e = 0; e < E; ++e) {
             const int x = out_index<N, E, +1>(t, e);
             const float2 phi = cmul(a.obj[orow + x], prow[x]);
-            const float2 ps = psv[e];
-            a.psi_out[prow_psi + x] = make_float2(ps.x + u[e].x - phi.x, ps.y + u[e].y - phi.y);
+            a.psi_out[prow_psi + x] = make_float2(phi.x + u[e].x, phi.y + u[e].y);
         }
     }
 }
 
 // ========================================================== column pass ===
-enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4 };
+// OP_CORR writes (s - 1) F(X) instead of s F(X): since P_F(X) = X + F^-1((s-1) F(X))
+// (s = 1 at bad pixels), the DM update Psi + P_F(2 Phi - Psi) - Phi equals
+// Phi + F^-1((s - 1) F(2 Phi - Psi)), which the inverse row pass forms from the
+// views alone, without reading the old exit waves again.
+enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4, OP_CORR = 5 };
 
 // Column FFTs of all K modes held together in registers, the Fourier-space
 // step and (project / grad) the inverse column FFTs, written back in place.
@@ -289,6 +286,8 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
         float sc;
         if constexpr (OP == OP_PROJECT) {
             sc = bad ? inv_n2 : sqrtf(iob / fmaxf(inten, a.eps)) * inv_n2;
+        } else if constexpr (OP == OP_CORR) {
+            sc = bad ? 0.0f : (sqrtf(iob / fmaxf(inten, a.eps)) - 1.0f) * inv_n2;
         } else {
             const float ifl = fmaxf(inten, a.eps);
             sc = bad ? 0.0f : (1.0f - iob / ifl) * inv_n2;
@@ -400,9 +399,10 @@ __global__ __launch_bounds__(256) void k_gather_obj(GatherArgs a) {
     const int ent = a.ent0 + blockIdx.x;
     const int tile = a.ent_tile[ent];
     const int ty = tile / a.ntx, tx = tile % a.ntx;
-    const int col = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    const int col = threadIdx.x % OTILE_X, r0 = threadIdx.x / OTILE_X;
+    constexpr int RSTEP = 256 / OTILE_X;            // row phases per block
     const int px = tx * OTILE_X + col;
-    constexpr int PY = OTILE_Y / 4;
+    constexpr int PY = OTILE_Y / RSTEP;
     float2 acc[PY];
     float den[PY];
 #pragma unroll
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(256) void k_gather_obj(GatherArgs a) {
         const float2 *ps = a.psi + (size_t)(FROM_SCR ? s : j) * K * fsz;
 #pragma unroll
         for (int i = 0; i < PY; ++i) {
-            const int y = ty * OTILE_Y + r0 + 4 * i - o.x;
+            const int y = ty * OTILE_Y + r0 + RSTEP * i - o.x;
             if (y < 0 || y >= N) continue;
             const size_t pix = (size_t)y * N + x;
 #pragma unroll
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void k_gather_obj(GatherArgs a) {
     if (px >= a.Nx) return;
 #pragma unroll
     for (int i = 0; i < PY; ++i) {
-        const int py = ty * OTILE_Y + r0 + 4 * i;
+        const int py = ty * OTILE_Y + r0 + RSTEP * i;
         if (py >= a.Ny) continue;
         const size_t op = (size_t)py * a.Nx + px;
         const float2 n0 = a.numO[op];
@@ -454,6 +454,7 @@ struct ObjAllArgs {
     int N, K, Ny, Nx, ntx;
     const int *tptr;              // tile -> range of covering frames (CSR)
     const int4 *tent;             // (frame, oy, ox, 0) per entry
+    const int *order;             // block -> tile, most frames first
     const float2 *probe;
     const float2 *psi;
     float2 *numO;
@@ -462,11 +463,12 @@ struct ObjAllArgs {
 
 template <int K>
 __global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
-    const int tile = blockIdx.x;
+    const int tile = a.order[blockIdx.x];
     const int ty = tile / a.ntx, tx = tile % a.ntx;
-    const int col = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    const int col = threadIdx.x % OTILE_X, r0 = threadIdx.x / OTILE_X;
+    constexpr int RSTEP = 256 / OTILE_X;            // row phases per block
     const int px = tx * OTILE_X + col;
-    constexpr int PY = OTILE_Y / 4;
+    constexpr int PY = OTILE_Y / RSTEP;
     float2 acc[PY];
     float den[PY];
 #pragma unroll
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
         float m[PY];
 #pragma unroll
         for (int i = 0; i < PY; ++i) {
-            const int y = ty * OTILE_Y + r0 + 4 * i - e.y;
+            const int y = ty * OTILE_Y + r0 + RSTEP * i - e.y;
             m[i] = (xin && (unsigned)y < (unsigned)N) ? 1.0f : 0.0f;
             const size_t pix = (size_t)min(max(y, 0), N - 1) * N + xc;
 #pragma unroll
@@ -513,7 +515,7 @@ __global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
     if (px >= a.Nx) return;
 #pragma unroll
     for (int i = 0; i < PY; ++i) {
-        const int py = ty * OTILE_Y + r0 + 4 * i;
+        const int py = ty * OTILE_Y + r0 + RSTEP * i;
         if (py >= a.Ny) continue;
         const size_t op = (size_t)py * a.Nx + px;
         a.numO[op] = acc[i];
@@ -558,6 +560,7 @@ __global__ __launch_bounds__(256) void k_gather_probe(GatherArgs a) {
 struct ProbeAllArgs {
     int N, K, J, Nx;
     const int2 *offs;
+    const int *order;   // frames in a spatially compact order (object rows reused in L2)
     const float2 *obj;
     const float2 *psi;
     float2 *part_num;   // [C][K][N*N]
@@ -574,7 +577,8 @@ __global__ __launch_bounds__(256) void k_gather_probe_all(ProbeAllArgs a) {
     const int j0 = (int)((long)c * a.J / C), j1 = (int)((long)(c + 1) * a.J / C);
     float2 acc = make_float2(0.0f, 0.0f);
     float den = 0.0f;
-    for (int j = j0; j < j1; ++j) {
+    for (int q = j0; q < j1; ++q) {
+        const int j = a.order[q];
         const int2 o = a.offs[j];
         const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
         const float2 v = a.psi[((size_t)j * a.K + k) * fsz + idx];

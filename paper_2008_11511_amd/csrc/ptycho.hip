@@ -109,7 +109,7 @@ static constexpr int NSCAL = 64;        // device scalars
 struct Layout {
     int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
     size_t nent_max, nfr_max, nred;
-    size_t off_offs, off_order, off_ent_tile, off_ent_fptr, off_ent_fr, off_all_tptr, off_all_fr, off_scr, off_numO, off_denO,
+    size_t off_offs, off_order, off_ent_tile, off_ent_fptr, off_ent_fr, off_all_tptr, off_all_fr, off_tile_order, off_scr, off_numO, off_denO,
         off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, total;
 };
 
@@ -122,10 +122,13 @@ static int probe_chunks(const ptycho_desc_t &d) {
     return (int)std::min<long>(c, d.n_frames);
 }
 
+// Frames per launch.  The stack kernels are bandwidth-bound and do not keep
+// data in cache from one launch to the next, so larger launches (fewer
+// launches, smaller tails) are faster; the scratch is sized to ~2 GiB.
 static int auto_stack(const ptycho_desc_t &d) {
     if (d.stack > 0) return std::min(d.stack, d.n_frames);
     const double per = (double)d.n_modes * d.n * d.n * 8.0;
-    int s = (int)std::floor((96.0 * 1024 * 1024) / per);
+    int s = (int)std::floor((2048.0 * 1024 * 1024) / per);
     s = std::max(1, std::min(s, d.n_frames));
     return s;
 }
@@ -155,6 +158,7 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.off_ent_fr = o; o = up(o + sizeof(int) * L.nfr_max);
     L.off_all_tptr = o; o = up(o + sizeof(int) * (ntiles + 1));
     L.off_all_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
+    L.off_tile_order = o; o = up(o + sizeof(int) * ntiles);
     L.off_scr = o; o = up(o + sizeof(float2) * (size_t)std::max(L.S, 3 * L.S_ls) * K * n2);
     L.off_numO = o; o = up(o + sizeof(float2) * no);
     L.off_denO = o; o = up(o + sizeof(float) * no);
@@ -192,6 +196,7 @@ struct ptycho_plan_s {
     int *order;
     int *ent_tile, *ent_fptr, *ent_fr, *all_tptr;
     int4 *all_ent;
+    int *tile_order;
     float2 *scr, *numO, *numP, *pnum;
     float *denO, *denP, *pden, *part;
     double *red, *scal;
@@ -202,6 +207,7 @@ struct ptycho_plan_s {
     std::vector<int2> h_offs;
     std::vector<int> h_order, h_tile, h_fptr, h_fr, h_all_tptr;
     std::vector<int4> h_all_ent;
+    std::vector<int> h_tile_order;
 };
 
 // Records an event pair around the launches made while it is alive.
@@ -313,6 +319,7 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     p->ent_fr = (int *)(p->ws + L.off_ent_fr);
     p->all_tptr = (int *)(p->ws + L.off_all_tptr);
     p->all_ent = (int4 *)(p->ws + L.off_all_fr);
+    p->tile_order = (int *)(p->ws + L.off_tile_order);
     p->scr = (float2 *)(p->ws + L.off_scr);
     p->numO = (float2 *)(p->ws + L.off_numO);
     p->denO = (float *)(p->ws + L.off_denO);
@@ -389,6 +396,13 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
                 for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx)
                     p->h_all_ent[fill[ty * p->ntx + tx]++] = make_int4(j, o.x, o.y, 0);
         }
+        // blocks of the all-frame object gather start with the tiles covered by
+        // the most frames, so the light border tiles fill in at the end
+        p->h_tile_order.resize(ntiles);
+        for (int t = 0; t < ntiles; ++t) p->h_tile_order[t] = t;
+        std::stable_sort(p->h_tile_order.begin(), p->h_tile_order.end(), [&](int a, int b) {
+            return cnt[a + 1] - cnt[a] > cnt[b + 1] - cnt[b];
+        });
     }
     if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max || p->h_all_ent.size() > L.nfr_max) {
         delete p;
@@ -419,6 +433,7 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int) * p->h_fr.size());
     if (e == hipSuccess) e = up_copy(p->all_tptr, p->h_all_tptr.data(), sizeof(int) * p->h_all_tptr.size());
     if (e == hipSuccess) e = up_copy(p->all_ent, p->h_all_ent.data(), sizeof(int4) * p->h_all_ent.size());
+    if (e == hipSuccess) e = up_copy(p->tile_order, p->h_tile_order.data(), sizeof(int) * p->h_tile_order.size());
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         delete p;
@@ -615,6 +630,7 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         {
             Timed tm(p, TC_COLS);
             if (kind == 2) launch_cols_joint<N, K, OP_GRAD>(a, s);
+            else if (kind == 1) launch_cols_joint<N, K, OP_CORR>(a, s);
             else launch_cols_joint<N, K, OP_PROJECT>(a, s);
         }
         {
@@ -649,6 +665,7 @@ static int object_pass(ptycho_plan_s *p, const float *probe, const float *psi) {
     a.ntx = p->ntx;
     a.tptr = p->all_tptr;
     a.tent = p->all_ent;
+    a.order = p->tile_order;
     a.probe = (const float2 *)probe;
     a.psi = (const float2 *)psi;
     a.numO = p->numO;
@@ -668,6 +685,7 @@ static int probe_pass(ptycho_plan_s *p, const float *obj, const float *psi) {
     a.J = p->d.n_frames;
     a.Nx = p->d.obj_nx;
     a.offs = p->offs;
+    a.order = p->order;
     a.obj = (const float2 *)obj;
     a.psi = (const float2 *)psi;
     a.part_num = p->pnum;
