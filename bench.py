@@ -221,15 +221,19 @@ def main():
         hist = torch.zeros(args.ml_steps, dtype=torch.float64, device=dev)
         plan2.ml_cycle(o2, p2, st, 2, 3, reset=True, hist=hist[:2].contiguous())
         torch.cuda.synchronize()
+        plan2.timing(True)
         t0 = time.perf_counter()
         plan2.ml_cycle(o2, p2, st, args.ml_steps, 3, reset=False, hist=hist)
         torch.cuda.synchronize()
         dt2 = time.perf_counter() - t0
+        per2 = plan2.timing_read()
+        plan2.timing(False)
         h = hist.cpu().numpy()
         ml = {"workload": "ml256", "frames": wl2.n_frames, "cycles": args.ml_steps,
               "ms_per_cycle": round(dt2 / args.ml_steps * 1e3, 3),
               "frames_cycles_per_s": round(wl2.n_frames * args.ml_steps / dt2, 1),
-              "llk_first": float(h[0]), "llk_last": float(h[-1])}
+              "llk_first": float(h[0]), "llk_last": float(h[-1]),
+              "kernels_ms_per_cycle": {k: round(ms / args.ml_steps, 4) for k, (ms, n) in per2.items() if n}}
         log(f"ML: {ml['ms_per_cycle']} ms/cycle, {ml['frames_cycles_per_s']} frames*cycles/s")
         del plan2, st
 

@@ -67,18 +67,6 @@ struct StackArgs {
     float eps;
 };
 
-struct GatherArgs {
-    int N, K, Ny, Nx, ntx, S, s0, ent0;
-    const int2 *offs;
-    const int *order;
-    const int *ent_tile, *ent_fptr, *ent_fr;
-    const float2 *obj, *probe;
-    const float2 *psi;           // scratch [S][K][N][N] or state [J][K][N][N]
-    float2 *numO;
-    float *denO;
-    float2 *numP;
-    float *denP;
-};
 
 // --------------------------------------------------------- reductions -----
 __device__ __forceinline__ double wave_sum(double v) {
@@ -332,6 +320,11 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     float i0[E], i1[E], i2[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) i0[e] = i1[e] = i2[e] = 0.0f;
+    // the SETS transforms of a mode run pass by pass together
+    ColLds<N, CB> Ls[SETS];
+#pragma unroll
+    for (int set = 0; set < SETS; ++set) Ls[set] = ColLds<N, CB>(lds_dyn + set * G::LDS_F2, cl);
+    (void)L;
     for (int k = 0; k < a.K; ++k) {
         float2 u[SETS][E];
 #pragma unroll
@@ -339,8 +332,8 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
             const float2 *src = a.scr + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + c;
 #pragma unroll
             for (int e = 0; e < E; ++e) u[set][e] = src[(size_t)in_index<N, E, -1>(t, e) * N];
-            fft1d<N, E, -1>(u[set], t, L);
         }
+        fftk<N, E, -1, SETS>(u, t, Ls);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             i0[e] += cnorm(u[0][e]);
@@ -390,80 +383,27 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
 }
 
 // ============================================================== gathers ===
-// Object numerator/denominator for one (stack, object tile): every object
-// pixel of the tile is summed by one thread over the stack's frames that
-// cover the tile, in ascending slot order; the result is added to the
-// running per-cycle sums (read-modify-write, one writer per pixel).
-template <int K, bool FROM_SCR>
-__global__ __launch_bounds__(256) void k_gather_obj(GatherArgs a) {
-    const int ent = a.ent0 + blockIdx.x;
-    const int tile = a.ent_tile[ent];
-    const int ty = tile / a.ntx, tx = tile % a.ntx;
-    const int col = threadIdx.x % OTILE_X, r0 = threadIdx.x / OTILE_X;
-    constexpr int RSTEP = 256 / OTILE_X;            // row phases per block
-    const int px = tx * OTILE_X + col;
-    constexpr int PY = OTILE_Y / RSTEP;
-    float2 acc[PY];
-    float den[PY];
-#pragma unroll
-    for (int i = 0; i < PY; ++i) {
-        acc[i] = make_float2(0.0f, 0.0f);
-        den[i] = 0.0f;
-    }
-    const int N = a.N;
-    const size_t fsz = (size_t)N * N;
-    for (int f = a.ent_fptr[ent]; f < a.ent_fptr[ent + 1]; ++f) {
-        const int s = a.ent_fr[f];
-        const int j = a.order[a.s0 + s];
-        const int2 o = a.offs[j];
-        const int x = px - o.y;
-        if (x < 0 || x >= N) continue;
-        const float2 *ps = a.psi + (size_t)(FROM_SCR ? s : j) * K * fsz;
-#pragma unroll
-        for (int i = 0; i < PY; ++i) {
-            const int y = ty * OTILE_Y + r0 + RSTEP * i - o.x;
-            if (y < 0 || y >= N) continue;
-            const size_t pix = (size_t)y * N + x;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float2 p = a.probe[k * fsz + pix];
-                const float2 v = ps[k * fsz + pix];
-                const float2 cv = cmulc(p, v);
-                acc[i].x += cv.x;
-                acc[i].y += cv.y;
-                den[i] += cnorm(p);
-            }
-        }
-    }
-    if (px >= a.Nx) return;
-#pragma unroll
-    for (int i = 0; i < PY; ++i) {
-        const int py = ty * OTILE_Y + r0 + RSTEP * i;
-        if (py >= a.Ny) continue;
-        const size_t op = (size_t)py * a.Nx + px;
-        const float2 n0 = a.numO[op];
-        a.numO[op] = make_float2(n0.x + acc[i].x, n0.y + acc[i].y);
-        a.denO[op] += den[i];
-    }
-}
-
-// Object numerator/denominator over ALL frames from stored exit waves
-// [J][K][N][N]: one block per object tile (every tile of the object, so the
-// sums are written, never accumulated), frames in ascending index order.
-struct ObjAllArgs {
+// Object numerator/denominator by object tile: block b sums, for every pixel
+// of tile tiles[b], the frames of entries [tptr[b], tptr[b+1]) in list order;
+// each entry is (exit-wave index, oy, ox, 0), the index being the slot in the
+// stack scratch or the frame in stored exit waves [J][K][N][N].  Blocks are
+// listed with the most covering frames first, so light border tiles fill in
+// at the end.  ACCUM adds to the running sums (one stack of many), otherwise
+// the sums are written (every tile of the object is listed).
+struct ObjTileArgs {
     int N, K, Ny, Nx, ntx;
-    const int *tptr;              // tile -> range of covering frames (CSR)
-    const int4 *tent;             // (frame, oy, ox, 0) per entry
-    const int *order;             // block -> tile, most frames first
+    const int *tiles;             // block -> tile
+    const int *tptr;              // block -> entry range
+    const int4 *tent;
     const float2 *probe;
     const float2 *psi;
     float2 *numO;
     float *denO;
 };
 
-template <int K>
-__global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
-    const int tile = a.order[blockIdx.x];
+template <int K, bool ACCUM>
+__global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
+    const int tile = a.tiles[blockIdx.x];
     const int ty = tile / a.ntx, tx = tile % a.ntx;
     const int col = threadIdx.x % OTILE_X, r0 = threadIdx.x / OTILE_X;
     constexpr int RSTEP = 256 / OTILE_X;            // row phases per block
@@ -478,7 +418,7 @@ __global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
     }
     const int N = a.N;
     const size_t fsz = (size_t)N * N;
-    const int f0 = a.tptr[tile], f1 = a.tptr[tile + 1];
+    const int f0 = a.tptr[blockIdx.x], f1 = a.tptr[blockIdx.x + 1];
     int4 nxt = f0 < f1 ? a.tent[f0] : make_int4(0, 0, 0, 0);
     for (int f = f0; f < f1; ++f) {
         const int4 e = nxt;
@@ -518,70 +458,49 @@ __global__ __launch_bounds__(256) void k_gather_obj_all(ObjAllArgs a) {
         const int py = ty * OTILE_Y + r0 + RSTEP * i;
         if (py >= a.Ny) continue;
         const size_t op = (size_t)py * a.Nx + px;
-        a.numO[op] = acc[i];
-        a.denO[op] = den[i];
+        if constexpr (ACCUM) {
+            const float2 n0 = a.numO[op];
+            a.numO[op] = make_float2(n0.x + acc[i].x, n0.y + acc[i].y);
+            a.denO[op] += den[i];
+        } else {
+            a.numO[op] = acc[i];
+            a.denO[op] = den[i];
+        }
     }
 }
 
-// Probe numerator/denominator: one thread per (probe pixel, mode), summing
-// over the stack's frames in slot order; the denominator is formed by the
-// mode-0 threads.
-template <bool FROM_SCR>
-__global__ __launch_bounds__(256) void k_gather_probe(GatherArgs a) {
-    const int N = a.N;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    const int k = blockIdx.y;
-    if (idx >= N * N) return;
-    const int y = idx / N, x = idx % N;
-    const size_t fsz = (size_t)N * N;
-    float2 acc = make_float2(0.0f, 0.0f);
-    float den = 0.0f;
-    for (int s = 0; s < a.S; ++s) {
-        const int j = a.order[a.s0 + s];
-        const int2 o = a.offs[j];
-        const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
-        const float2 v = a.psi[((size_t)(FROM_SCR ? s : j) * a.K + k) * fsz + idx];
-        const float2 cv = cmulc(ov, v);
-        acc.x += cv.x;
-        acc.y += cv.y;
-        den += cnorm(ov);
-    }
-    const size_t pp = (size_t)k * fsz + idx;
-    const float2 n0 = a.numP[pp];
-    a.numP[pp] = make_float2(n0.x + acc.x, n0.y + acc.y);
-    if (k == 0) a.denP[idx] += den;
-}
-
-// Probe numerator/denominator over ALL frames from stored exit waves
-// [J][K][N][N], taken after the object update (so with the new object).
-// One thread per (probe pixel, mode); the frames are split into gridDim.z
-// chunks of consecutive frame indices whose partial sums are added in chunk
-// order by k_probe_reduce.
+// Probe numerator/denominator over the frames order[q0 .. q0+nq), with the
+// given object: one thread per (probe pixel, mode); the range is split into
+// gridDim.z chunks whose partial sums k_probe_reduce adds in chunk order.
+// Exit waves are read from the stack scratch by slot (FROM_SCR, slot = q -
+// q0) or from stored exit waves [J][K][N][N] by frame.  The order is the
+// plan's spatially compact one, so object rows are reused in L2.
 struct ProbeAllArgs {
-    int N, K, J, Nx;
+    int N, K, q0, nq, Nx;
     const int2 *offs;
-    const int *order;   // frames in a spatially compact order (object rows reused in L2)
+    const int *order;
     const float2 *obj;
     const float2 *psi;
     float2 *part_num;   // [C][K][N*N]
     float *part_den;    // [C][N*N]
 };
 
-__global__ __launch_bounds__(256) void k_gather_probe_all(ProbeAllArgs a) {
+template <bool FROM_SCR>
+__global__ __launch_bounds__(256) void k_gather_probe(ProbeAllArgs a) {
     const int N = a.N;
     const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     const int k = blockIdx.y, c = blockIdx.z, C = gridDim.z;
     if (idx >= N * N) return;
     const int y = idx / N, x = idx % N;
     const size_t fsz = (size_t)N * N;
-    const int j0 = (int)((long)c * a.J / C), j1 = (int)((long)(c + 1) * a.J / C);
+    const int j0 = (int)((long)c * a.nq / C), j1 = (int)((long)(c + 1) * a.nq / C);
     float2 acc = make_float2(0.0f, 0.0f);
     float den = 0.0f;
     for (int q = j0; q < j1; ++q) {
-        const int j = a.order[q];
+        const int j = a.order[a.q0 + q];
         const int2 o = a.offs[j];
         const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
-        const float2 v = a.psi[((size_t)j * a.K + k) * fsz + idx];
+        const float2 v = a.psi[((size_t)(FROM_SCR ? q : j) * a.K + k) * fsz + idx];
         const float2 cv = cmulc(ov, v);
         acc.x += cv.x;
         acc.y += cv.y;
@@ -591,11 +510,12 @@ __global__ __launch_bounds__(256) void k_gather_probe_all(ProbeAllArgs a) {
     if (k == 0) a.part_den[(size_t)c * fsz + idx] = den;
 }
 
+// numP, denP (=, or += with accumulate) the chunk partials in chunk order.
 __global__ __launch_bounds__(256) void k_probe_reduce(const float2 *part_num, const float *part_den, int C, int K,
-                                                      long n2, float2 *numP, float *denP) {
+                                                      long n2, float2 *numP, float *denP, int accumulate) {
     const long np = n2 * K;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
-        float2 s = make_float2(0.0f, 0.0f);
+        float2 s = accumulate ? numP[i] : make_float2(0.0f, 0.0f);
         for (int c = 0; c < C; ++c) {
             const float2 v = part_num[(size_t)c * np + i];
             s.x += v.x;
@@ -603,7 +523,7 @@ __global__ __launch_bounds__(256) void k_probe_reduce(const float2 *part_num, co
         }
         numP[i] = s;
         if (i < n2) {
-            float d = 0.0f;
+            float d = accumulate ? denP[i] : 0.0f;
             for (int c = 0; c < C; ++c) d += part_den[(size_t)c * n2 + i];
             denP[i] = d;
         }

@@ -155,7 +155,7 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.off_order = o; o = up(o + sizeof(int) * J);
     L.off_ent_tile = o; o = up(o + sizeof(int) * L.nent_max);
     L.off_ent_fptr = o; o = up(o + sizeof(int) * (L.nent_max + 1));
-    L.off_ent_fr = o; o = up(o + sizeof(int) * L.nfr_max);
+    L.off_ent_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
     L.off_all_tptr = o; o = up(o + sizeof(int) * (ntiles + 1));
     L.off_all_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
     L.off_tile_order = o; o = up(o + sizeof(int) * ntiles);
@@ -194,8 +194,8 @@ struct ptycho_plan_s {
     char *ws;
     int2 *offs;
     int *order;
-    int *ent_tile, *ent_fptr, *ent_fr, *all_tptr;
-    int4 *all_ent;
+    int *ent_tile, *ent_fptr, *all_tptr;
+    int4 *ent_fr, *all_ent;
     int *tile_order;
     float2 *scr, *numO, *numP, *pnum;
     float *denO, *denP, *pden, *part;
@@ -205,8 +205,8 @@ struct ptycho_plan_s {
     std::vector<int> h_stack_ent;   // [nstacks+1] first entry of every stack
     // host copies kept alive for the asynchronous uploads
     std::vector<int2> h_offs;
-    std::vector<int> h_order, h_tile, h_fptr, h_fr, h_all_tptr;
-    std::vector<int4> h_all_ent;
+    std::vector<int> h_order, h_tile, h_fptr, h_all_tptr;
+    std::vector<int4> h_fr, h_all_ent;
     std::vector<int> h_tile_order;
 };
 
@@ -316,7 +316,7 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     p->order = (int *)(p->ws + L.off_order);
     p->ent_tile = (int *)(p->ws + L.off_ent_tile);
     p->ent_fptr = (int *)(p->ws + L.off_ent_fptr);
-    p->ent_fr = (int *)(p->ws + L.off_ent_fr);
+    p->ent_fr = (int4 *)(p->ws + L.off_ent_fr);
     p->all_tptr = (int *)(p->ws + L.off_all_tptr);
     p->all_ent = (int4 *)(p->ws + L.off_all_fr);
     p->tile_order = (int *)(p->ws + L.off_tile_order);
@@ -346,29 +346,33 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     p->h_order.resize(J);
     for (int j = 0; j < J; ++j) p->h_order[j] = key[j].second;
 
-    // per stack: touched object tiles (ascending) and, per tile, the slots
-    // of the covering frames (ascending)
+    // Object-gather lists: per stack, the touched object tiles with, per
+    // tile, entries (slot, oy, ox) of the covering frames in slot order; for
+    // all frames, every tile with entries (frame, oy, ox) in frame order.
+    // Within a list the tiles with the most entries come first.
     const int ntiles = p->ntx * p->nty;
-    std::vector<std::vector<int>> per_tile(ntiles);
+    auto by_size = [](std::vector<int> &tiles, const std::vector<std::vector<int4>> &lists) {
+        std::stable_sort(tiles.begin(), tiles.end(),
+                         [&](int a, int b) { return lists[a].size() > lists[b].size(); });
+    };
+    std::vector<std::vector<int4>> per_tile(ntiles);
     std::vector<int> touched;
     p->h_stack_ent.assign(L.nstacks + 1, 0);
-    p->h_fptr.clear();
-    p->h_fptr.push_back(0);
+    p->h_fptr.assign(1, 0);
     for (int sidx = 0; sidx < L.nstacks; ++sidx) {
         const int s0 = sidx * L.S, sn = std::min(L.S, J - s0);
         touched.clear();
         for (int s = 0; s < sn; ++s) {
             const int2 o = p->h_offs[p->h_order[s0 + s]];
-            const int ty0 = o.x / OTILE_Y, ty1 = (o.x + N - 1) / OTILE_Y;
-            const int tx0 = o.y / OTILE_X, tx1 = (o.y + N - 1) / OTILE_X;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
+            for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
+                for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx) {
                     auto &v = per_tile[ty * p->ntx + tx];
                     if (v.empty()) touched.push_back(ty * p->ntx + tx);
-                    v.push_back(s);
+                    v.push_back(make_int4(s, o.x, o.y, 0));
                 }
         }
         std::sort(touched.begin(), touched.end());
+        by_size(touched, per_tile);
         for (int t : touched) {
             p->h_tile.push_back(t);
             auto &v = per_tile[t];
@@ -378,31 +382,23 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
         }
         p->h_stack_ent[sidx + 1] = (int)p->h_tile.size();
     }
-    // all frames: tile -> covering frames in ascending frame index
     {
-        std::vector<int> cnt(ntiles + 1, 0);
-        for (int j = 0; j < J; ++j) {
-            const int2 o = p->h_offs[j];
-            for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
-                for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx) cnt[ty * p->ntx + tx + 1]++;
-        }
-        for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
-        p->h_all_tptr = cnt;
-        p->h_all_ent.assign(cnt[ntiles], make_int4(0, 0, 0, 0));
-        std::vector<int> fill(cnt.begin(), cnt.end() - 1);
         for (int j = 0; j < J; ++j) {
             const int2 o = p->h_offs[j];
             for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
                 for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx)
-                    p->h_all_ent[fill[ty * p->ntx + tx]++] = make_int4(j, o.x, o.y, 0);
+                    per_tile[ty * p->ntx + tx].push_back(make_int4(j, o.x, o.y, 0));
         }
-        // blocks of the all-frame object gather start with the tiles covered by
-        // the most frames, so the light border tiles fill in at the end
         p->h_tile_order.resize(ntiles);
         for (int t = 0; t < ntiles; ++t) p->h_tile_order[t] = t;
-        std::stable_sort(p->h_tile_order.begin(), p->h_tile_order.end(), [&](int a, int b) {
-            return cnt[a + 1] - cnt[a] > cnt[b + 1] - cnt[b];
-        });
+        by_size(p->h_tile_order, per_tile);
+        p->h_all_tptr.assign(1, 0);
+        for (int t : p->h_tile_order) {
+            auto &v = per_tile[t];
+            p->h_all_ent.insert(p->h_all_ent.end(), v.begin(), v.end());
+            p->h_all_tptr.push_back((int)p->h_all_ent.size());
+            v.clear();
+        }
     }
     if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max || p->h_all_ent.size() > L.nfr_max) {
         delete p;
@@ -430,7 +426,7 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     if (e == hipSuccess) e = up_copy(p->order, p->h_order.data(), sizeof(int) * J);
     if (e == hipSuccess) e = up_copy(p->ent_tile, p->h_tile.data(), sizeof(int) * p->h_tile.size());
     if (e == hipSuccess) e = up_copy(p->ent_fptr, p->h_fptr.data(), sizeof(int) * p->h_fptr.size());
-    if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int) * p->h_fr.size());
+    if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int4) * p->h_fr.size());
     if (e == hipSuccess) e = up_copy(p->all_tptr, p->h_all_tptr.data(), sizeof(int) * p->h_all_tptr.size());
     if (e == hipSuccess) e = up_copy(p->all_ent, p->h_all_ent.data(), sizeof(int4) * p->h_all_ent.size());
     if (e == hipSuccess) e = up_copy(p->tile_order, p->h_tile_order.data(), sizeof(int) * p->h_tile_order.size());
@@ -518,32 +514,6 @@ static StackArgs stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, 
     return a;
 }
 
-static GatherArgs gather_args(ptycho_plan_s *p, int sidx, int s0, int sn, const float *obj, const float *probe,
-                              const float2 *psi) {
-    GatherArgs g{};
-    g.N = p->d.n;
-    g.K = p->d.n_modes;
-    g.Ny = p->d.obj_ny;
-    g.Nx = p->d.obj_nx;
-    g.ntx = p->ntx;
-    g.S = sn;
-    g.s0 = s0;
-    g.ent0 = p->h_stack_ent[sidx];
-    g.offs = p->offs;
-    g.order = p->order;
-    g.ent_tile = p->ent_tile;
-    g.ent_fptr = p->ent_fptr;
-    g.ent_fr = p->ent_fr;
-    g.obj = (const float2 *)obj;
-    g.probe = (const float2 *)probe;
-    g.psi = psi;
-    g.numO = p->numO;
-    g.denO = p->denO;
-    g.numP = p->numP;
-    g.denP = p->denP;
-    return g;
-}
-
 // Kernels whose dynamic LDS exceeds 64 KiB must opt in once per process.
 template <class KernelT>
 static hipError_t set_dyn_lds(KernelT kern, size_t bytes) {
@@ -569,22 +539,74 @@ static void launch_cols_joint(const StackArgs &a, hipStream_t s) {
 }
 template <int N, int OP>
 static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2;
+    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * (OP == OP_LS ? 3 : 1);
     static const hipError_t attr = set_dyn_lds(k_cols_seq<N, OP>, lds);
     (void)attr;
     hipLaunchKernelGGL((k_cols_seq<N, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
 }
 
+// Object sums from exit waves: over one stack from the scratch (accumulated)
+// or, with sidx < 0, over all frames from stored exit waves (written).
 template <int K>
-static void launch_gather_obj(const GatherArgs &g, int nent, bool from_scr, hipStream_t s) {
-    if (nent <= 0) return;
-    if (from_scr) hipLaunchKernelGGL((k_gather_obj<K, true>), dim3(nent), dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_gather_obj<K, false>), dim3(nent), dim3(256), 0, s, g);
+static int object_sums(ptycho_plan_s *p, const float *probe, const float2 *psi, int sidx) {
+    ObjTileArgs a{};
+    a.N = p->d.n;
+    a.K = K;
+    a.Ny = p->d.obj_ny;
+    a.Nx = p->d.obj_nx;
+    a.ntx = p->ntx;
+    a.probe = (const float2 *)probe;
+    a.psi = psi;
+    a.numO = p->numO;
+    a.denO = p->denO;
+    int nb;
+    if (sidx < 0) {
+        a.tiles = p->tile_order;
+        a.tptr = p->all_tptr;
+        a.tent = p->all_ent;
+        nb = p->ntx * p->nty;
+    } else {
+        const int b0 = p->h_stack_ent[sidx];
+        nb = p->h_stack_ent[sidx + 1] - b0;
+        a.tiles = p->ent_tile + b0;
+        a.tptr = p->ent_fptr + b0;
+        a.tent = p->ent_fr;
+    }
+    if (nb <= 0) return PTYCHO_OK;
+    Timed tm(p, TC_GATHER_OBJ);
+    if (sidx < 0) hipLaunchKernelGGL((k_gather_obj<K, false>), dim3(nb), dim3(256), 0, p->stream, a);
+    else hipLaunchKernelGGL((k_gather_obj<K, true>), dim3(nb), dim3(256), 0, p->stream, a);
+    LAUNCHCHK();
+    return PTYCHO_OK;
 }
-static void launch_gather_probe(const GatherArgs &g, bool from_scr, hipStream_t s) {
-    dim3 grid((g.N * g.N + 255) / 256, g.K);
-    if (from_scr) hipLaunchKernelGGL((k_gather_probe<true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_gather_probe<false>), grid, dim3(256), 0, s, g);
+
+// Probe sums over frames order[q0 .. q0+nq) with the given object, from the
+// stack scratch (slots) or stored exit waves (frames); deterministic chunked
+// reduction, written or added to the running sums.
+static int probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, int q0, int nq, bool from_scr,
+                      bool accumulate) {
+    ProbeAllArgs a{};
+    a.N = p->d.n;
+    a.K = p->d.n_modes;
+    a.q0 = q0;
+    a.nq = nq;
+    a.Nx = p->d.obj_nx;
+    a.offs = p->offs;
+    a.order = p->order;
+    a.obj = (const float2 *)obj;
+    a.psi = psi;
+    a.part_num = p->pnum;
+    a.part_den = p->pden;
+    const long n2 = (long)a.N * a.N;
+    const int chunks = std::max(1, std::min(p->L.pchunks, nq));
+    dim3 grid((unsigned)((n2 + 255) / 256), a.K, chunks);
+    Timed tm(p, from_scr ? TC_GATHER_PROBE : TC_PROBE_ALL);
+    if (from_scr) hipLaunchKernelGGL(k_gather_probe<true>, grid, dim3(256), 0, p->stream, a);
+    else hipLaunchKernelGGL(k_gather_probe<false>, grid, dim3(256), 0, p->stream, a);
+    hipLaunchKernelGGL(k_probe_reduce, dim3(grid_for(n2 * a.K)), dim3(256), 0, p->stream, p->pnum, p->pden, chunks,
+                       a.K, n2, p->numP, p->denP, accumulate ? 1 : 0);
+    LAUNCHCHK();
+    return PTYCHO_OK;
 }
 
 // Which sums a projection pass accumulates.
@@ -639,64 +661,13 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
             else if (store) hipLaunchKernelGGL((k_rows_inv<N, OUT_STORE>), rg, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((k_rows_inv<N, OUT_SCR>), rg, dim3(256), 0, s, a);
         }
-        const bool from_scr = !store;
-        GatherArgs g = gather_args(p, sidx, s0, sn, obj, probe, from_scr ? p->scr : (const float2 *)psi);
-        if (acc & ACC_OBJ) {
-            Timed tm(p, TC_GATHER_OBJ);
-            launch_gather_obj<K>(g, p->h_stack_ent[sidx + 1] - p->h_stack_ent[sidx], from_scr, s);
-        }
-        if (acc & ACC_PROBE) {
-            Timed tm(p, TC_GATHER_PROBE);
-            launch_gather_probe(g, from_scr, s);
-        }
         LAUNCHCHK();
+        // per-stack sums read this stack's exit waves from the scratch
+        int st = PTYCHO_OK;
+        if (acc & ACC_OBJ) st = object_sums<K>(p, probe, p->scr, sidx);
+        if (!st && (acc & ACC_PROBE)) st = probe_sums(p, obj, p->scr, s0, sn, true, true);
+        if (st) return st;
     }
-    return PTYCHO_OK;
-}
-
-// Object sums over all frames from stored exit waves (written, not added).
-template <int K>
-static int object_pass(ptycho_plan_s *p, const float *probe, const float *psi) {
-    ObjAllArgs a{};
-    a.N = p->d.n;
-    a.K = K;
-    a.Ny = p->d.obj_ny;
-    a.Nx = p->d.obj_nx;
-    a.ntx = p->ntx;
-    a.tptr = p->all_tptr;
-    a.tent = p->all_ent;
-    a.order = p->tile_order;
-    a.probe = (const float2 *)probe;
-    a.psi = (const float2 *)psi;
-    a.numO = p->numO;
-    a.denO = p->denO;
-    Timed tm(p, TC_GATHER_OBJ);
-    hipLaunchKernelGGL((k_gather_obj_all<K>), dim3(p->ntx * p->nty), dim3(256), 0, p->stream, a);
-    LAUNCHCHK();
-    return PTYCHO_OK;
-}
-
-// Probe sums over all frames from stored exit waves, with the current
-// (already updated) object; deterministic chunked reduction.
-static int probe_pass(ptycho_plan_s *p, const float *obj, const float *psi) {
-    ProbeAllArgs a{};
-    a.N = p->d.n;
-    a.K = p->d.n_modes;
-    a.J = p->d.n_frames;
-    a.Nx = p->d.obj_nx;
-    a.offs = p->offs;
-    a.order = p->order;
-    a.obj = (const float2 *)obj;
-    a.psi = (const float2 *)psi;
-    a.part_num = p->pnum;
-    a.part_den = p->pden;
-    const long n2 = (long)a.N * a.N;
-    dim3 grid((unsigned)((n2 + 255) / 256), a.K, p->L.pchunks);
-    Timed tm(p, TC_PROBE_ALL);
-    hipLaunchKernelGGL(k_gather_probe_all, grid, dim3(256), 0, p->stream, a);
-    hipLaunchKernelGGL(k_probe_reduce, dim3(grid_for(n2 * a.K)), dim3(256), 0, p->stream, p->pnum, p->pden,
-                       p->L.pchunks, a.K, n2, p->numP, p->denP);
-    LAUNCHCHK();
     return PTYCHO_OK;
 }
 
@@ -741,9 +712,9 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
                 int s2 = PTYCHO_OK;
                 if ((upd & 1u) && !stored) s2 = zero_sums(p, ACC_OBJ);
                 if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, stored ? 0u : (upd & 1u));
-                if (!s2 && (upd & 1u) && stored) s2 = object_pass<K>(p, probe, psi);
+                if (!s2 && (upd & 1u) && stored) s2 = object_sums<K>(p, probe, (const float2 *)psi, -1);
                 if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
-                if (!s2 && (upd & 2u)) s2 = probe_pass(p, obj, psi);
+                if (!s2 && (upd & 2u)) s2 = probe_sums(p, obj, (const float2 *)psi, 0, p->d.n_frames, false, false);
                 if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);
                 if (s2) return s2;
             }
@@ -790,9 +761,15 @@ static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         a.icalc = icalc;
         a.red = p->red + (size_t)sidx * maxb * (ls ? 2 : 1);
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
-        if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS>), rg, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), rg, dim3(256), 0, s, a);
-        launch_cols_seq<N, OP>(a, s);
+        {
+            Timed tm(p, TC_ROWS_FWD);
+            if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS>), rg, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), rg, dim3(256), 0, s, a);
+        }
+        {
+            Timed tm(p, TC_COLS);
+            launch_cols_seq<N, OP>(a, s);
+        }
         LAUNCHCHK();
     }
     return PTYCHO_OK;
@@ -928,6 +905,8 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
         // 1. gradient (sums in numO/numP), LLK, denominators
         st = grad_pass(p, obj, probe);
         if (st) return st;
+        {
+        Timed tm(p, TC_OTHER);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, p->red, (long)p->L.nred, 1, scal + CG_LLK, 0);
         hipLaunchKernelGGL(k_max_partial, dim3(NPART), dim3(256), 0, s, p->denO, (long)no, p->denP, n2, p->part);
         // 2. inner products for beta, then the new direction
@@ -936,6 +915,7 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
         hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, cpart, p->part, NPART, scal, hist ? hist + c : nullptr);
         hipLaunchKernelGGL(k_cg_direction, dim3(grid_for((long)std::max(no, np))), dim3(256), 0, s, p->numO, g_o, d_o,
                            (long)no, p->numP, g_p, d_p, (long)np, upd, scal);
+        }
         // 3. line search along d, then the step
         st = ls_pass(p, obj, probe, (const float *)d_o, (const float *)d_p, scal + CG_L1);
         if (st) return st;
