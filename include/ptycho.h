@@ -108,6 +108,13 @@ int ptycho_plan_create(const ptycho_desc_t *desc, const int32_t *offsets_host,
                        void *workspace_dev, size_t workspace_bytes,
                        void *stream, ptycho_plan_t *out);
 
+/* Build and check a plan's host-side index tables (frame order, object-gather
+ * lists) for `desc` and offsets_host without any GPU work; *table_bytes_out
+ * receives their size.  Same checks and status codes as ptycho_plan_create
+ * (without the device pointers); for capacity planning and tests. */
+int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
+                        size_t *table_bytes_out);
+
 /* Change the stream later calls enqueue on (hipStream_t). */
 int ptycho_plan_set_stream(ptycho_plan_t plan, void *stream);
 

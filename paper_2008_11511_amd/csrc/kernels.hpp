@@ -47,6 +47,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (b & 7) * (full >> 3) + (b >> 3);
 }
 
+// Streaming load: data read once (exit waves in the gathers) are marked
+// non-temporal so that they do not evict the data the gathers reuse from L2
+// (the probe, the object rows).
+__device__ __forceinline__ float2 ld_stream(const float2 *p) {
+    return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+
 // Object tile of the atomic-free object gather.
 constexpr int OTILE_Y = 16, OTILE_X = 64;
 
@@ -392,13 +399,16 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
 // the sums are written (every tile of the object is listed).
 struct ObjTileArgs {
     int N, K, Ny, Nx, ntx;
-    const int *tiles;             // block -> tile
+    const int *tiles;             // block -> tile (-1: nothing to do)
     const int *tptr;              // block -> entry range
+    const int *pslot;             // block -> partial slot, -1: write the sums directly
     const int4 *tent;
     const float2 *probe;
     const float2 *psi;
     float2 *numO;
     float *denO;
+    float2 *pnum;                 // partial sums [slot][OTILE_Y * OTILE_X]
+    float *pden;
 };
 
 template <int K, bool ACCUM>
@@ -419,38 +429,58 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
     const int N = a.N;
     const size_t fsz = (size_t)N * N;
     const int f0 = a.tptr[blockIdx.x], f1 = a.tptr[blockIdx.x + 1];
-    int4 nxt = f0 < f1 ? a.tent[f0] : make_int4(0, 0, 0, 0);
-    for (int f = f0; f < f1; ++f) {
-        const int4 e = nxt;
-        if (f + 1 < f1) nxt = a.tent[f + 1];          // next entry in flight early
-        // branch-free body: out-of-window pixels read a clamped in-window
-        // address and are weighted 0, so all loads of a frame issue at once
-        const int x = px - e.z;
-        const bool xin = (unsigned)x < (unsigned)N;
-        const int xc = min(max(x, 0), N - 1);
-        const float2 *ps = a.psi + (size_t)e.x * K * fsz;
-        float2 v[PY][K], p[PY][K];
-        float m[PY];
+    // Two frames per iteration: all loads of both are issued before either
+    // is summed (the per-pixel order of the sum is unchanged).  Out-of-window
+    // pixels read a clamped in-window address and are weighted 0, so the
+    // body is branch-free.
+    for (int f = f0; f < f1; f += 2) {
+        const bool two = f + 1 < f1;
+        const int4 e0 = a.tent[f];
+        const int4 e1 = two ? a.tent[f + 1] : e0;
+        float2 v[2][PY][K], p[2][PY][K];
+        float m[2][PY];
 #pragma unroll
-        for (int i = 0; i < PY; ++i) {
-            const int y = ty * OTILE_Y + r0 + RSTEP * i - e.y;
-            m[i] = (xin && (unsigned)y < (unsigned)N) ? 1.0f : 0.0f;
-            const size_t pix = (size_t)min(max(y, 0), N - 1) * N + xc;
+        for (int h = 0; h < 2; ++h) {
+            const int4 e = h ? e1 : e0;
+            const int x = px - e.z;
+            const bool xin = (unsigned)x < (unsigned)N && (h == 0 || two);
+            const int xc = min(max(x, 0), N - 1);
+            const float2 *ps = a.psi + (size_t)e.x * K * fsz;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                p[i][k] = a.probe[k * fsz + pix];
-                v[i][k] = ps[k * fsz + pix];
+            for (int i = 0; i < PY; ++i) {
+                const int y = ty * OTILE_Y + r0 + RSTEP * i - e.y;
+                m[h][i] = (xin && (unsigned)y < (unsigned)N) ? 1.0f : 0.0f;
+                const size_t pix = (size_t)min(max(y, 0), N - 1) * N + xc;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    p[h][i][k] = a.probe[k * fsz + pix];
+                    v[h][i][k] = ps[k * fsz + pix];
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < PY; ++i)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float2 cv = cmulc(p[i][k], v[i][k]);
-                acc[i].x += m[i] * cv.x;
-                acc[i].y += m[i] * cv.y;
-                den[i] += m[i] * cnorm(p[i][k]);
-            }
+            for (int i = 0; i < PY; ++i)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float2 cv = cmulc(p[h][i][k], v[h][i][k]);
+                    acc[i].x += m[h][i] * cv.x;
+                    acc[i].y += m[h][i] * cv.y;
+                    den[i] += m[h][i] * cnorm(p[h][i][k]);
+                }
+    }
+    const int slot = a.pslot[blockIdx.x];
+    if (slot >= 0) {
+        // a chunk of a long frame list: partial sums, added in chunk order by
+        // k_obj_chunk_reduce
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            const size_t q = (size_t)slot * (OTILE_Y * OTILE_X) + (r0 + RSTEP * i) * OTILE_X + col;
+            a.pnum[q] = acc[i];
+            a.pden[q] = den[i];
+        }
+        return;
     }
     if (px >= a.Nx) return;
 #pragma unroll
@@ -465,6 +495,37 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
         } else {
             a.numO[op] = acc[i];
             a.denO[op] = den[i];
+        }
+    }
+}
+
+// Sums of the chunk partials of split tiles: block b handles tile rtile[b]
+// whose chunks occupy partial slots rfirst[b] .. rfirst[b] + rcount[b] - 1.
+template <bool ACCUM>
+__global__ __launch_bounds__(256) void k_obj_chunk_reduce(const int *rtile, const int *rfirst, const int *rcount,
+                                                          const float2 *pnum, const float *pden, float2 *numO,
+                                                          float *denO, int ntx, int Ny, int Nx) {
+    const int tile = rtile[blockIdx.x], first = rfirst[blockIdx.x], n = rcount[blockIdx.x];
+    const int ty = tile / ntx, tx = tile % ntx;
+    for (int q = threadIdx.x; q < OTILE_Y * OTILE_X; q += 256) {
+        const int py = ty * OTILE_Y + q / OTILE_X, px = tx * OTILE_X + q % OTILE_X;
+        float2 s = make_float2(0.0f, 0.0f);
+        float d = 0.0f;
+        for (int c = 0; c < n; ++c) {
+            const size_t i = (size_t)(first + c) * (OTILE_Y * OTILE_X) + q;
+            s.x += pnum[i].x;
+            s.y += pnum[i].y;
+            d += pden[i];
+        }
+        if (py >= Ny || px >= Nx) continue;
+        const size_t op = (size_t)py * Nx + px;
+        if constexpr (ACCUM) {
+            const float2 n0 = numO[op];
+            numO[op] = make_float2(n0.x + s.x, n0.y + s.y);
+            denO[op] += d;
+        } else {
+            numO[op] = s;
+            denO[op] = d;
         }
     }
 }
@@ -500,7 +561,7 @@ __global__ __launch_bounds__(256) void k_gather_probe(ProbeAllArgs a) {
         const int j = a.order[a.q0 + q];
         const int2 o = a.offs[j];
         const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
-        const float2 v = a.psi[((size_t)(FROM_SCR ? q : j) * a.K + k) * fsz + idx];
+        const float2 v = ld_stream(a.psi + ((size_t)(FROM_SCR ? q : j) * a.K + k) * fsz + idx);
         const float2 cv = cmulc(ov, v);
         acc.x += cv.x;
         acc.y += cv.y;

@@ -108,8 +108,9 @@ static constexpr int NSCAL = 64;        // device scalars
 
 struct Layout {
     int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
+    size_t nlist_ints, npslots;   // object-gather block/reduce lists, partial slots
     size_t nent_max, nfr_max, nred;
-    size_t off_offs, off_order, off_ent_tile, off_ent_fptr, off_ent_fr, off_all_tptr, off_all_fr, off_tile_order, off_scr, off_numO, off_denO,
+    size_t off_offs, off_order, off_lists, off_ent_fr, off_all_fr, off_opart, off_scr, off_numO, off_denO,
         off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, total;
 };
 
@@ -145,20 +146,25 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.maxb_ls = (int)(((long)L.S_ls * N + cb - 1) / cb);
     const long ty = (N + OTILE_Y - 1) / OTILE_Y + 1, tx = (N + OTILE_X - 1) / OTILE_X + 1;
     L.nfr_max = (size_t)J * ty * tx;
-    const long ntiles = (long)((d.obj_ny + OTILE_Y - 1) / OTILE_Y) * ((d.obj_nx + OTILE_X - 1) / OTILE_X);
+    const long ntx = (d.obj_nx + OTILE_X - 1) / OTILE_X, nty = (d.obj_ny + OTILE_Y - 1) / OTILE_Y;
+    const long ntiles = ntx * nty;
     L.nent_max = std::min((size_t)L.nstacks * ntiles, L.nfr_max);
+    // object-gather lists (all frames, and per stack): per block tile, entry
+    // range, partial slot; per split tile: tile, first slot, count
+    const size_t nb_all = (size_t)ntiles + L.nfr_max / 16 + 1;
+    const size_t nb_st = L.nent_max + L.nfr_max / 16 + L.nstacks;
+    L.nlist_ints = 3 * (nb_all + nb_st) + 2 + 3 * ((size_t)ntiles + L.nent_max);
+    L.npslots = std::min<size_t>(8192, L.nfr_max / 8 + 1);
     L.nred = std::max((size_t)L.nstacks * L.maxb, (size_t)L.nstacks_ls * L.maxb_ls * 2);
     L.pchunks = probe_chunks(d);
     const size_t n2 = (size_t)N * N, no = (size_t)d.obj_ny * d.obj_nx;
     size_t o = 0;
     L.off_offs = o; o = up(o + sizeof(int2) * J);
     L.off_order = o; o = up(o + sizeof(int) * J);
-    L.off_ent_tile = o; o = up(o + sizeof(int) * L.nent_max);
-    L.off_ent_fptr = o; o = up(o + sizeof(int) * (L.nent_max + 1));
+    L.off_lists = o; o = up(o + sizeof(int) * L.nlist_ints);
     L.off_ent_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
-    L.off_all_tptr = o; o = up(o + sizeof(int) * (ntiles + 1));
     L.off_all_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
-    L.off_tile_order = o; o = up(o + sizeof(int) * ntiles);
+    L.off_opart = o; o = up(o + (sizeof(float2) + sizeof(float)) * L.npslots * OTILE_Y * OTILE_X);
     L.off_scr = o; o = up(o + sizeof(float2) * (size_t)std::max(L.S, 3 * L.S_ls) * K * n2);
     L.off_numO = o; o = up(o + sizeof(float2) * no);
     L.off_denO = o; o = up(o + sizeof(float) * no);
@@ -194,20 +200,28 @@ struct ptycho_plan_s {
     char *ws;
     int2 *offs;
     int *order;
-    int *ent_tile, *ent_fptr, *all_tptr;
     int4 *ent_fr, *all_ent;
-    int *tile_order;
+    int *lists;          // device copy of h_lists
+    float2 *opnum;       // object-gather chunk partials
+    float *opden;
     float2 *scr, *numO, *numP, *pnum;
     float *denO, *denP, *pden, *part;
     double *red, *scal;
     int ntx, nty;
     long n_obs;
-    std::vector<int> h_stack_ent;   // [nstacks+1] first entry of every stack
+    // Object-gather lists.  A list is a run of blocks (tile, entry range,
+    // partial slot or -1) followed by a run of reductions (split tile, first
+    // slot, count), stored in h_lists; GatherList gives the offsets.
+    struct GatherList {
+        int nb, blk_tile, blk_ptr, blk_slot, nr, red_tile, red_first, red_count;
+    };
+    GatherList all_list;
+    std::vector<GatherList> stack_lists;
+    std::vector<int> h_lists;
     // host copies kept alive for the asynchronous uploads
     std::vector<int2> h_offs;
-    std::vector<int> h_order, h_tile, h_fptr, h_all_tptr;
+    std::vector<int> h_order;
     std::vector<int4> h_fr, h_all_ent;
-    std::vector<int> h_tile_order;
 };
 
 // Records an event pair around the launches made while it is alive.
@@ -286,53 +300,11 @@ static uint32_t spread_bits(uint32_t v) {
     return v;
 }
 
-extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets, const float *iobs,
-                                  const uint8_t *mask, void *ws, size_t ws_bytes, void *stream,
-                                  ptycho_plan_t *out) {
-    int st = check_desc(d);
-    if (st) return st;
-    if (!offsets || !iobs || !out) return fail(PTYCHO_E_INVALID, "null pointer");
-    const Layout L = layout_for(*d);
-    if (!ws) return fail(PTYCHO_E_WORKSPACE, "null workspace");
-    if (((uintptr_t)ws) % ALIGN) return fail(PTYCHO_E_WORKSPACE, "workspace not 256-byte aligned");
-    if (ws_bytes < L.total) return fail(PTYCHO_E_WORKSPACE, "workspace too small");
+// Host-side index tables of a plan: frame order, object-gather lists.  No
+// GPU work; shared by ptycho_plan_create and ptycho_plan_dry_run.
+static int build_host_tables(ptycho_plan_s *p, const Layout &L, const int32_t *offsets) {
+    const ptycho_desc_t *d = &p->d;
     const int J = d->n_frames, N = d->n;
-    for (int j = 0; j < J; ++j) {
-        const int oy = offsets[2 * j], ox = offsets[2 * j + 1];
-        if (oy < 0 || ox < 0 || oy > d->obj_ny - N || ox > d->obj_nx - N)
-            return fail(PTYCHO_E_BOUNDS, "frame window outside the object (frame " + std::to_string(j) + ")");
-    }
-    st = ensure_twiddles();
-    if (st) return st;
-
-    auto *p = new ptycho_plan_s();
-    p->d = *d;
-    p->L = L;
-    p->stream = (hipStream_t)stream;
-    p->iobs = iobs;
-    p->mask = mask;
-    p->ws = (char *)ws;
-    p->offs = (int2 *)(p->ws + L.off_offs);
-    p->order = (int *)(p->ws + L.off_order);
-    p->ent_tile = (int *)(p->ws + L.off_ent_tile);
-    p->ent_fptr = (int *)(p->ws + L.off_ent_fptr);
-    p->ent_fr = (int4 *)(p->ws + L.off_ent_fr);
-    p->all_tptr = (int *)(p->ws + L.off_all_tptr);
-    p->all_ent = (int4 *)(p->ws + L.off_all_fr);
-    p->tile_order = (int *)(p->ws + L.off_tile_order);
-    p->scr = (float2 *)(p->ws + L.off_scr);
-    p->numO = (float2 *)(p->ws + L.off_numO);
-    p->denO = (float *)(p->ws + L.off_denO);
-    p->numP = (float2 *)(p->ws + L.off_numP);
-    p->denP = (float *)(p->ws + L.off_denP);
-    p->pnum = (float2 *)(p->ws + L.off_pnum);
-    p->pden = (float *)(p->ws + L.off_pden);
-    p->part = (float *)(p->ws + L.off_part);
-    p->red = (double *)(p->ws + L.off_red);
-    p->scal = (double *)(p->ws + L.off_scal);
-    p->ntx = (d->obj_nx + OTILE_X - 1) / OTILE_X;
-    p->nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
-
     // frame order: Morton (Z) order of the window corners, so that every
     // stack covers a compact patch of the object
     p->h_offs.resize(J);
@@ -349,16 +321,58 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     // Object-gather lists: per stack, the touched object tiles with, per
     // tile, entries (slot, oy, ox) of the covering frames in slot order; for
     // all frames, every tile with entries (frame, oy, ox) in frame order.
-    // Within a list the tiles with the most entries come first.
+    // Tiles with the most entries come first; a tile with more than F entries
+    // (F ~ entries / 4096, at least 16) is split into chunks of at most F
+    // whose partial sums a reduction adds in chunk order, so no block carries
+    // a much longer serial frame loop than the others.
     const int ntiles = p->ntx * p->nty;
-    auto by_size = [](std::vector<int> &tiles, const std::vector<std::vector<int4>> &lists) {
-        std::stable_sort(tiles.begin(), tiles.end(),
-                         [&](int a, int b) { return lists[a].size() > lists[b].size(); });
-    };
     std::vector<std::vector<int4>> per_tile(ntiles);
+    int max_slots = 0;
+    auto emit_list = [&](std::vector<int> &tiles, std::vector<int4> &ents, size_t ent_base) {
+        std::stable_sort(tiles.begin(), tiles.end(),
+                         [&](int a, int b) { return per_tile[a].size() > per_tile[b].size(); });
+        size_t total = 0;
+        for (int t : tiles) total += per_tile[t].size();
+        const int F = (int)std::max<size_t>(16, (total + 4095) / 4096);
+        std::vector<int> bt, bp, bs, rt, rf, rc;
+        int slots = 0;
+        for (int t : tiles) {
+            auto &v = per_tile[t];
+            const int n = (int)v.size();
+            const int nch = (n + F - 1) / F;
+            if (nch > 1) {
+                rt.push_back(t);
+                rf.push_back(slots);
+                rc.push_back(nch);
+            }
+            for (int c = 0; c < nch; ++c) {
+                bt.push_back(t);
+                bp.push_back((int)(ents.size() - ent_base) + c * F);
+                bs.push_back(nch > 1 ? slots + c : -1);
+            }
+            if (nch > 1) slots += nch;
+            ents.insert(ents.end(), v.begin(), v.end());
+            v.clear();
+        }
+        bp.push_back((int)(ents.size() - ent_base));
+        max_slots = std::max(max_slots, slots);
+        ptycho_plan_s::GatherList gl{};
+        auto put = [&](const std::vector<int> &x) {
+            const int at = (int)p->h_lists.size();
+            p->h_lists.insert(p->h_lists.end(), x.begin(), x.end());
+            return at;
+        };
+        gl.nb = (int)bt.size();
+        gl.blk_tile = put(bt);
+        gl.blk_ptr = put(bp);
+        gl.blk_slot = put(bs);
+        gl.nr = (int)rt.size();
+        gl.red_tile = put(rt);
+        gl.red_first = put(rf);
+        gl.red_count = put(rc);
+        return gl;
+    };
     std::vector<int> touched;
-    p->h_stack_ent.assign(L.nstacks + 1, 0);
-    p->h_fptr.assign(1, 0);
     for (int sidx = 0; sidx < L.nstacks; ++sidx) {
         const int s0 = sidx * L.S, sn = std::min(L.S, J - s0);
         touched.clear();
@@ -372,37 +386,77 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
                 }
         }
         std::sort(touched.begin(), touched.end());
-        by_size(touched, per_tile);
-        for (int t : touched) {
-            p->h_tile.push_back(t);
-            auto &v = per_tile[t];
-            p->h_fr.insert(p->h_fr.end(), v.begin(), v.end());
-            p->h_fptr.push_back((int)p->h_fr.size());
-            v.clear();
-        }
-        p->h_stack_ent[sidx + 1] = (int)p->h_tile.size();
+        const size_t base = p->h_fr.size();
+        p->stack_lists.push_back(emit_list(touched, p->h_fr, 0));
+        (void)base;
+    }
+    for (int j = 0; j < J; ++j) {
+        const int2 o = p->h_offs[j];
+        for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
+            for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx)
+                per_tile[ty * p->ntx + tx].push_back(make_int4(j, o.x, o.y, 0));
     }
     {
-        for (int j = 0; j < J; ++j) {
-            const int2 o = p->h_offs[j];
-            for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
-                for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx)
-                    per_tile[ty * p->ntx + tx].push_back(make_int4(j, o.x, o.y, 0));
-        }
-        p->h_tile_order.resize(ntiles);
-        for (int t = 0; t < ntiles; ++t) p->h_tile_order[t] = t;
-        by_size(p->h_tile_order, per_tile);
-        p->h_all_tptr.assign(1, 0);
-        for (int t : p->h_tile_order) {
-            auto &v = per_tile[t];
-            p->h_all_ent.insert(p->h_all_ent.end(), v.begin(), v.end());
-            p->h_all_tptr.push_back((int)p->h_all_ent.size());
-            v.clear();
-        }
+        std::vector<int> all_tiles;
+        for (int t = 0; t < ntiles; ++t)
+            if (!per_tile[t].empty()) all_tiles.push_back(t);
+        p->all_list = emit_list(all_tiles, p->h_all_ent, 0);
     }
-    if (p->h_tile.size() > L.nent_max || p->h_fr.size() > L.nfr_max || p->h_all_ent.size() > L.nfr_max) {
+    if (p->h_fr.size() > L.nfr_max || p->h_all_ent.size() > L.nfr_max || p->h_lists.size() > L.nlist_ints ||
+        (size_t)max_slots > L.npslots) {
+        return fail(PTYCHO_E_WORKSPACE, "internal: object-gather lists exceed their bound");
+    }
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets, const float *iobs,
+                                  const uint8_t *mask, void *ws, size_t ws_bytes, void *stream,
+                                  ptycho_plan_t *out) {
+    int st = check_desc(d);
+    if (st) return st;
+    if (!offsets || !iobs || !out) return fail(PTYCHO_E_INVALID, "null pointer");
+    const Layout L = layout_for(*d);
+    if (!ws) return fail(PTYCHO_E_WORKSPACE, "null workspace");
+    if (((uintptr_t)ws) % ALIGN) return fail(PTYCHO_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < L.total) return fail(PTYCHO_E_WORKSPACE, "workspace too small");
+    const int J = d->n_frames, N = d->n;
+    for (int j = 0; j < J; ++j) {
+        const int oy = offsets[2 * j], ox = offsets[2 * j + 1];
+        if (oy < 0 || ox < 0 || oy > d->obj_ny - N || ox > d->obj_nx - N)
+            return fail(PTYCHO_E_BOUNDS, "frame window outside the object (frame " + std::to_string(j) + ")");
+    }
+    auto *p = new ptycho_plan_s();
+    p->d = *d;
+    p->L = L;
+    p->stream = (hipStream_t)stream;
+    p->iobs = iobs;
+    p->mask = mask;
+    p->ws = (char *)ws;
+    p->offs = (int2 *)(p->ws + L.off_offs);
+    p->order = (int *)(p->ws + L.off_order);
+    p->lists = (int *)(p->ws + L.off_lists);
+    p->ent_fr = (int4 *)(p->ws + L.off_ent_fr);
+    p->all_ent = (int4 *)(p->ws + L.off_all_fr);
+    p->opnum = (float2 *)(p->ws + L.off_opart);
+    p->opden = (float *)(p->opnum + L.npslots * OTILE_Y * OTILE_X);
+    p->scr = (float2 *)(p->ws + L.off_scr);
+    p->numO = (float2 *)(p->ws + L.off_numO);
+    p->denO = (float *)(p->ws + L.off_denO);
+    p->numP = (float2 *)(p->ws + L.off_numP);
+    p->denP = (float *)(p->ws + L.off_denP);
+    p->pnum = (float2 *)(p->ws + L.off_pnum);
+    p->pden = (float *)(p->ws + L.off_pden);
+    p->part = (float *)(p->ws + L.off_part);
+    p->red = (double *)(p->ws + L.off_red);
+    p->scal = (double *)(p->ws + L.off_scal);
+    p->ntx = (d->obj_nx + OTILE_X - 1) / OTILE_X;
+    p->nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
+
+    st = build_host_tables(p, L, offsets);
+    if (!st) st = ensure_twiddles();
+    if (st) {
         delete p;
-        return fail(PTYCHO_E_WORKSPACE, "internal: tile lists exceed their bound");
+        return st;
     }
     long good = (long)N * N;
     if (mask) {
@@ -424,18 +478,38 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up_copy(p->offs, p->h_offs.data(), sizeof(int2) * J);
     if (e == hipSuccess) e = up_copy(p->order, p->h_order.data(), sizeof(int) * J);
-    if (e == hipSuccess) e = up_copy(p->ent_tile, p->h_tile.data(), sizeof(int) * p->h_tile.size());
-    if (e == hipSuccess) e = up_copy(p->ent_fptr, p->h_fptr.data(), sizeof(int) * p->h_fptr.size());
+    if (e == hipSuccess) e = up_copy(p->lists, p->h_lists.data(), sizeof(int) * p->h_lists.size());
     if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int4) * p->h_fr.size());
-    if (e == hipSuccess) e = up_copy(p->all_tptr, p->h_all_tptr.data(), sizeof(int) * p->h_all_tptr.size());
     if (e == hipSuccess) e = up_copy(p->all_ent, p->h_all_ent.data(), sizeof(int4) * p->h_all_ent.size());
-    if (e == hipSuccess) e = up_copy(p->tile_order, p->h_tile_order.data(), sizeof(int) * p->h_tile_order.size());
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         delete p;
         return fail(PTYCHO_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
     }
     *out = p;
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_dry_run(const ptycho_desc_t *d, const int32_t *offsets, size_t *table_bytes) {
+    int st = check_desc(d);
+    if (st) return st;
+    if (!offsets || !table_bytes) return fail(PTYCHO_E_INVALID, "null pointer");
+    const Layout L = layout_for(*d);
+    const int J = d->n_frames, N = d->n;
+    for (int j = 0; j < J; ++j) {
+        const int oy = offsets[2 * j], ox = offsets[2 * j + 1];
+        if (oy < 0 || ox < 0 || oy > d->obj_ny - N || ox > d->obj_nx - N)
+            return fail(PTYCHO_E_BOUNDS, "frame window outside the object (frame " + std::to_string(j) + ")");
+    }
+    ptycho_plan_s p{};
+    p.d = *d;
+    p.L = L;
+    p.ntx = (d->obj_nx + OTILE_X - 1) / OTILE_X;
+    p.nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
+    st = build_host_tables(&p, L, offsets);
+    if (st) return st;
+    *table_bytes = sizeof(int) * p.h_lists.size() + sizeof(int4) * (p.h_fr.size() + p.h_all_ent.size()) +
+                   sizeof(int) * p.h_order.size() + sizeof(int2) * p.h_offs.size();
     return PTYCHO_OK;
 }
 
@@ -549,33 +623,40 @@ static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
 // or, with sidx < 0, over all frames from stored exit waves (written).
 template <int K>
 static int object_sums(ptycho_plan_s *p, const float *probe, const float2 *psi, int sidx) {
+    const ptycho_plan_s::GatherList &gl = sidx < 0 ? p->all_list : p->stack_lists[sidx];
+    if (gl.nb <= 0) return PTYCHO_OK;
     ObjTileArgs a{};
     a.N = p->d.n;
     a.K = K;
     a.Ny = p->d.obj_ny;
     a.Nx = p->d.obj_nx;
     a.ntx = p->ntx;
+    a.tiles = p->lists + gl.blk_tile;
+    a.tptr = p->lists + gl.blk_ptr;
+    a.pslot = p->lists + gl.blk_slot;
+    a.tent = sidx < 0 ? p->all_ent : p->ent_fr;
     a.probe = (const float2 *)probe;
     a.psi = psi;
     a.numO = p->numO;
     a.denO = p->denO;
-    int nb;
-    if (sidx < 0) {
-        a.tiles = p->tile_order;
-        a.tptr = p->all_tptr;
-        a.tent = p->all_ent;
-        nb = p->ntx * p->nty;
-    } else {
-        const int b0 = p->h_stack_ent[sidx];
-        nb = p->h_stack_ent[sidx + 1] - b0;
-        a.tiles = p->ent_tile + b0;
-        a.tptr = p->ent_fptr + b0;
-        a.tent = p->ent_fr;
-    }
-    if (nb <= 0) return PTYCHO_OK;
+    a.pnum = p->opnum;
+    a.pden = p->opden;
     Timed tm(p, TC_GATHER_OBJ);
-    if (sidx < 0) hipLaunchKernelGGL((k_gather_obj<K, false>), dim3(nb), dim3(256), 0, p->stream, a);
-    else hipLaunchKernelGGL((k_gather_obj<K, true>), dim3(nb), dim3(256), 0, p->stream, a);
+    // all frames: every tile of the object that a frame covers is written
+    // (the rest were zeroed); one stack: sums are added
+    if (sidx < 0) hipLaunchKernelGGL((k_gather_obj<K, false>), dim3(gl.nb), dim3(256), 0, p->stream, a);
+    else hipLaunchKernelGGL((k_gather_obj<K, true>), dim3(gl.nb), dim3(256), 0, p->stream, a);
+    if (gl.nr > 0) {
+        const int *L0 = p->lists;
+        if (sidx < 0)
+            hipLaunchKernelGGL(k_obj_chunk_reduce<false>, dim3(gl.nr), dim3(256), 0, p->stream, L0 + gl.red_tile,
+                               L0 + gl.red_first, L0 + gl.red_count, p->opnum, p->opden, p->numO, p->denO, p->ntx,
+                               p->d.obj_ny, p->d.obj_nx);
+        else
+            hipLaunchKernelGGL(k_obj_chunk_reduce<true>, dim3(gl.nr), dim3(256), 0, p->stream, L0 + gl.red_tile,
+                               L0 + gl.red_first, L0 + gl.red_count, p->opnum, p->opden, p->numO, p->denO, p->ntx,
+                               p->d.obj_ny, p->d.obj_nx);
+    }
     LAUNCHCHK();
     return PTYCHO_OK;
 }
@@ -710,7 +791,7 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
             const bool stored = (psi != nullptr);
             for (int c = 0; c < n_cycles; ++c) {
                 int s2 = PTYCHO_OK;
-                if ((upd & 1u) && !stored) s2 = zero_sums(p, ACC_OBJ);
+                if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
                 if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, stored ? 0u : (upd & 1u));
                 if (!s2 && (upd & 1u) && stored) s2 = object_sums<K>(p, probe, (const float2 *)psi, -1);
                 if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);

@@ -106,3 +106,46 @@ def test_plan_create_rejects_bad_arguments_before_gpu_work():
     assert h.ptycho_plan_destroy(None) == 0
     assert h.ptycho_fft2(48, 1, fake, -1, None) == -3
     assert h.ptycho_fft2(64, 1, fake, 0, None) == -1
+
+
+def _dry(n, k, j, obj, stack, offs):
+    h = _lib.lib()
+    d = _desc(n=n, n_modes=k, n_frames=j, obj_ny=obj[0], obj_nx=obj[1], stack=stack)
+    nbytes = ctypes.c_size_t()
+    offs = np.ascontiguousarray(offs, dtype=np.int32)
+    return h.ptycho_plan_dry_run(ctypes.byref(d), offs.ctypes.data, ctypes.byref(nbytes)), nbytes.value
+
+
+@pytest.mark.parametrize("stack", [0, 1, 3, 7, 16, 1000])
+def test_plan_tables_fit_their_workspace_bounds_for_any_stack(stack):
+    import synth
+    for name in ("ap64", "dm256"):
+        wl = synth.workload(name)
+        offs = oracle.offsets_from_positions(synth.spiral_positions(wl.n_frames, wl.step), wl.n, wl.obj_shape)
+        st, nbytes = _dry(wl.n, wl.n_modes, wl.n_frames, wl.obj_shape, stack, offs)
+        assert st == 0, _lib.lib().ptycho_last_error()
+        assert nbytes > 0
+
+
+def test_plan_tables_for_awkward_shapes_and_dense_scans():
+    rng = np.random.default_rng(2)
+    cases = [(16, 1, 1, (16, 16)), (16, 2, 5, (17, 33)), (32, 1, 40, (40, 200)), (64, 3, 300, (64, 64)),
+             (128, 4, 57, (130, 700)), (512, 4, 9, (513, 1100)), (256, 3, 2000, (300, 300))]
+    for n, k, j, obj in cases:
+        offs = np.stack([rng.integers(0, obj[0] - n + 1, j), rng.integers(0, obj[1] - n + 1, j)], axis=1)
+        for stack in (0, 1, 5):
+            st, _ = _dry(n, k, j, obj, stack, offs)
+            assert st == 0, (n, k, j, obj, stack, _lib.lib().ptycho_last_error())
+    # all windows at one spot: the heaviest possible tile lists
+    offs = np.zeros((3000, 2), np.int32)
+    assert _dry(64, 1, 3000, (64, 64), 0, offs)[0] == 0
+    # out-of-bounds offsets are reported, as by ptycho_plan_create
+    assert _dry(64, 1, 1, (64, 64), 0, np.array([[1, 0]]))[0] == -2
+
+
+def test_plan_tables_for_the_large_scan():
+    import synth
+    wl = synth.workload("apdm512")
+    offs = oracle.offsets_from_positions(synth.spiral_positions(wl.n_frames, wl.step), wl.n, wl.obj_shape)
+    st, nbytes = _dry(wl.n, wl.n_modes, wl.n_frames, wl.obj_shape, 0, offs)
+    assert st == 0 and nbytes > 0
