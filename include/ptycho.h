@@ -101,8 +101,9 @@ int ptycho_workspace_bytes(const ptycho_desc_t *desc, size_t *bytes_out);
  * (mask may be NULL); the plan keeps these pointers, which must stay valid
  * for the plan's life.  workspace_dev: at least ptycho_workspace_bytes()
  * bytes, 256-byte aligned, owned by the caller, used exclusively by this
- * plan.  stream: a hipStream_t (NULL = default stream).  The call copies the
- * index tables to the workspace on `stream` and returns the handle in *out. */
+ * plan.  stream: a hipStream_t (NULL = default stream).  The call reads the
+ * mask and copies the index tables to the workspace on `stream`, waits for
+ * that stream (only), and returns the handle in *out. */
 int ptycho_plan_create(const ptycho_desc_t *desc, const int32_t *offsets_host,
                        const float *iobs_dev, const uint8_t *mask_dev,
                        void *workspace_dev, size_t workspace_bytes,

@@ -37,6 +37,30 @@ struct ColGeom {
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * CB : 1;   // one transform buffer
 };
 
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Layout of one frame-mode plane of the stack scratch: column tiles of W
+// adjacent columns, each tile holding rows 0..N-1 of its W columns (W
+// elements per row, rows consecutive).  A column block then reads and writes
+// one contiguous N*W range, and each row pass writes, for every tile, runs
+// of W elements over consecutive rows.  W = N is the row-major layout; the
+// exit waves the caller stores are always row-major.
+template <int N>
+struct ScrTile {
+    static constexpr int W = ColGeom<N>::CB < N ? ColGeom<N>::CB : N;
+    static constexpr int LW = ilog2(W);
+    static_assert((1 << LW) == W, "tile width is a power of two");
+};
+template <int N>
+__device__ __forceinline__ int scr_at(int y, int x) {
+    constexpr int W = ScrTile<N>::W;
+    return ((x / W) * N + y) * W + (x % W);
+}
+// The same with the tile width's log2 known at run time (lw = log2 N: row-major).
+__device__ __forceinline__ size_t tiled_at(int y, int x, int n, int lw) {
+    return ((size_t)((x >> lw) * n + y) << lw) + (x & ((1 << lw) - 1));
+}
+
 // Blocks are dispatched to the 8 XCDs round-robin (block i on XCD i % 8), each
 // XCD with its own L2.  This remap gives every XCD a contiguous range of
 // logical blocks, so neighbouring column blocks that share 128-byte lines
@@ -170,10 +194,10 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
 #pragma unroll
     for (int set = 0; set < SETS; ++set) {
         fft1d<N, E, -1>(u[set], t, L);
-        float2 *dst = a.scr + (((size_t)s * SETS * a.K + set * a.K + k) * N + y) * N;
+        float2 *dst = a.scr + ((size_t)s * SETS * a.K + set * a.K + k) * N * N;
         if (active) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) dst[out_index<N, E, -1>(t, e)] = u[set][e];
+            for (int e = 0; e < E; ++e) dst[scr_at<N>(y, out_index<N, E, -1>(t, e))] = u[set][e];
         }
     }
 }
@@ -196,16 +220,16 @@ __global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
     const int j = a.order[a.s0 + s];
     RowLds<N> L(lds, rr);
 
-    float2 *src = a.scr + (((size_t)s * a.K + k) * N + y) * N;
+    float2 *src = a.scr + ((size_t)s * a.K + k) * N * N;
     float2 u[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = src[in_index<N, E, +1>(t, e)];
+    for (int e = 0; e < E; ++e) u[e] = src[scr_at<N>(y, in_index<N, E, +1>(t, e))];
     const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
     fft1d<N, E, +1>(u, t, L);
     if (!active) return;
     if constexpr (MODE == OUT_SCR) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) src[out_index<N, E, +1>(t, e)] = u[e];
+        for (int e = 0; e < E; ++e) src[scr_at<N>(y, out_index<N, E, +1>(t, e))] = u[e];
     } else if constexpr (MODE == OUT_STORE) {
         float2 *dst = a.psi_out + (((size_t)j * a.K + k) * N + y) * N;
 #pragma unroll
@@ -252,9 +276,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     float2 u[K][E];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const float2 *src = a.scr + ((size_t)(s * K + k) * N) * N + c;
+        const float2 *src = a.scr + ((size_t)(s * K + k) * N) * N + scr_at<N>(0, c);
 #pragma unroll
-        for (int e = 0; e < E; ++e) u[k][e] = src[(size_t)in_index<N, E, -1>(t, e) * N];
+        for (int e = 0; e < E; ++e) u[k][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
     }
     // the data of the pixels this thread will own after the transform are
     // loaded now: loads cannot move across the transform's barriers
@@ -295,9 +319,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     if (active) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            float2 *dst = a.scr + ((size_t)(s * K + k) * N) * N + c;
+            float2 *dst = a.scr + ((size_t)(s * K + k) * N) * N + scr_at<N>(0, c);
 #pragma unroll
-            for (int e = 0; e < E; ++e) dst[(size_t)out_index<N, E, +1>(t, e) * N] = u[k][e];
+            for (int e = 0; e < E; ++e) dst[out_index<N, E, +1>(t, e) * ScrTile<N>::W] = u[k][e];
         }
     }
     if constexpr (OP == OP_GRAD) {
@@ -336,9 +360,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
         float2 u[SETS][E];
 #pragma unroll
         for (int set = 0; set < SETS; ++set) {
-            const float2 *src = a.scr + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + c;
+            const float2 *src = a.scr + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + scr_at<N>(0, c);
 #pragma unroll
-            for (int e = 0; e < E; ++e) u[set][e] = src[(size_t)in_index<N, E, -1>(t, e) * N];
+            for (int e = 0; e < E; ++e) u[set][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
         }
         fftk<N, E, -1, SETS>(u, t, Ls);
 #pragma unroll
@@ -399,6 +423,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
 // the sums are written (every tile of the object is listed).
 struct ObjTileArgs {
     int N, K, Ny, Nx, ntx;
+    int lw;                       // log2 of the exit waves' tile width (log2 N: row-major)
     const int *tiles;             // block -> tile (-1: nothing to do)
     const int *tptr;              // block -> entry range
     const int *pslot;             // block -> partial slot, -1: write the sums directly
@@ -450,11 +475,13 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
             for (int i = 0; i < PY; ++i) {
                 const int y = ty * OTILE_Y + r0 + RSTEP * i - e.y;
                 m[h][i] = (xin && (unsigned)y < (unsigned)N) ? 1.0f : 0.0f;
-                const size_t pix = (size_t)min(max(y, 0), N - 1) * N + xc;
+                const int yc = min(max(y, 0), N - 1);
+                const size_t pix = (size_t)yc * N + xc;
+                const size_t vpix = tiled_at(yc, xc, N, a.lw);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     p[h][i][k] = a.probe[k * fsz + pix];
-                    v[h][i][k] = ps[k * fsz + pix];
+                    v[h][i][k] = ps[k * fsz + vpix];
                 }
             }
         }
@@ -538,6 +565,7 @@ __global__ __launch_bounds__(256) void k_obj_chunk_reduce(const int *rtile, cons
 // plan's spatially compact one, so object rows are reused in L2.
 struct ProbeAllArgs {
     int N, K, q0, nq, Nx;
+    int lw;             // log2 of the exit waves' tile width (log2 N: row-major)
     const int2 *offs;
     const int *order;
     const float2 *obj;
@@ -554,6 +582,7 @@ __global__ __launch_bounds__(256) void k_gather_probe(ProbeAllArgs a) {
     if (idx >= N * N) return;
     const int y = idx / N, x = idx % N;
     const size_t fsz = (size_t)N * N;
+    const size_t vpix = tiled_at(y, x, N, a.lw);
     const int j0 = (int)((long)c * a.nq / C), j1 = (int)((long)(c + 1) * a.nq / C);
     float2 acc = make_float2(0.0f, 0.0f);
     float den = 0.0f;
@@ -561,7 +590,7 @@ __global__ __launch_bounds__(256) void k_gather_probe(ProbeAllArgs a) {
         const int j = a.order[a.q0 + q];
         const int2 o = a.offs[j];
         const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
-        const float2 v = ld_stream(a.psi + ((size_t)(FROM_SCR ? q : j) * a.K + k) * fsz + idx);
+        const float2 v = ld_stream(a.psi + ((size_t)(FROM_SCR ? q : j) * a.K + k) * fsz + vpix);
         const float2 cv = cmulc(ov, v);
         acc.x += cv.x;
         acc.y += cv.y;

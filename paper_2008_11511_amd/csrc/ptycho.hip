@@ -461,7 +461,10 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     long good = (long)N * N;
     if (mask) {
         std::vector<uint8_t> hm((size_t)N * N);
-        hipError_t e = hipMemcpy(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost);
+        // on the plan's stream only: a copy on the null stream would also wait
+        // for every other blocking stream's work (other plans in flight)
+        hipError_t e = hipMemcpyAsync(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
         if (e != hipSuccess) {
             delete p;
             return fail(PTYCHO_E_HIP, std::string("mask copy: ") + hipGetErrorString(e));
@@ -619,6 +622,14 @@ static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_cols_seq<N, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
 }
 
+// log2 of the tile width of exit waves at psi: the stack scratch is stored in
+// column tiles, caller-stored exit waves are row-major.
+static int psi_tile_log2(const ptycho_plan_s *p, const float2 *psi) {
+    const int n = p->d.n;
+    if (psi != p->scr) return ilog2(n);
+    return with_n(n, [&](auto nn) { return ScrTile<decltype(nn)::value>::LW; });
+}
+
 // Object sums from exit waves: over one stack from the scratch (accumulated)
 // or, with sidx < 0, over all frames from stored exit waves (written).
 template <int K>
@@ -631,6 +642,7 @@ static int object_sums(ptycho_plan_s *p, const float *probe, const float2 *psi, 
     a.Ny = p->d.obj_ny;
     a.Nx = p->d.obj_nx;
     a.ntx = p->ntx;
+    a.lw = psi_tile_log2(p, psi);
     a.tiles = p->lists + gl.blk_tile;
     a.tptr = p->lists + gl.blk_ptr;
     a.pslot = p->lists + gl.blk_slot;
@@ -672,6 +684,7 @@ static int probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, int
     a.q0 = q0;
     a.nq = nq;
     a.Nx = p->d.obj_nx;
+    a.lw = psi_tile_log2(p, psi);
     a.offs = p->offs;
     a.order = p->order;
     a.obj = (const float2 *)obj;

@@ -63,7 +63,7 @@ class Plan:
 
     def __init__(self, offsets, iobs: torch.Tensor, mask: Optional[torch.Tensor], n_modes: int,
                  obj_shape, stack: int = 0, obj_inertia: float = 1e-2, probe_inertia: float = 1e-2,
-                 icalc_floor: float = 1e-20):
+                 icalc_floor: float = 1e-20, workspace: Optional[torch.Tensor] = None):
         offs = np.ascontiguousarray(offsets, dtype=np.int32)
         if offs.ndim != 2 or offs.shape[1] != 2:
             raise ValueError("offsets must be [J][2]")
@@ -82,8 +82,14 @@ class Plan:
         nbytes = ctypes.c_size_t()
         check(lib().ptycho_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
-        # torch's caching allocator returns 512-byte aligned blocks
-        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            # torch's caching allocator returns 512-byte aligned blocks
+            workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        if (workspace.dtype != torch.uint8 or workspace.numel() < self.workspace_bytes or
+                workspace.device != self.device or workspace.data_ptr() % 256):
+            raise ValueError("workspace must be a uint8 device tensor of at least workspace_bytes, "
+                             "256-byte aligned")
+        self.workspace = workspace
         self.iobs, self.mask, self.offsets = iobs, mask, offs
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -57,18 +57,26 @@ class Scheduler:
     """Admission and progress policy over an executor.
 
     executor.footprint(req) -> bytes;  executor.start(req) -> handle;
-    executor.advance(handle) -> None (enqueue more work if the pipeline has
-    room);  executor.finished(handle) -> bool;  executor.collect(handle) ->
+    executor.advance(handle, slot) -> None (enqueue more work, in running
+    slot `slot`, if the pipeline has room);  executor.finished(handle) -> bool;  executor.collect(handle) ->
     result (host);  executor.release(handle).
     """
 
     def __init__(self, executor, hbm_budget: int, max_active: int = 8, max_backfill: int = 8,
                  sequential: bool = False, clock: Callable[[], float] = time.perf_counter,
-                 idle: Callable[[], None] = lambda: time.sleep(2e-4)):
+                 idle: Callable[[], None] = lambda: time.sleep(2e-4), max_running: Optional[int] = None,
+                 order: str = "fifo"):
+        if order not in ("fifo", "srpt"):
+            raise ValueError("order must be 'fifo' or 'srpt'")
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_active = 1 if sequential else int(max_active)
         self.max_backfill = 0 if sequential else int(max_backfill)
+        # of the admitted requests, at most max_running get new work enqueued
+        # at a time (the others hold their data resident and wait), chosen
+        # by admission order or by least remaining work
+        self.max_running = self.max_active if max_running is None else max(1, int(max_running))
+        self.order = order
         self.clock = clock
         self.idle = idle
         self.log: List[tuple] = []
@@ -94,7 +102,7 @@ class Scheduler:
             while i < len(queue) and len(active) < self.max_active:
                 r = queue[i]
                 need = self.ex.footprint(r)
-                if used + need <= self.budget:
+                if used + need <= self.budget and getattr(self.ex, "fits", lambda q: True)(r):
                     queue.pop(i)
                     r.admitted = self.clock() - t0
                     h = self.ex.start(r)
@@ -122,8 +130,11 @@ class Scheduler:
                     used -= need
                     self.log.append(("done", r.rid, r.done, used))
                     progressed = True
-                else:
-                    self.ex.advance(h)
+            running = list(active)
+            if self.order == "srpt":
+                running.sort(key=lambda e: (self.ex.remaining(e[1]), e[0].admitted, e[0].rid))
+            for slot, (r, h, need) in enumerate(running[:self.max_running]):
+                self.ex.advance(h, slot)
             if not progressed:
                 self.idle()
         return requests
@@ -141,6 +152,47 @@ def summarize(reqs: List[Request], wall: float) -> dict:
 
 
 # --------------------------------------------------------------------------
+# Device arena
+# --------------------------------------------------------------------------
+
+class Arena:
+    """First-fit allocator over one contiguous range of `size` bytes, with
+    coalescing of free neighbours (offsets only; no device calls)."""
+
+    ALIGN = 4096
+
+    def __init__(self, size: int):
+        self.size = int(size)
+        self.free = [(0, self.size)]          # sorted (offset, length)
+
+    def alloc(self, n: int) -> Optional[int]:
+        n = -(-int(n) // self.ALIGN) * self.ALIGN
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + n, ln - n)
+                return off
+        return None
+
+    def release(self, off: int, n: int) -> None:
+        n = -(-int(n) // self.ALIGN) * self.ALIGN
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+    def largest_hole(self) -> int:
+        return max((ln for _, ln in self.free), default=0)
+
+
+# --------------------------------------------------------------------------
 # GPU executor
 # --------------------------------------------------------------------------
 
@@ -149,12 +201,19 @@ class _Job:
 
 
 class GpuExecutor:
-    """Runs requests with the HIP library, one stream per active request.
+    """Runs requests with the HIP library on a fixed set of streams.
 
     Inputs of a request (truth, positions, mask, starts) are prepared on the
     host beforehand by `prepare`; at admission its data are generated on the
     device (library forward model + Poisson draw), which stands in for the
     detector stream arriving.
+
+    Streams: one for admissions (uploads, data, plan tables) and one per
+    running slot.  The device has a few hardware queues and streams beyond
+    them share one, so a stream per request would let an admission wait
+    behind the cycles already queued by a running request; with a fixed set,
+    admissions overlap the running work.  A request that moves to another
+    slot's stream is ordered after its own last enqueued work by an event.
     """
 
     def __init__(self, device="cuda:0", chunk: int = 5, depth: int = 2):
@@ -164,6 +223,8 @@ class GpuExecutor:
         self.chunk = int(chunk)
         self.depth = int(depth)
         self.host = {}
+        self.setup_stream = torch.cuda.Stream(device=self.dev)
+        self.run_streams = []
 
     # -- host preparation (outside the timed trace) -----------------------
     def prepare(self, req: Request) -> None:
@@ -182,59 +243,174 @@ class GpuExecutor:
             obj0=np.ascontiguousarray(synth.start_object(wl.obj_shape).astype(np.complex64)),
             probe0=np.ascontiguousarray(synth.start_probe(probe).astype(np.complex64)))
 
+    def close(self) -> None:
+        """Give the arena back to the device."""
+        self.pool = None
+        self.arena = None
+        self.torch.cuda.empty_cache()
+
+    def attach_arena(self, nbytes: int) -> None:
+        """Reserve the device memory the service admits requests into."""
+        torch = self.torch
+        self.pool = torch.empty(int(nbytes), dtype=torch.uint8, device=self.dev)
+        self.arena = Arena(int(nbytes))
+
     @staticmethod
-    def footprint(req: Request) -> int:
-        """Device bytes a request holds while active."""
+    def _layout(req: Request):
+        """Byte layout of one request's contiguous device region."""
         import ctypes
         from ._lib import Desc, check, lib
         wl = req.wl
         n2 = wl.n * wl.n
+        no = wl.obj_shape[0] * wl.obj_shape[1]
         d = Desc(wl.n, wl.n_modes, wl.n_frames, wl.obj_shape[0], wl.obj_shape[1], 0, 1e-2, 1e-2, 1e-20, 0)
         ws = ctypes.c_size_t()
         check(lib().ptycho_workspace_bytes(ctypes.byref(d), ctypes.byref(ws)))
+        parts = [("iobs", 4 * wl.n_frames * n2), ("psi", 8 * wl.n_frames * wl.n_modes * n2),
+                 ("ws", int(ws.value)), ("state", 0), ("obj", 8 * no), ("probe", 8 * wl.n_modes * n2),
+                 ("obj_t", 8 * no), ("probe_t", 8 * wl.n_modes * n2), ("mask", n2), ("llk", 16)]
+        return parts
+
+    @staticmethod
+    def footprint(req: Request) -> int:
+        """Device bytes a request holds while active (one contiguous region)."""
+        wl = req.wl
         no = wl.obj_shape[0] * wl.obj_shape[1]
-        iobs = 4 * wl.n_frames * n2
-        psi = 8 * wl.n_frames * wl.n_modes * n2
-        state = 8 * (2 * no + 2 * wl.n_modes * n2) + 4096
-        small = 8 * (2 * no + 2 * wl.n_modes * n2) + n2
-        return int(ws.value) + iobs + psi + state + small + iobs    # + the intensity temporary
+        n2k = wl.n_modes * wl.n * wl.n
+        state = 8 * 16 + 2 * 8 * no + 2 * 8 * n2k + 8 * 4 * 256 + 8 * 256 * 6
+        total = 0
+        for name, nb in GpuExecutor._layout(req):
+            total += (-(-(state if name == "state" else nb) // 4096)) * 4096
+        # plus the Poisson draw's temporary, which goes through torch
+        return total + 4 * wl.n_frames * wl.n * wl.n
+
+    def fits(self, req: Request) -> bool:
+        arena = getattr(self, "arena", None)
+        if arena is None:
+            return True
+        return arena.largest_hole() >= self.footprint(req) - 4 * req.wl.n_frames * req.wl.n * req.wl.n
 
     # -- device work ------------------------------------------------------
     def start(self, req: Request) -> _Job:
         torch = self.torch
         from .plan import Plan
+        t_start = time.perf_counter()
+        parts = []
+
+        def mark(label):
+            parts.append((label, time.perf_counter()))
+
         h = self.host[req.rid]
         wl = req.wl
         j = _Job()
         j.req = req
-        j.stream = torch.cuda.Stream(device=self.dev)
+        j.stream = self.setup_stream
+        n, k, jj = wl.n, wl.n_modes, wl.n_frames
+        region = None
+        if getattr(self, "arena", None) is not None:
+            size = self.footprint(req) - 4 * jj * n * n
+            off = self.arena.alloc(size)
+            if off is None:
+                raise RuntimeError("arena has no room (admission should have prevented this)")
+            j.region = (off, size)
+            region = self.pool[off:off + size]
+        else:
+            j.region = None
+
+        cursor = [0]
+
+        def carve(nbytes, dtype, shape):
+            if region is None:
+                return torch.empty(shape, dtype=dtype, device=self.dev)
+            c = cursor[0]
+            cursor[0] = c + (-(-nbytes // 4096)) * 4096
+            return region[c:c + nbytes].view(dtype).view(shape)
+
+        sizes = dict(self._layout(req))
+        mark("alloc")
+
+        def upload(dst, arr):
+            # page-locked staging, so the copy is a DMA on the request's stream
+            # and the host does not wait for it
+            dst.copy_(torch.from_numpy(arr).pin_memory(), non_blocking=True)
+
         with torch.cuda.stream(j.stream):
-            o_t = torch.from_numpy(h["obj"]).to(self.dev, non_blocking=False)
-            p_t = torch.from_numpy(h["probe"]).to(self.dev, non_blocking=False)
-            zero = torch.zeros((wl.n_frames, wl.n, wl.n), dtype=torch.float32, device=self.dev)
-            sim = Plan(h["offs"], zero, None, wl.n_modes, wl.obj_shape)
-            inten = sim.icalc(o_t, p_t)
+            j.iobs = carve(sizes["iobs"], torch.float32, (jj, n, n))
+            j.psi = carve(sizes["psi"], torch.complex64, (jj, k, n, n))
+            ws = carve(sizes["ws"], torch.uint8, (sizes["ws"],))
+            j.mask = None
+            if h["mask"] is not None:
+                j.mask = carve(sizes["mask"], torch.uint8, (n, n))
+                upload(j.mask, h["mask"])
+            o_t = carve(sizes["obj_t"], torch.complex64, wl.obj_shape)
+            p_t = carve(sizes["probe_t"], torch.complex64, (k, n, n))
+            upload(o_t, h["obj"])
+            upload(p_t, h["probe"])
+            mark("upload_truth")
+            # data: the forward model written into the data buffer, then the
+            # Poisson draw (the plan reads the buffer only from the first cycle on)
+            j.plan = Plan(h["offs"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws)
+            mark("plan")
+            j.plan.icalc(o_t, p_t, out=j.iobs)
+            mark("icalc")
             gen = torch.Generator(device=self.dev)
             gen.manual_seed(int(wl.seed))
-            j.iobs = torch.poisson(inten.clamp_min(0), generator=gen).contiguous()
-            sim.close()
-            del sim, zero, inten, o_t, p_t
-            j.mask = torch.from_numpy(h["mask"]).to(self.dev) if h["mask"] is not None else None
-            j.plan = Plan(h["offs"], j.iobs, j.mask, wl.n_modes, wl.obj_shape)
-            j.obj = torch.from_numpy(h["obj0"]).to(self.dev)
-            j.probe = torch.from_numpy(h["probe0"]).to(self.dev)
-            j.psi = j.plan.psi_init(j.obj, j.probe)
-            j.state = j.plan.ml_state()
+            j.iobs.copy_(torch.poisson(j.iobs.clamp_min_(0), generator=gen))
+            mark("poisson")
+            j.obj = carve(sizes["obj"], torch.complex64, wl.obj_shape)
+            j.probe = carve(sizes["probe"], torch.complex64, (k, n, n))
+            upload(j.obj, h["obj0"])
+            upload(j.probe, h["probe0"])
+            mark("upload_start")
+            j.plan.psi_init(j.obj, j.probe, j.psi)
+            j.state = carve(self._state_bytes(j.plan), torch.uint8, (self._state_bytes(j.plan),))
+            j.llk_buf = carve(16, torch.float64, (2,))
+            mark("psi_init")
+        # page-locked result buffers, allocated before any work is enqueued
+        j.out_obj = torch.empty(wl.obj_shape, dtype=torch.complex64, pin_memory=True)
+        j.out_probe = torch.empty((k, n, n), dtype=torch.complex64, pin_memory=True)
+        j.out_llk = torch.empty(2, dtype=torch.float64, pin_memory=True)
+        mark("pinned")
         j.phase = 0
         j.left = req.schedule[0][1]
+        j.last = torch.cuda.Event()
+        j.last.record(j.stream)
         j.events = []
         j.final = None
         j.fresh_ml = True
+        j.setup_s = time.perf_counter() - t_start
+        prev, j.setup_parts = t_start, {}
+        for label, t in parts:
+            j.setup_parts[label] = round(t - prev, 4)
+            prev = t
         return j
 
-    def advance(self, j: _Job) -> None:
+    @staticmethod
+    def _state_bytes(plan) -> int:
+        import ctypes
+        from ._lib import check, lib
+        nb = ctypes.c_size_t()
+        check(lib().ptycho_ml_state_bytes(plan._h, ctypes.byref(nb)))
+        return int(nb.value)
+
+    @staticmethod
+    def remaining(j: _Job) -> float:
+        """Work not yet enqueued, in frame-mode-pixel-cycles."""
+        wl = j.req.wl
+        cycles = j.left + sum(n for _, n in j.req.schedule[j.phase + 1:]) if j.phase < len(j.req.schedule) else 0
+        return float(wl.n_frames) * wl.n_modes * wl.n * wl.n * cycles
+
+    def advance(self, j: _Job, slot: int = 0) -> None:
         torch = self.torch
         j.events = [e for e in j.events if not e.query()]
+        if len(j.events) >= self.depth or j.phase >= len(j.req.schedule):
+            return
+        while len(self.run_streams) <= slot:
+            self.run_streams.append(torch.cuda.Stream(device=self.dev))
+        stream = self.run_streams[slot]
+        if j.stream is not stream:
+            stream.wait_event(j.last)
+            j.stream = stream
         with torch.cuda.stream(j.stream):
             while len(j.events) < self.depth and j.phase < len(j.req.schedule):
                 kind, _ = j.req.schedule[j.phase]
@@ -254,11 +430,9 @@ class GpuExecutor:
                 ev = torch.cuda.Event()
                 ev.record(j.stream)
                 j.events.append(ev)
+                j.last = ev
                 if j.phase == len(j.req.schedule):
-                    j.llk = j.plan.llk(j.obj, j.probe)
-                    j.out_obj = torch.empty(j.obj.shape, dtype=j.obj.dtype, pin_memory=True)
-                    j.out_probe = torch.empty(j.probe.shape, dtype=j.probe.dtype, pin_memory=True)
-                    j.out_llk = torch.empty(2, dtype=torch.float64, pin_memory=True)
+                    j.llk = j.plan.llk(j.obj, j.probe, out=j.llk_buf)
                     j.out_obj.copy_(j.obj, non_blocking=True)
                     j.out_probe.copy_(j.probe, non_blocking=True)
                     j.out_llk.copy_(j.llk, non_blocking=True)
@@ -270,12 +444,18 @@ class GpuExecutor:
 
     def collect(self, j: _Job) -> dict:
         llk = j.out_llk.numpy()
-        return {"obj": j.out_obj.numpy(), "probe": j.out_probe.numpy(), "llk": float(llk[0] / llk[1])}
+        return {"obj": j.out_obj.numpy(), "probe": j.out_probe.numpy(), "llk": float(llk[0] / llk[1]),
+                "setup_s": j.setup_s, "setup_parts": j.setup_parts}
 
     def release(self, j: _Job) -> None:
         j.plan.close()
-        for name in ("plan", "iobs", "mask", "obj", "probe", "psi", "state", "llk"):
+        for name in ("plan", "iobs", "mask", "obj", "probe", "psi", "state", "llk", "llk_buf"):
             setattr(j, name, None)
+        if j.region is not None:
+            # the region is reused by work enqueued after this point: every
+            # kernel of this request precedes its final event
+            j.final.synchronize()
+            self.arena.release(*j.region)
         self.host.pop(j.req.rid, None)
 
 
@@ -291,7 +471,8 @@ def make_trace(n_requests: int, rate: float, seed: int = 0, max_frames: int = 20
 
 def serve_trace(n_requests: int = 64, rate: float = 2.0, seed: int = 0, hbm_budget: Optional[int] = None,
                 max_active: int = 8, sequential: bool = False, device="cuda:0", max_frames: int = 2000,
-                sizes=(128, 256, 512), schedule=SCHEDULE, min_frames: int = 200, min_side: int = 1024):
+                sizes=(128, 256, 512), schedule=SCHEDULE, min_frames: int = 200, min_side: int = 1024,
+                max_running: Optional[int] = 1, order: str = "srpt"):
     """Run an arrival trace through the service; returns (requests, summary)."""
     import torch
     reqs = make_trace(n_requests, rate, seed, max_frames, sizes, schedule, min_frames, min_side)
@@ -301,12 +482,18 @@ def serve_trace(n_requests: int = 64, rate: float = 2.0, seed: int = 0, hbm_budg
     if hbm_budget is None:
         free, total = torch.cuda.mem_get_info(torch.device(device))
         hbm_budget = int(0.8 * free)
-    sch = Scheduler(ex, hbm_budget, max_active=max_active, sequential=sequential)
+    # the arena holds the requests' persistent buffers; the per-request
+    # Poisson temporary (counted in the footprint) stays with torch
+    ex.attach_arena(int(hbm_budget * 0.85))
+    sch = Scheduler(ex, hbm_budget, max_active=max_active, sequential=sequential, max_running=max_running,
+                    order=order)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sch.run(reqs)
     wall = time.perf_counter() - t0
     s = summarize(reqs, wall)
     s["mode"] = "sequential" if sequential else "continuous"
+    s["max_active"], s["max_running"], s["order"] = sch.max_active, sch.max_running, sch.order
     s["hbm_budget_GB"] = round(hbm_budget / 1e9, 1)
+    ex.close()
     return reqs, s

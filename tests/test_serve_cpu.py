@@ -34,7 +34,7 @@ class FakeExecutor:
         self.active[r.rid] = [r, r.wl.n_frames / 1000.0, self.clock()]
         return r.rid
 
-    def advance(self, h):
+    def advance(self, h, slot=0):
         pass
 
     def finished(self, h):
@@ -106,3 +106,82 @@ def test_backfill_admits_smaller_requests_when_the_head_is_blocked_by_memory():
     assert admits.index(2) < admits.index(1)       # small ones fill the memory left by request 0
     with pytest.raises(ValueError):
         Scheduler(ex, 100, clock=clock, idle=clock.tick).run([Request(9, 0.0, wl(900))])
+
+
+def test_arena_first_fit_and_coalescing():
+    from paper_2008_11511_amd.serve import Arena
+    a = Arena(10 * 4096)
+    x = a.alloc(3 * 4096)
+    y = a.alloc(1)                 # rounded to one page
+    z = a.alloc(4 * 4096)
+    assert (x, y, z) == (0, 3 * 4096, 4 * 4096)
+    assert a.alloc(3 * 4096) is None and a.largest_hole() == 2 * 4096
+    a.release(y, 1)
+    a.release(x, 3 * 4096)
+    assert a.largest_hole() == 4 * 4096          # x and y merged
+    a.release(z, 4 * 4096)
+    assert a.free == [(0, 10 * 4096)]
+
+
+class QuantumExecutor:
+    """Work advances only when the scheduler enqueues it: each advance()
+    completes one quantum of a request's remaining work."""
+
+    def __init__(self):
+        self.left = {}
+        self.advanced = []
+
+    def footprint(self, r):
+        return 1
+
+    def start(self, r):
+        self.left[r.rid] = r.wl.n_frames
+        return r.rid
+
+    def remaining(self, h):
+        return self.left[h]
+
+    def advance(self, h, slot=0):
+        assert slot == 0
+        self.advanced.append(h)
+        self.left[h] = max(0, self.left[h] - 100)
+
+    def finished(self, h):
+        return self.left[h] == 0
+
+    def collect(self, h):
+        return {}
+
+    def release(self, h):
+        self.left.pop(h)
+
+
+def _burst(order, max_running):
+    clock = FakeClock()
+    ex = QuantumExecutor()
+    reqs = make_trace(12, rate=1e6, seed=4, max_frames=2000)     # all present at once
+    sch = Scheduler(ex, 10**9, max_active=12, clock=clock, idle=clock.tick, order=order,
+                    max_running=max_running)
+    sch.run(reqs)
+    done = [e[1] for e in sch.log if e[0] == "done"]
+    return reqs, done, ex
+
+
+def test_srpt_running_set_finishes_shortest_first():
+    reqs, done, ex = _burst("srpt", 1)
+    frames = {r.rid: r.wl.n_frames for r in reqs}
+    # every request admitted in the first pass, so completion is by size
+    assert [frames[d] for d in done] == sorted(frames[d] for d in done)
+
+
+def test_fifo_running_set_serves_in_admission_order():
+    reqs, done, ex = _burst("fifo", 1)
+    assert done == sorted(done, key=lambda rid: next(r.admitted for r in reqs if r.rid == rid))
+    # one request's work at a time: its quanta are contiguous in the advance log
+    runs = [k for i, k in enumerate(ex.advanced) if i == 0 or ex.advanced[i - 1] != k]
+    assert len(runs) == len(set(runs)) == len(reqs)
+
+
+def test_order_argument_checked():
+    with pytest.raises(ValueError):
+        Scheduler(QuantumExecutor(), 1, order="lifo")
