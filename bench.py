@@ -89,8 +89,8 @@ def algorithmic_bytes(wl, nstacks, kind):
     if kind == "dm":
         out["rows_fwd"] = J * ((2 * K + 1) * U)              # read Psi, view; write stack
         out["cols"] = J * (2 * K * U + W)                    # read+write stack, read Iobs
-        out["rows_inv"] = J * ((2 * K + 1) * U)              # read stack and view; write Psi
-        out["gather_obj"] = J * K * U + 2 * obj_sums         # read Psi; object sums
+        out["rows_inv"] = J * ((2 * K + 2) * U)              # read stack, view; write Psi, q
+        out["gather_obj"] = J * U + 2 * obj_sums             # read q; object sums
         out["probe_all"] = J * (K * U + U)                   # read Psi and views
     return out
 
@@ -108,8 +108,8 @@ def timed_dm(plan, o, p, psi, steps, warmup, torch):
     return dt, per
 
 
-def cpu_baseline(wl, truth, sample):
-    """FP64 oracle, one DM cycle over the first `sample` frames of the scan."""
+def cpu_baseline(wl, truth, sample, cycles):
+    """FP64 oracle, `cycles` DM cycles over the first `sample` frames of the scan."""
     import oracle
     import synth
     obj_t, probe_t, pos, m = truth
@@ -121,9 +121,10 @@ def cpu_baseline(wl, truth, sample):
     p0 = synth.start_probe(probe_t)
     psi = oracle.psi_init(o0, p0, offs)
     t0 = time.perf_counter()
-    oracle.dm_cycle(o0, p0, psi, offs, iobs, m)
+    for _ in range(cycles):
+        o0, p0, psi = oracle.dm_cycle(o0, p0, psi, offs, iobs, m)
     dt = time.perf_counter() - t0
-    return sample / dt, dt
+    return sample * cycles / dt, dt
 
 
 def traffic_for(kernel, launches_per_cycle):
@@ -150,7 +151,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--ml-steps", type=int, default=10)
     ap.add_argument("--stack", type=int, default=0, help="frames per launch (0 = the library's choice)")
-    ap.add_argument("--cpu-sample", type=int, default=300, help="frames of the oracle CPU baseline sample")
+    ap.add_argument("--cpu-sample", type=int, default=1000, help="frames of the oracle CPU baseline sample")
+    ap.add_argument("--cpu-cycles", type=int, default=2, help="DM cycles of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ml", action="store_true")
     ap.add_argument("--large-cycles", default="2,5",
@@ -315,12 +317,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"CPU baseline: FP64 oracle, one DM cycle over {args.cpu_sample} frames")
-        fcs, t = cpu_baseline(wl, truth, args.cpu_sample)
+        log(f"CPU baseline: FP64 oracle, {args.cpu_cycles} DM cycles over {args.cpu_sample} frames")
+        fcs, t = cpu_baseline(wl, truth, args.cpu_sample, args.cpu_cycles)
         cores = 1
         cpu = {"value": round(fcs, 3), "unit": "frames*cycles/s", "cores": cores, "kind": "oracle",
-               "sample": f"one DM cycle over the first {args.cpu_sample} of {wl.n_frames} frames of the same "
-                         f"scan (256x256, 3 modes), {t:.1f} s; numpy FFT single-threaded",
+               "sample": f"{args.cpu_cycles} DM cycles over the first {args.cpu_sample} of {wl.n_frames} frames "
+                         f"of the same scan (256x256, 3 modes), {t:.1f} s timed; numpy FFT single-threaded",
                "host_cpus": len(os.sched_getaffinity(0))}
         log(f"CPU oracle: {fcs:.2f} frames*cycles/s ({t:.1f} s)")
 

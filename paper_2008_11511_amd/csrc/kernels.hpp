@@ -21,10 +21,17 @@ namespace ptycho {
 // ------------------------------------------------------------- geometry ---
 // Row transforms: 16 elements per thread from N = 128 up (fewer LDS passes),
 // RB rows per 256-thread block.
-template <int N>
+template <int N, int E_ = ((N >= 128 || N == 16) ? 16 : 8)>
 struct RowGeom {
-    static constexpr int E = (N >= 128 || N == 16) ? 16 : 8, T = N / E, RB = 256 / T, THREADS = 256;
+    static constexpr int E = E_, T = N / E, RB = 256 / T, THREADS = 256;
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? RB * (N + N / 16) : 1;
+};
+// The inverse row pass runs one wavefront per probe mode over the same
+// RQ rows, so that the modes of a pixel meet in one block.
+template <int N>
+struct InvRowGeom {
+    static constexpr int E = RowGeom<N>::E, T = N / E, RQ = 64 / T;
+    static constexpr int ROW_F2 = N + N / 16;        // one RowLds row
 };
 // Column transforms keep all K modes in registers at once, so they use 8
 // elements per thread (16 at N = 16), CB adjacent columns per block (a
@@ -90,7 +97,8 @@ struct StackArgs {
     const float2 *dobj, *dprobe; // line-search direction
     const float2 *psi;           // DM state read  [J][K][N][N]
     float2 *psi_out;             // DM state write [J][K][N][N]
-    float2 *scr;                 // stack scratch [S][sets*K][N][N]
+    float2 *scr;                 // stack scratch [S][sets*K][N][N] (column tiles)
+    float2 *qbuf;                // per slot sum_k conj(P_k) Psi_k, [S][N][N] row-major
     const float *iobs;           // [J][N][N]
     const unsigned char *mask;   // [N][N] or null
     float *icalc;                // [J][N][N] (icalc op)
@@ -202,48 +210,82 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     }
 }
 
-enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2 };
+enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2, OUT_NONE = 3 };
 
-// Inverse row FFT of the stack scratch and the real-space epilogue, one probe
-// mode per blockIdx.y.
-template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_rows_inv(StackArgs a) {
-    using G = RowGeom<N>;
-    constexpr int E = G::E, T = G::T, RB = G::RB;
-    __shared__ float2 lds[G::LDS_F2];
-    const int tid = threadIdx.x, rr = tid / T, t = tid % T;
-    const int k = blockIdx.y;
-    const int g = xcd_block(blockIdx.x, gridDim.x) * RB + rr;
+// Inverse row FFT of the stack scratch and the real-space epilogue.  A block
+// has one wavefront per probe mode, all on the same RQ rows.  Outputs:
+// OUT_SCR the exit waves back into the scratch, OUT_STORE into psi_out
+// [J][K][N][N], OUT_DM Phi + u into psi_out, OUT_NONE nothing.  With WQ the
+// block also writes q = sum_k conj(P_k) Psi_k (the modes summed through LDS),
+// the frame's term of the object numerator, to qbuf, so that the object
+// gather reads one plane per frame instead of K exit waves and K probe
+// values.
+template <int N, int K, int MODE, bool WQ>
+__global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
+    using G = InvRowGeom<N>;
+    constexpr int E = G::E, T = G::T, RQ = G::RQ;
+    __shared__ float2 lds[K * RQ * G::ROW_F2];
+    const int k = threadIdx.x / 64, lane = threadIdx.x % 64, rr = lane / T, t = lane % T;
+    const int g = xcd_block(blockIdx.x, gridDim.x) * RQ + rr;
     const bool active = g < a.S * N;
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, y = gg % N;
     const int j = a.order[a.s0 + s];
-    RowLds<N> L(lds, rr);
+    RowLds<N> L(lds, k * RQ + rr);
 
-    float2 *src = a.scr + ((size_t)s * a.K + k) * N * N;
+    float2 *src = a.scr + ((size_t)s * K + k) * N * N;
     float2 u[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = src[scr_at<N>(y, in_index<N, E, +1>(t, e))];
-    const size_t prow_psi = (((size_t)j * a.K + k) * N + y) * N;
     fft1d<N, E, +1>(u, t, L);
-    if (!active) return;
-    if constexpr (MODE == OUT_SCR) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) src[scr_at<N>(y, out_index<N, E, +1>(t, e))] = u[e];
-    } else if constexpr (MODE == OUT_STORE) {
-        float2 *dst = a.psi_out + (((size_t)j * a.K + k) * N + y) * N;
-#pragma unroll
-        for (int e = 0; e < E; ++e) dst[out_index<N, E, +1>(t, e)] = u[e];
-    } else {
+    const float2 *prow = a.probe + ((size_t)k * N + y) * N;
+    const size_t prow_psi = (((size_t)j * K + k) * N + y) * N;
+    size_t orow = 0;
+    if constexpr (MODE == OUT_DM) {
         const int2 o = a.offs[j];
-        const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
-        const float2 *prow = a.probe + ((size_t)k * N + y) * N;
+        orow = (size_t)(o.x + y) * a.Nx + o.y;
+    }
+    float2 qk[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int x = out_index<N, E, +1>(t, e);
-            const float2 phi = cmul(a.obj[orow + x], prow[x]);
-            a.psi_out[prow_psi + x] = make_float2(phi.x + u[e].x, phi.y + u[e].y);
+    for (int e = 0; e < E; ++e) {
+        const int x = out_index<N, E, +1>(t, e);
+        float2 v = u[e];
+        if constexpr (MODE == OUT_DM) {
+            if (active) v = cadd(cmul(a.obj[orow + x], prow[x]), v);
         }
+        if (active) {
+            if constexpr (MODE == OUT_SCR) src[scr_at<N>(y, x)] = v;
+            if constexpr (MODE == OUT_STORE || MODE == OUT_DM) a.psi_out[prow_psi + x] = v;
+        }
+        if constexpr (WQ) qk[e] = cmulc(prow[x], v);
+    }
+    if constexpr (WQ) {
+        __syncthreads();                 // the transforms' LDS reads are done
+#pragma unroll
+        for (int e = 0; e < E; ++e) L.st(out_index<N, E, +1>(t, e), qk[e]);
+        __syncthreads();
+        // wave k sums and writes the pixels of its elements e = k, k + K, ...
+        if (active) {
+            float2 *qrow = a.qbuf + ((size_t)s * N + y) * N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (e % K != k) continue;
+                const int x = out_index<N, E, +1>(t, e);
+                float2 q = RowLds<N>(lds, rr).ld(x);
+#pragma unroll
+                for (int m = 1; m < K; ++m) q = cadd(q, RowLds<N>(lds, m * RQ + rr).ld(x));
+                qrow[x] = q;
+            }
+        }
+    }
+}
+
+// sum over modes of |P_k|^2 per probe pixel (the object denominator's term)
+__global__ __launch_bounds__(256) void k_probe_intensity(const float2 *probe, int K, long n2, float *pint) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long)gridDim.x * 256) {
+        float v = 0.0f;
+        for (int k = 0; k < K; ++k) v += cnorm(probe[k * n2 + i]);
+        pint[i] = v;
     }
 }
 
@@ -416,27 +458,25 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
 // ============================================================== gathers ===
 // Object numerator/denominator by object tile: block b sums, for every pixel
 // of tile tiles[b], the frames of entries [tptr[b], tptr[b+1]) in list order;
-// each entry is (exit-wave index, oy, ox, 0), the index being the slot in the
-// stack scratch or the frame in stored exit waves [J][K][N][N].  Blocks are
-// listed with the most covering frames first, so light border tiles fill in
-// at the end.  ACCUM adds to the running sums (one stack of many), otherwise
-// the sums are written (every tile of the object is listed).
+// each entry is (slot, oy, ox, 0).  A frame adds q = sum_k conj(P_k) Psi_k
+// (from the inverse row pass) to the numerator and sum_k |P_k|^2 to the
+// denominator.  Blocks are listed with the most covering frames first, so
+// light border tiles fill in at the end; a long list is split into chunks
+// whose partial sums k_obj_chunk_reduce adds in order.
 struct ObjTileArgs {
-    int N, K, Ny, Nx, ntx;
-    int lw;                       // log2 of the exit waves' tile width (log2 N: row-major)
-    const int *tiles;             // block -> tile (-1: nothing to do)
+    int N, Ny, Nx, ntx;
+    const int *tiles;             // block -> tile
     const int *tptr;              // block -> entry range
-    const int *pslot;             // block -> partial slot, -1: write the sums directly
+    const int *pslot;             // block -> partial slot, -1: add to the sums directly
     const int4 *tent;
-    const float2 *probe;
-    const float2 *psi;
+    const float *pint;            // [N][N] sum_k |P_k|^2
+    const float2 *q;              // [S][N][N]
     float2 *numO;
     float *denO;
     float2 *pnum;                 // partial sums [slot][OTILE_Y * OTILE_X]
     float *pden;
 };
 
-template <int K, bool ACCUM>
 __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
     const int tile = a.tiles[blockIdx.x];
     const int ty = tile / a.ntx, tx = tile % a.ntx;
@@ -444,6 +484,7 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
     constexpr int RSTEP = 256 / OTILE_X;            // row phases per block
     const int px = tx * OTILE_X + col;
     constexpr int PY = OTILE_Y / RSTEP;
+    constexpr int FU = 4;                            // frames per iteration
     float2 acc[PY];
     float den[PY];
 #pragma unroll
@@ -454,53 +495,41 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
     const int N = a.N;
     const size_t fsz = (size_t)N * N;
     const int f0 = a.tptr[blockIdx.x], f1 = a.tptr[blockIdx.x + 1];
-    // Two frames per iteration: all loads of both are issued before either
-    // is summed (the per-pixel order of the sum is unchanged).  Out-of-window
-    // pixels read a clamped in-window address and are weighted 0, so the
-    // body is branch-free.
-    for (int f = f0; f < f1; f += 2) {
-        const bool two = f + 1 < f1;
-        const int4 e0 = a.tent[f];
-        const int4 e1 = two ? a.tent[f + 1] : e0;
-        float2 v[2][PY][K], p[2][PY][K];
-        float m[2][PY];
+    // FU frames per iteration: all loads are issued before any is summed
+    // (the per-pixel order of the sum is unchanged).  Out-of-window pixels
+    // and missing frames read a clamped in-window address and are weighted
+    // 0, so the body is branch-free.
+    for (int f = f0; f < f1; f += FU) {
+        float2 v[FU][PY];
+        float d[FU][PY], m[FU][PY];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int4 e = h ? e1 : e0;
+        for (int h = 0; h < FU; ++h) {
+            const bool have = f + h < f1;
+            const int4 e = a.tent[have ? f + h : f];
             const int x = px - e.z;
-            const bool xin = (unsigned)x < (unsigned)N && (h == 0 || two);
+            const bool xin = (unsigned)x < (unsigned)N && have;
             const int xc = min(max(x, 0), N - 1);
-            const float2 *ps = a.psi + (size_t)e.x * K * fsz;
+            const float2 *qs = a.q + (size_t)e.x * fsz;
 #pragma unroll
             for (int i = 0; i < PY; ++i) {
                 const int y = ty * OTILE_Y + r0 + RSTEP * i - e.y;
                 m[h][i] = (xin && (unsigned)y < (unsigned)N) ? 1.0f : 0.0f;
-                const int yc = min(max(y, 0), N - 1);
-                const size_t pix = (size_t)yc * N + xc;
-                const size_t vpix = tiled_at(yc, xc, N, a.lw);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    p[h][i][k] = a.probe[k * fsz + pix];
-                    v[h][i][k] = ps[k * fsz + vpix];
-                }
+                const size_t pix = (size_t)min(max(y, 0), N - 1) * N + xc;
+                v[h][i] = qs[pix];
+                d[h][i] = a.pint[pix];
             }
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < FU; ++h)
 #pragma unroll
-            for (int i = 0; i < PY; ++i)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float2 cv = cmulc(p[h][i][k], v[h][i][k]);
-                    acc[i].x += m[h][i] * cv.x;
-                    acc[i].y += m[h][i] * cv.y;
-                    den[i] += m[h][i] * cnorm(p[h][i][k]);
-                }
+            for (int i = 0; i < PY; ++i) {
+                acc[i].x += m[h][i] * v[h][i].x;
+                acc[i].y += m[h][i] * v[h][i].y;
+                den[i] += m[h][i] * d[h][i];
+            }
     }
     const int slot = a.pslot[blockIdx.x];
     if (slot >= 0) {
-        // a chunk of a long frame list: partial sums, added in chunk order by
-        // k_obj_chunk_reduce
 #pragma unroll
         for (int i = 0; i < PY; ++i) {
             const size_t q = (size_t)slot * (OTILE_Y * OTILE_X) + (r0 + RSTEP * i) * OTILE_X + col;
@@ -515,20 +544,15 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
         const int py = ty * OTILE_Y + r0 + RSTEP * i;
         if (py >= a.Ny) continue;
         const size_t op = (size_t)py * a.Nx + px;
-        if constexpr (ACCUM) {
-            const float2 n0 = a.numO[op];
-            a.numO[op] = make_float2(n0.x + acc[i].x, n0.y + acc[i].y);
-            a.denO[op] += den[i];
-        } else {
-            a.numO[op] = acc[i];
-            a.denO[op] = den[i];
-        }
+        const float2 n0 = a.numO[op];
+        a.numO[op] = make_float2(n0.x + acc[i].x, n0.y + acc[i].y);
+        a.denO[op] += den[i];
     }
 }
 
-// Sums of the chunk partials of split tiles: block b handles tile rtile[b]
-// whose chunks occupy partial slots rfirst[b] .. rfirst[b] + rcount[b] - 1.
-template <bool ACCUM>
+// Sums of the chunk partials of split tiles, added to the object sums: block
+// b handles tile rtile[b] whose chunks occupy partial slots rfirst[b] ..
+// rfirst[b] + rcount[b] - 1.
 __global__ __launch_bounds__(256) void k_obj_chunk_reduce(const int *rtile, const int *rfirst, const int *rcount,
                                                           const float2 *pnum, const float *pden, float2 *numO,
                                                           float *denO, int ntx, int Ny, int Nx) {
@@ -546,14 +570,9 @@ __global__ __launch_bounds__(256) void k_obj_chunk_reduce(const int *rtile, cons
         }
         if (py >= Ny || px >= Nx) continue;
         const size_t op = (size_t)py * Nx + px;
-        if constexpr (ACCUM) {
-            const float2 n0 = numO[op];
-            numO[op] = make_float2(n0.x + s.x, n0.y + s.y);
-            denO[op] += d;
-        } else {
-            numO[op] = s;
-            denO[op] = d;
-        }
+        const float2 n0 = numO[op];
+        numO[op] = make_float2(n0.x + s.x, n0.y + s.y);
+        denO[op] += d;
     }
 }
 
@@ -586,15 +605,28 @@ __global__ __launch_bounds__(256) void k_gather_probe(ProbeAllArgs a) {
     const int j0 = (int)((long)c * a.nq / C), j1 = (int)((long)(c + 1) * a.nq / C);
     float2 acc = make_float2(0.0f, 0.0f);
     float den = 0.0f;
-    for (int q = j0; q < j1; ++q) {
-        const int j = a.order[a.q0 + q];
-        const int2 o = a.offs[j];
-        const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
-        const float2 v = ld_stream(a.psi + ((size_t)(FROM_SCR ? q : j) * a.K + k) * fsz + vpix);
-        const float2 cv = cmulc(ov, v);
-        acc.x += cv.x;
-        acc.y += cv.y;
-        den += cnorm(ov);
+    // FU frames per iteration, all loads issued before the (in-order) sums;
+    // missing frames of the last group repeat frame j0 with weight 0
+    constexpr int FU = 4;
+    for (int q = j0; q < j1; q += FU) {
+        float2 ov[FU], v[FU];
+        float w[FU];
+#pragma unroll
+        for (int h = 0; h < FU; ++h) {
+            const int qq = q + h < j1 ? q + h : j0;
+            w[h] = q + h < j1 ? 1.0f : 0.0f;
+            const int j = a.order[a.q0 + qq];
+            const int2 o = a.offs[j];
+            ov[h] = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
+            v[h] = ld_stream(a.psi + ((size_t)(FROM_SCR ? qq : j) * a.K + k) * fsz + vpix);
+        }
+#pragma unroll
+        for (int h = 0; h < FU; ++h) {
+            const float2 cv = cmulc(ov[h], v[h]);
+            acc.x += w[h] * cv.x;
+            acc.y += w[h] * cv.y;
+            den += w[h] * cnorm(ov[h]);
+        }
     }
     a.part_num[((size_t)c * a.K + k) * fsz + idx] = acc;
     if (k == 0) a.part_den[(size_t)c * fsz + idx] = den;

@@ -110,7 +110,7 @@ struct Layout {
     int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
     size_t nlist_ints, npslots;   // object-gather block/reduce lists, partial slots
     size_t nent_max, nfr_max, nred;
-    size_t off_offs, off_order, off_lists, off_ent_fr, off_all_fr, off_opart, off_scr, off_numO, off_denO,
+    size_t off_offs, off_order, off_lists, off_ent_fr, off_opart, off_scr, off_q, off_pint, off_numO, off_denO,
         off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, total;
 };
 
@@ -149,11 +149,11 @@ static Layout layout_for(const ptycho_desc_t &d) {
     const long ntx = (d.obj_nx + OTILE_X - 1) / OTILE_X, nty = (d.obj_ny + OTILE_Y - 1) / OTILE_Y;
     const long ntiles = ntx * nty;
     L.nent_max = std::min((size_t)L.nstacks * ntiles, L.nfr_max);
-    // object-gather lists (all frames, and per stack): per block tile, entry
-    // range, partial slot; per split tile: tile, first slot, count
-    const size_t nb_all = (size_t)ntiles + L.nfr_max / 16 + 1;
+    // object-gather lists per stack: per block tile, entry range, partial
+    // slot (plus one end pointer per list); per split tile: tile, first
+    // slot, count
     const size_t nb_st = L.nent_max + L.nfr_max / 16 + L.nstacks;
-    L.nlist_ints = 3 * (nb_all + nb_st) + 2 + 3 * ((size_t)ntiles + L.nent_max);
+    L.nlist_ints = 3 * nb_st + 3 * L.nent_max + 2;
     L.npslots = std::min<size_t>(8192, L.nfr_max / 8 + 1);
     L.nred = std::max((size_t)L.nstacks * L.maxb, (size_t)L.nstacks_ls * L.maxb_ls * 2);
     L.pchunks = probe_chunks(d);
@@ -163,9 +163,10 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.off_order = o; o = up(o + sizeof(int) * J);
     L.off_lists = o; o = up(o + sizeof(int) * L.nlist_ints);
     L.off_ent_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
-    L.off_all_fr = o; o = up(o + sizeof(int4) * L.nfr_max);
     L.off_opart = o; o = up(o + (sizeof(float2) + sizeof(float)) * L.npslots * OTILE_Y * OTILE_X);
     L.off_scr = o; o = up(o + sizeof(float2) * (size_t)std::max(L.S, 3 * L.S_ls) * K * n2);
+    L.off_q = o; o = up(o + sizeof(float2) * (size_t)L.S * n2);
+    L.off_pint = o; o = up(o + sizeof(float) * n2);
     L.off_numO = o; o = up(o + sizeof(float2) * no);
     L.off_denO = o; o = up(o + sizeof(float) * no);
     L.off_numP = o; o = up(o + sizeof(float2) * K * n2);
@@ -200,12 +201,12 @@ struct ptycho_plan_s {
     char *ws;
     int2 *offs;
     int *order;
-    int4 *ent_fr, *all_ent;
+    int4 *ent_fr;
     int *lists;          // device copy of h_lists
     float2 *opnum;       // object-gather chunk partials
     float *opden;
-    float2 *scr, *numO, *numP, *pnum;
-    float *denO, *denP, *pden, *part;
+    float2 *scr, *q, *numO, *numP, *pnum;
+    float *pint, *denO, *denP, *pden, *part;
     double *red, *scal;
     int ntx, nty;
     long n_obs;
@@ -215,13 +216,12 @@ struct ptycho_plan_s {
     struct GatherList {
         int nb, blk_tile, blk_ptr, blk_slot, nr, red_tile, red_first, red_count;
     };
-    GatherList all_list;
     std::vector<GatherList> stack_lists;
     std::vector<int> h_lists;
     // host copies kept alive for the asynchronous uploads
     std::vector<int2> h_offs;
     std::vector<int> h_order;
-    std::vector<int4> h_fr, h_all_ent;
+    std::vector<int4> h_fr;
 };
 
 // Records an event pair around the launches made while it is alive.
@@ -319,8 +319,7 @@ static int build_host_tables(ptycho_plan_s *p, const Layout &L, const int32_t *o
     for (int j = 0; j < J; ++j) p->h_order[j] = key[j].second;
 
     // Object-gather lists: per stack, the touched object tiles with, per
-    // tile, entries (slot, oy, ox) of the covering frames in slot order; for
-    // all frames, every tile with entries (frame, oy, ox) in frame order.
+    // tile, entries (slot, oy, ox) of the covering frames in slot order.
     // Tiles with the most entries come first; a tile with more than F entries
     // (F ~ entries / 4096, at least 16) is split into chunks of at most F
     // whose partial sums a reduction adds in chunk order, so no block carries
@@ -386,23 +385,9 @@ static int build_host_tables(ptycho_plan_s *p, const Layout &L, const int32_t *o
                 }
         }
         std::sort(touched.begin(), touched.end());
-        const size_t base = p->h_fr.size();
         p->stack_lists.push_back(emit_list(touched, p->h_fr, 0));
-        (void)base;
     }
-    for (int j = 0; j < J; ++j) {
-        const int2 o = p->h_offs[j];
-        for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
-            for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx)
-                per_tile[ty * p->ntx + tx].push_back(make_int4(j, o.x, o.y, 0));
-    }
-    {
-        std::vector<int> all_tiles;
-        for (int t = 0; t < ntiles; ++t)
-            if (!per_tile[t].empty()) all_tiles.push_back(t);
-        p->all_list = emit_list(all_tiles, p->h_all_ent, 0);
-    }
-    if (p->h_fr.size() > L.nfr_max || p->h_all_ent.size() > L.nfr_max || p->h_lists.size() > L.nlist_ints ||
+    if (p->h_fr.size() > L.nfr_max || p->h_lists.size() > L.nlist_ints ||
         (size_t)max_slots > L.npslots) {
         return fail(PTYCHO_E_WORKSPACE, "internal: object-gather lists exceed their bound");
     }
@@ -436,10 +421,11 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     p->order = (int *)(p->ws + L.off_order);
     p->lists = (int *)(p->ws + L.off_lists);
     p->ent_fr = (int4 *)(p->ws + L.off_ent_fr);
-    p->all_ent = (int4 *)(p->ws + L.off_all_fr);
     p->opnum = (float2 *)(p->ws + L.off_opart);
     p->opden = (float *)(p->opnum + L.npslots * OTILE_Y * OTILE_X);
     p->scr = (float2 *)(p->ws + L.off_scr);
+    p->q = (float2 *)(p->ws + L.off_q);
+    p->pint = (float *)(p->ws + L.off_pint);
     p->numO = (float2 *)(p->ws + L.off_numO);
     p->denO = (float *)(p->ws + L.off_denO);
     p->numP = (float2 *)(p->ws + L.off_numP);
@@ -483,7 +469,6 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     if (e == hipSuccess) e = up_copy(p->order, p->h_order.data(), sizeof(int) * J);
     if (e == hipSuccess) e = up_copy(p->lists, p->h_lists.data(), sizeof(int) * p->h_lists.size());
     if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int4) * p->h_fr.size());
-    if (e == hipSuccess) e = up_copy(p->all_ent, p->h_all_ent.data(), sizeof(int4) * p->h_all_ent.size());
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         delete p;
@@ -511,7 +496,7 @@ extern "C" int ptycho_plan_dry_run(const ptycho_desc_t *d, const int32_t *offset
     p.nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
     st = build_host_tables(&p, L, offsets);
     if (st) return st;
-    *table_bytes = sizeof(int) * p.h_lists.size() + sizeof(int4) * (p.h_fr.size() + p.h_all_ent.size()) +
+    *table_bytes = sizeof(int) * p.h_lists.size() + sizeof(int4) * p.h_fr.size() +
                    sizeof(int) * p.h_order.size() + sizeof(int2) * p.h_offs.size();
     return PTYCHO_OK;
 }
@@ -585,6 +570,7 @@ static StackArgs stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, 
     a.obj = (const float2 *)obj;
     a.probe = (const float2 *)probe;
     a.scr = p->scr;
+    a.qbuf = p->q;
     a.iobs = p->iobs;
     a.mask = p->mask;
     a.eps = p->d.icalc_floor;
@@ -630,44 +616,34 @@ static int psi_tile_log2(const ptycho_plan_s *p, const float2 *psi) {
     return with_n(n, [&](auto nn) { return ScrTile<decltype(nn)::value>::LW; });
 }
 
-// Object sums from exit waves: over one stack from the scratch (accumulated)
-// or, with sidx < 0, over all frames from stored exit waves (written).
-template <int K>
-static int object_sums(ptycho_plan_s *p, const float *probe, const float2 *psi, int sidx) {
-    const ptycho_plan_s::GatherList &gl = sidx < 0 ? p->all_list : p->stack_lists[sidx];
+// Object sums of one stack, added to the running sums, from the stack's
+// per-frame numerator terms q (written by the inverse row pass) and the
+// probe intensity image.
+static int object_sums(ptycho_plan_s *p, int sidx) {
+    const ptycho_plan_s::GatherList &gl = p->stack_lists[sidx];
     if (gl.nb <= 0) return PTYCHO_OK;
     ObjTileArgs a{};
     a.N = p->d.n;
-    a.K = K;
     a.Ny = p->d.obj_ny;
     a.Nx = p->d.obj_nx;
     a.ntx = p->ntx;
-    a.lw = psi_tile_log2(p, psi);
     a.tiles = p->lists + gl.blk_tile;
     a.tptr = p->lists + gl.blk_ptr;
     a.pslot = p->lists + gl.blk_slot;
-    a.tent = sidx < 0 ? p->all_ent : p->ent_fr;
-    a.probe = (const float2 *)probe;
-    a.psi = psi;
+    a.tent = p->ent_fr;
+    a.pint = p->pint;
+    a.q = p->q;
     a.numO = p->numO;
     a.denO = p->denO;
     a.pnum = p->opnum;
     a.pden = p->opden;
     Timed tm(p, TC_GATHER_OBJ);
-    // all frames: every tile of the object that a frame covers is written
-    // (the rest were zeroed); one stack: sums are added
-    if (sidx < 0) hipLaunchKernelGGL((k_gather_obj<K, false>), dim3(gl.nb), dim3(256), 0, p->stream, a);
-    else hipLaunchKernelGGL((k_gather_obj<K, true>), dim3(gl.nb), dim3(256), 0, p->stream, a);
+    hipLaunchKernelGGL(k_gather_obj, dim3(gl.nb), dim3(256), 0, p->stream, a);
     if (gl.nr > 0) {
         const int *L0 = p->lists;
-        if (sidx < 0)
-            hipLaunchKernelGGL(k_obj_chunk_reduce<false>, dim3(gl.nr), dim3(256), 0, p->stream, L0 + gl.red_tile,
-                               L0 + gl.red_first, L0 + gl.red_count, p->opnum, p->opden, p->numO, p->denO, p->ntx,
-                               p->d.obj_ny, p->d.obj_nx);
-        else
-            hipLaunchKernelGGL(k_obj_chunk_reduce<true>, dim3(gl.nr), dim3(256), 0, p->stream, L0 + gl.red_tile,
-                               L0 + gl.red_first, L0 + gl.red_count, p->opnum, p->opden, p->numO, p->denO, p->ntx,
-                               p->d.obj_ny, p->d.obj_nx);
+        hipLaunchKernelGGL(k_obj_chunk_reduce, dim3(gl.nr), dim3(256), 0, p->stream, L0 + gl.red_tile,
+                           L0 + gl.red_first, L0 + gl.red_count, p->opnum, p->opden, p->numO, p->denO, p->ntx,
+                           p->d.obj_ny, p->d.obj_nx);
     }
     LAUNCHCHK();
     return PTYCHO_OK;
@@ -720,17 +696,33 @@ static int zero_sums(ptycho_plan_s *p, unsigned acc) {
     return st;
 }
 
+template <int N, int K, int MODE>
+static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
+    const dim3 grid((unsigned)(((long)a.S * N + InvRowGeom<N>::RQ - 1) / InvRowGeom<N>::RQ));
+    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true>), grid, dim3(64 * K), 0, s, a);
+    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false>), grid, dim3(64 * K), 0, s, a);
+}
+
 // One pass over all stacks: forward rows, column op, inverse rows and the
 // per-stack gathers.  kind: 0 = AP projection, 1 = DM, 2 = ML gradient.
 // Exit waves go to `psi` (all frames) when it is given, else stay in the
-// stack scratch.  acc selects the per-stack gathers (object; probe only for
-// the gradient, whose two sums are taken at the same point).
+// stack scratch.  acc selects the sums taken per stack: the object sums
+// (from the inverse row pass's per-frame terms), the probe sums (only for
+// the gradient, whose two sums are taken at the same point; they read the
+// exit waves from the scratch).
 template <int N, int K>
 static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind,
                         unsigned acc) {
     const int J = p->d.n_frames, S = p->L.S;
     hipStream_t s = p->stream;
     const bool store = (psi != nullptr);
+    const bool wq = (acc & ACC_OBJ) != 0;
+    if (wq) {
+        const long n2 = (long)N * N;
+        Timed tm(p, TC_GATHER_OBJ);
+        hipLaunchKernelGGL(k_probe_intensity, dim3(grid_for(n2)), dim3(256), 0, s, (const float2 *)probe, K, n2,
+                           p->pint);
+    }
     for (int sidx = 0; sidx < p->L.nstacks; ++sidx) {
         const int s0 = sidx * S, sn = std::min(S, J - s0);
         StackArgs a = stack_args(p, s0, sn, obj, probe);
@@ -751,14 +743,14 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         }
         {
             Timed tm(p, TC_ROWS_INV);
-            if (kind == 1) hipLaunchKernelGGL((k_rows_inv<N, OUT_DM>), rg, dim3(256), 0, s, a);
-            else if (store) hipLaunchKernelGGL((k_rows_inv<N, OUT_STORE>), rg, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_rows_inv<N, OUT_SCR>), rg, dim3(256), 0, s, a);
+            if (kind == 1) launch_rows_inv<N, K, OUT_DM>(a, wq, s);
+            else if (store) launch_rows_inv<N, K, OUT_STORE>(a, wq, s);
+            else if (acc & ACC_PROBE) launch_rows_inv<N, K, OUT_SCR>(a, wq, s);
+            else launch_rows_inv<N, K, OUT_NONE>(a, wq, s);
         }
         LAUNCHCHK();
-        // per-stack sums read this stack's exit waves from the scratch
         int st = PTYCHO_OK;
-        if (acc & ACC_OBJ) st = object_sums<K>(p, probe, p->scr, sidx);
+        if (acc & ACC_OBJ) st = object_sums(p, sidx);
         if (!st && (acc & ACC_PROBE)) st = probe_sums(p, obj, p->scr, s0, sn, true, true);
         if (st) return st;
     }
@@ -799,14 +791,10 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
         constexpr int N = decltype(nn)::value;
         return with_k(p->d.n_modes, [&](auto kk) {
             constexpr int K = decltype(kk)::value;
-            // with stored exit waves the object sums are taken once over all
-            // frames; without (AP, object only) per stack from the scratch
-            const bool stored = (psi != nullptr);
             for (int c = 0; c < n_cycles; ++c) {
                 int s2 = PTYCHO_OK;
                 if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
-                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, stored ? 0u : (upd & 1u));
-                if (!s2 && (upd & 1u) && stored) s2 = object_sums<K>(p, probe, (const float2 *)psi, -1);
+                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, (upd & 1u) ? ACC_OBJ : 0u);
                 if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
                 if (!s2 && (upd & 2u)) s2 = probe_sums(p, obj, (const float2 *)psi, 0, p->d.n_frames, false, false);
                 if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);
