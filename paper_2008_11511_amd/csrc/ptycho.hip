@@ -719,7 +719,7 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
     const bool wq = (acc & ACC_OBJ) != 0;
     if (wq) {
         const long n2 = (long)N * N;
-        Timed tm(p, TC_GATHER_OBJ);
+        Timed tm(p, TC_OTHER);
         hipLaunchKernelGGL(k_probe_intensity, dim3(grid_for(n2)), dim3(256), 0, s, (const float2 *)probe, K, n2,
                            p->pint);
     }
