@@ -158,8 +158,9 @@ def main():
     ap.add_argument("--large-cycles", default="2,5",
                     help="AP,DM cycles timed on the 4000 x 512^2 x 4-mode scan (the full chain is 20,50; "
                          "0,0 skips it)")
-    ap.add_argument("--serve-requests", type=int, default=16,
-                    help="requests of the served mixed workload (0 = skip; 64 = the full trace)")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the served mixed workload (0 = skip)")
+    ap.add_argument("--serve-seed", type=int, default=7, help="seed of the arrival trace")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -289,17 +290,20 @@ def main():
         torch.cuda.empty_cache()
         log(f"serving: {args.serve_requests} requests at {args.serve_rate} req/s, 30 DM + 20 ML each, "
             f"continuous batching")
-        con, s_con = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=0)
+        con, s_con = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=args.serve_seed)
         log(f"continuous: {s_con}")
         log("serving: same trace, sequential plain solves (one request resident at a time)")
-        seq, s_seq = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=0, sequential=True)
+        seq, s_seq = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=args.serve_seed,
+                                 sequential=True)
         log(f"sequential: {s_seq}")
         same = all(np.array_equal(a.result["obj"], b.result["obj"]) and
                    np.array_equal(a.result["probe"], b.result["probe"]) for a, b in zip(con, seq))
         serve = {"workload": f"{args.serve_requests} requests, Poisson arrivals at {args.serve_rate}/s, frames "
                              f"128/256/512, 200-2000 positions, 1 or 3 modes, 30 DM + 20 ML cycles each",
                  "continuous": s_con, "sequential": s_seq,
+                 "seed": args.serve_seed,
                  "p50_speedup": round(s_seq["p50_latency_s"] / s_con["p50_latency_s"], 3),
+                 "mean_speedup": round(s_seq["mean_latency_s"] / s_con["mean_latency_s"], 3),
                  "p99_speedup": round(s_seq["p99_latency_s"] / s_con["p99_latency_s"], 3),
                  "results_identical": bool(same),
                  "mean_final_llk_per_pixel": round(float(np.mean([r.result["llk"] for r in con])), 4)}

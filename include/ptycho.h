@@ -101,9 +101,10 @@ int ptycho_workspace_bytes(const ptycho_desc_t *desc, size_t *bytes_out);
  * (mask may be NULL); the plan keeps these pointers, which must stay valid
  * for the plan's life.  workspace_dev: at least ptycho_workspace_bytes()
  * bytes, 256-byte aligned, owned by the caller, used exclusively by this
- * plan.  stream: a hipStream_t (NULL = default stream).  The call reads the
- * mask and copies the index tables to the workspace on `stream`, waits for
- * that stream (only), and returns the handle in *out. */
+ * plan.  stream: a hipStream_t (NULL = default stream).  The call enqueues
+ * the upload of the index tables (the plan keeps their host copies) and the
+ * count of unmasked pixels on `stream`, returns the handle in *out, and does
+ * not wait for the stream; later calls on the plan's stream see the tables. */
 int ptycho_plan_create(const ptycho_desc_t *desc, const int32_t *offsets_host,
                        const float *iobs_dev, const uint8_t *mask_dev,
                        void *workspace_dev, size_t workspace_bytes,

@@ -280,6 +280,14 @@ __global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
     }
 }
 
+// dst = J * (number of mask pixels equal to 0); every pixel if mask is null.
+__global__ __launch_bounds__(256) void k_count_good(const unsigned char *mask, int n2, double J, double *dst) {
+    double c = 0.0;
+    for (int i = threadIdx.x; i < n2; i += 256) c += (mask == nullptr || mask[i] == 0) ? 1.0 : 0.0;
+    c = block_sum(c);
+    if (threadIdx.x == 0) dst[0] = c * J;
+}
+
 // sum over modes of |P_k|^2 per probe pixel (the object denominator's term)
 __global__ __launch_bounds__(256) void k_probe_intensity(const float2 *probe, int K, long n2, float *pint) {
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long)gridDim.x * 256) {

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -105,6 +106,7 @@ static constexpr size_t ALIGN = 256;
 static size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 static constexpr int NPART = 512;       // blocks of the max-reduction
 static constexpr int NSCAL = 64;        // device scalars
+static constexpr int SC_NOBS = 0;       //   unmasked pixels of all frames (double)
 
 struct Layout {
     int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
@@ -209,7 +211,6 @@ struct ptycho_plan_s {
     float *pint, *denO, *denP, *pden, *part;
     double *red, *scal;
     int ntx, nty;
-    long n_obs;
     // Object-gather lists.  A list is a run of blocks (tile, entry range,
     // partial slot or -1) followed by a run of reductions (split tile, first
     // slot, count), stored in h_lists; GatherList gives the offsets.
@@ -394,6 +395,81 @@ static int build_host_tables(ptycho_plan_s *p, const Layout &L, const int32_t *o
     return PTYCHO_OK;
 }
 
+// Page-locked staging of the plan tables, one buffer per process used as a
+// ring.  A copy from pageable host memory can make the host wait for the
+// stream; from the ring it is a plain asynchronous DMA.  Each use records an
+// event, and a region is reused only once the uses overlapping it are done.
+// Tables larger than the ring are copied from the plan's own host vectors.
+struct StagingRing {
+    static constexpr size_t CAP = size_t(64) << 20;
+    std::mutex m;
+    char *buf = nullptr;
+    bool failed = false;
+    size_t head = 0;
+    struct Use { size_t a, b; hipEvent_t ev; };
+    std::deque<Use> uses;
+};
+static StagingRing g_ring;
+
+struct HostPart { void *dst; const void *src; size_t bytes; };
+
+static hipError_t upload_tables(const std::vector<HostPart> &parts, hipStream_t stream) {
+    size_t total = 0;
+    for (const HostPart &h : parts) total += up(h.bytes);
+    StagingRing &r = g_ring;
+    std::lock_guard<std::mutex> lk(r.m);
+    if (!r.buf && !r.failed) {
+        if (hipHostMalloc((void **)&r.buf, StagingRing::CAP, hipHostMallocDefault) != hipSuccess) {
+            r.buf = nullptr;
+            r.failed = true;
+            (void)hipGetLastError();
+        }
+    }
+    if (!r.buf || total > StagingRing::CAP) {
+        for (const HostPart &h : parts) {
+            if (!h.bytes) continue;
+            hipError_t e = hipMemcpyAsync(h.dst, h.src, h.bytes, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    // drop finished uses; wrap; wait for the uses that overlap the region
+    while (!r.uses.empty() && hipEventQuery(r.uses.front().ev) == hipSuccess) {
+        (void)hipEventDestroy(r.uses.front().ev);
+        r.uses.pop_front();
+    }
+    if (r.head + total > StagingRing::CAP) r.head = 0;
+    const size_t a = r.head, b = r.head + total;
+    for (;;) {
+        bool overlap = false;
+        for (const StagingRing::Use &u : r.uses) overlap |= (u.a < b && a < u.b);
+        if (!overlap) break;
+        hipError_t e = hipEventSynchronize(r.uses.front().ev);
+        (void)hipEventDestroy(r.uses.front().ev);
+        r.uses.pop_front();
+        if (e != hipSuccess) return e;
+    }
+    size_t o = a;
+    for (const HostPart &h : parts) {
+        if (!h.bytes) continue;
+        std::memcpy(r.buf + o, h.src, h.bytes);
+        hipError_t e = hipMemcpyAsync(h.dst, r.buf + o, h.bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return e;
+        o += up(h.bytes);
+    }
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, stream);
+    if (e != hipSuccess) {
+        // without an event the region cannot be tracked: wait for the copies
+        (void)hipStreamSynchronize(stream);
+        return e;
+    }
+    r.uses.push_back({a, b, ev});
+    r.head = b;
+    return hipSuccess;
+}
+
 extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets, const float *iobs,
                                   const uint8_t *mask, void *ws, size_t ws_bytes, void *stream,
                                   ptycho_plan_t *out) {
@@ -444,32 +520,18 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
         delete p;
         return st;
     }
-    long good = (long)N * N;
-    if (mask) {
-        std::vector<uint8_t> hm((size_t)N * N);
-        // on the plan's stream only: a copy on the null stream would also wait
-        // for every other blocking stream's work (other plans in flight)
-        hipError_t e = hipMemcpyAsync(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost, p->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-        if (e != hipSuccess) {
-            delete p;
-            return fail(PTYCHO_E_HIP, std::string("mask copy: ") + hipGetErrorString(e));
-        }
-        good = 0;
-        for (uint8_t v : hm) good += (v == 0);
+    hipError_t e = upload_tables({{p->offs, p->h_offs.data(), sizeof(int2) * J},
+                                  {p->order, p->h_order.data(), sizeof(int) * J},
+                                  {p->lists, p->h_lists.data(), sizeof(int) * p->h_lists.size()},
+                                  {p->ent_fr, p->h_fr.data(), sizeof(int4) * p->h_fr.size()}},
+                                 p->stream);
+    if (e == hipSuccess) {
+        // number of unmasked pixels of all frames, kept on the device (the
+        // plan never waits for its stream)
+        hipLaunchKernelGGL(k_count_good, dim3(1), dim3(256), 0, p->stream, mask, N * N, (double)J,
+                           p->scal + SC_NOBS);
+        e = hipGetLastError();
     }
-    p->n_obs = good * J;
-
-    auto up_copy = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
-        if (!bytes) return hipSuccess;
-        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->stream);
-    };
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = up_copy(p->offs, p->h_offs.data(), sizeof(int2) * J);
-    if (e == hipSuccess) e = up_copy(p->order, p->h_order.data(), sizeof(int) * J);
-    if (e == hipSuccess) e = up_copy(p->lists, p->h_lists.data(), sizeof(int) * p->h_lists.size());
-    if (e == hipSuccess) e = up_copy(p->ent_fr, p->h_fr.data(), sizeof(int4) * p->h_fr.size());
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         delete p;
         return fail(PTYCHO_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
@@ -860,7 +922,7 @@ static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
 static int zero_red(ptycho_plan_s *p) { return zero_async(p->red, up(sizeof(double) * p->L.nred), p->stream); }
 
 // llk_dev[0] = sum of the reduction partials, llk_dev[1] = number of good pixels
-__global__ void k_store_count(double *dst, double v) { dst[0] = v; }
+__global__ void k_copy_scalar(double *dst, const double *src) { dst[0] = src[0]; }
 
 int ptycho_llk_into(ptycho_plan_t p, const float *obj, const float *probe, double *llk) {
     int st = zero_red(p);
@@ -868,7 +930,7 @@ int ptycho_llk_into(ptycho_plan_t p, const float *obj, const float *probe, doubl
     st = with_n(p->d.n, [&](auto nn) { return forward_pass<decltype(nn)::value, OP_LLK>(p, obj, probe, nullptr, nullptr, nullptr); });
     if (st) return st;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
-    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, p->stream, llk + 1, (double)p->n_obs);
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, p->stream, llk + 1, p->scal + SC_NOBS);
     LAUNCHCHK();
     return PTYCHO_OK;
 }
@@ -914,7 +976,7 @@ extern "C" int ptycho_ml_grad(ptycho_plan_t p, const float *obj, const float *pr
     hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(np)), dim3(256), 0, p->stream, (float2 *)g_probe, p->numP, np, 2.0f);
     if (llk) {
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
-        hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, p->stream, llk + 1, (double)p->n_obs);
+        hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, p->stream, llk + 1, p->scal + SC_NOBS);
     }
     LAUNCHCHK();
     return PTYCHO_OK;
