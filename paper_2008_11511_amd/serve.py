@@ -65,7 +65,7 @@ class Scheduler:
     def __init__(self, executor, hbm_budget: int, max_active: int = 8, max_backfill: int = 8,
                  sequential: bool = False, clock: Callable[[], float] = time.perf_counter,
                  idle: Callable[[], None] = lambda: time.sleep(2e-4), max_running: Optional[int] = None,
-                 order: str = "fifo"):
+                 order: str = "fifo", age_cap: Optional[float] = None):
         if order not in ("fifo", "srpt"):
             raise ValueError("order must be 'fifo' or 'srpt'")
         self.ex = executor
@@ -74,9 +74,13 @@ class Scheduler:
         self.max_backfill = 0 if sequential else int(max_backfill)
         # of the admitted requests, at most max_running get new work enqueued
         # at a time (the others hold their data resident and wait), chosen
-        # by admission order or by least remaining work
+        # by admission order or by least remaining work; with age_cap, a
+        # request that arrived more than age_cap seconds ago goes before all
+        # younger ones (oldest first), which bounds how long short requests
+        # can hold back a long one
         self.max_running = self.max_active if max_running is None else max(1, int(max_running))
         self.order = order
+        self.age_cap = age_cap
         self.clock = clock
         self.idle = idle
         self.log: List[tuple] = []
@@ -132,7 +136,15 @@ class Scheduler:
                     progressed = True
             running = list(active)
             if self.order == "srpt":
-                running.sort(key=lambda e: (self.ex.remaining(e[1]), e[0].admitted, e[0].rid))
+                now = self.clock() - t0
+                cap = math.inf if self.age_cap is None else self.age_cap
+
+                def key(e):
+                    r, h, _ = e
+                    if now - r.arrival > cap:
+                        return (0, r.arrival, r.rid)
+                    return (1, self.ex.remaining(h), r.admitted, r.rid)
+                running.sort(key=key)
             for slot, (r, h, need) in enumerate(running[:self.max_running]):
                 self.ex.advance(h, slot)
             if not progressed:
@@ -472,7 +484,7 @@ def make_trace(n_requests: int, rate: float, seed: int = 0, max_frames: int = 20
 def serve_trace(n_requests: int = 64, rate: float = 2.0, seed: int = 0, hbm_budget: Optional[int] = None,
                 max_active: int = 8, sequential: bool = False, device="cuda:0", max_frames: int = 2000,
                 sizes=(128, 256, 512), schedule=SCHEDULE, min_frames: int = 200, min_side: int = 1024,
-                max_running: Optional[int] = 1, order: str = "srpt"):
+                max_running: Optional[int] = 1, order: str = "srpt", age_cap: Optional[float] = 1.0):
     """Run an arrival trace through the service; returns (requests, summary)."""
     import torch
     reqs = make_trace(n_requests, rate, seed, max_frames, sizes, schedule, min_frames, min_side)
@@ -486,7 +498,7 @@ def serve_trace(n_requests: int = 64, rate: float = 2.0, seed: int = 0, hbm_budg
     # Poisson temporary (counted in the footprint) stays with torch
     ex.attach_arena(int(hbm_budget * 0.85))
     sch = Scheduler(ex, hbm_budget, max_active=max_active, sequential=sequential, max_running=max_running,
-                    order=order)
+                    order=order, age_cap=age_cap)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sch.run(reqs)
@@ -494,6 +506,7 @@ def serve_trace(n_requests: int = 64, rate: float = 2.0, seed: int = 0, hbm_budg
     s = summarize(reqs, wall)
     s["mode"] = "sequential" if sequential else "continuous"
     s["max_active"], s["max_running"], s["order"] = sch.max_active, sch.max_running, sch.order
+    s["age_cap_s"] = sch.age_cap
     s["hbm_budget_GB"] = round(hbm_budget / 1e9, 1)
     ex.close()
     return reqs, s
