@@ -44,6 +44,17 @@ struct ColGeom {
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * CB : 1;   // one transform buffer
 };
 
+// The joint column pass runs the K transforms pass by pass together (one
+// barrier pair per pass, K exchange buffers) while their buffers fit 64 KiB
+// of LDS; beyond that (512-point columns, 3-4 modes) the transforms run one
+// after the other through a single buffer, which keeps occupancy and
+// register use down.
+template <int N, int K>
+struct ColJoint {
+    static constexpr bool SEQ = (size_t)K * ColGeom<N>::LDS_F2 * 8 > 64 * 1024;
+    static constexpr int BUFS = SEQ ? 1 : K;
+};
+
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 // Layout of one frame-mode plane of the stack scratch: column tiles of W
@@ -318,9 +329,10 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, c = gg % N;
     const int j = a.order[a.s0 + s];
+    constexpr bool SEQ = ColJoint<N, K>::SEQ;
     ColLds<N, CB> L[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) L[k] = ColLds<N, CB>(lds_dyn + k * G::LDS_F2, cl);
+    for (int k = 0; k < K; ++k) L[k] = ColLds<N, CB>(lds_dyn + (SEQ ? 0 : k) * G::LDS_F2, cl);
     constexpr float inv_n2 = 1.0f / ((float)N * (float)N);
 
     float2 u[K][E];
@@ -341,7 +353,12 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
         iobv[e] = io[(size_t)q * N];
         badv[e] = a.mask != nullptr && a.mask[q * N + c] != 0;
     }
-    fftk<N, E, -1, K>(u, t, L);
+    if constexpr (SEQ) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) fft1d<N, E, -1>(u[k], t, L[k]);
+    } else {
+        fftk<N, E, -1, K>(u, t, L);
+    }
 
     double acc = 0.0;
 #pragma unroll
@@ -365,7 +382,13 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
 #pragma unroll
         for (int k = 0; k < K; ++k) u[k][e] = cscale(u[k][e], sc);
     }
-    fftk<N, E, +1, K>(u, t, L);
+    if constexpr (SEQ) {
+        __syncthreads();     // the forward transforms' last LDS reads are done
+#pragma unroll
+        for (int k = 0; k < K; ++k) fft1d<N, E, +1>(u[k], t, L[k]);
+    } else {
+        fftk<N, E, +1, K>(u, t, L);
+    }
     if (active) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -585,11 +608,12 @@ __global__ __launch_bounds__(256) void k_obj_chunk_reduce(const int *rtile, cons
 }
 
 // Probe numerator/denominator over the frames order[q0 .. q0+nq), with the
-// given object: one thread per (probe pixel, mode); the range is split into
-// gridDim.z chunks whose partial sums k_probe_reduce adds in chunk order.
-// Exit waves are read from the stack scratch by slot (FROM_SCR, slot = q -
-// q0) or from stored exit waves [J][K][N][N] by frame.  The order is the
-// plan's spatially compact one, so object rows are reused in L2.
+// given object: one thread per probe pixel, all K modes (the object value of
+// a frame is read once for the K modes); the range is split into gridDim.z
+// chunks whose partial sums k_probe_reduce adds in chunk order.  Exit waves
+// are read from the stack scratch by slot (FROM_SCR, slot = q - q0) or from
+// stored exit waves [J][K][N][N] by frame.  The order is the plan's
+// spatially compact one, so object rows are reused in L2.
 struct ProbeAllArgs {
     int N, K, q0, nq, Nx;
     int lw;             // log2 of the exit waves' tile width (log2 N: row-major)
@@ -601,43 +625,36 @@ struct ProbeAllArgs {
     float *part_den;    // [C][N*N]
 };
 
-template <bool FROM_SCR>
+template <int K, bool FROM_SCR>
 __global__ __launch_bounds__(256) void k_gather_probe(ProbeAllArgs a) {
     const int N = a.N;
     const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    const int k = blockIdx.y, c = blockIdx.z, C = gridDim.z;
+    const int c = blockIdx.z, C = gridDim.z;
     if (idx >= N * N) return;
     const int y = idx / N, x = idx % N;
     const size_t fsz = (size_t)N * N;
     const size_t vpix = tiled_at(y, x, N, a.lw);
     const int j0 = (int)((long)c * a.nq / C), j1 = (int)((long)(c + 1) * a.nq / C);
-    float2 acc = make_float2(0.0f, 0.0f);
+    float2 acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = make_float2(0.0f, 0.0f);
     float den = 0.0f;
-    // FU frames per iteration, all loads issued before the (in-order) sums;
-    // missing frames of the last group repeat frame j0 with weight 0
-    constexpr int FU = 4;
-    for (int q = j0; q < j1; q += FU) {
-        float2 ov[FU], v[FU];
-        float w[FU];
+    for (int q = j0; q < j1; ++q) {
+        const int j = a.order[a.q0 + q];
+        const int2 o = a.offs[j];
+        const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
+        const float2 *ps = a.psi + (size_t)(FROM_SCR ? q : j) * K * fsz + vpix;
 #pragma unroll
-        for (int h = 0; h < FU; ++h) {
-            const int qq = q + h < j1 ? q + h : j0;
-            w[h] = q + h < j1 ? 1.0f : 0.0f;
-            const int j = a.order[a.q0 + qq];
-            const int2 o = a.offs[j];
-            ov[h] = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
-            v[h] = ld_stream(a.psi + ((size_t)(FROM_SCR ? qq : j) * a.K + k) * fsz + vpix);
+        for (int k = 0; k < K; ++k) {
+            const float2 cv = cmulc(ov, ld_stream(ps + k * fsz));
+            acc[k].x += cv.x;
+            acc[k].y += cv.y;
         }
-#pragma unroll
-        for (int h = 0; h < FU; ++h) {
-            const float2 cv = cmulc(ov[h], v[h]);
-            acc.x += w[h] * cv.x;
-            acc.y += w[h] * cv.y;
-            den += w[h] * cnorm(ov[h]);
-        }
+        den += cnorm(ov);
     }
-    a.part_num[((size_t)c * a.K + k) * fsz + idx] = acc;
-    if (k == 0) a.part_den[(size_t)c * fsz + idx] = den;
+#pragma unroll
+    for (int k = 0; k < K; ++k) a.part_num[((size_t)c * K + k) * fsz + idx] = acc[k];
+    a.part_den[(size_t)c * fsz + idx] = den;
 }
 
 // numP, denP (=, or += with accumulate) the chunk partials in chunk order.

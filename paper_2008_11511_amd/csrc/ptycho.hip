@@ -119,7 +119,7 @@ struct Layout {
 // Frame chunks of the all-frame probe gather: enough blocks to fill the
 // chip (about 4096), never more chunks than frames.
 static int probe_chunks(const ptycho_desc_t &d) {
-    const long blocks = (long)((d.n * d.n + 255) / 256) * d.n_modes;
+    const long blocks = (long)((d.n * d.n + 255) / 256);
     long c = (4096 + blocks - 1) / blocks;
     c = std::max(1L, std::min(c, 32L));
     return (int)std::min<long>(c, d.n_frames);
@@ -657,7 +657,7 @@ static int cols_blocks(int sn) {
 
 template <int N, int K, int OP>
 static void launch_cols_joint(const StackArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * K;
+    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * ColJoint<N, K>::BUFS;
     static const hipError_t attr = set_dyn_lds(k_cols_joint<N, K, OP>, lds);
     (void)attr;
     hipLaunchKernelGGL((k_cols_joint<N, K, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
@@ -731,10 +731,14 @@ static int probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, int
     a.part_den = p->pden;
     const long n2 = (long)a.N * a.N;
     const int chunks = std::max(1, std::min(p->L.pchunks, nq));
-    dim3 grid((unsigned)((n2 + 255) / 256), a.K, chunks);
+    dim3 grid((unsigned)((n2 + 255) / 256), 1, chunks);
     Timed tm(p, from_scr ? TC_GATHER_PROBE : TC_PROBE_ALL);
-    if (from_scr) hipLaunchKernelGGL(k_gather_probe<true>, grid, dim3(256), 0, p->stream, a);
-    else hipLaunchKernelGGL(k_gather_probe<false>, grid, dim3(256), 0, p->stream, a);
+    with_k(a.K, [&](auto kk) {
+        constexpr int K = decltype(kk)::value;
+        if (from_scr) hipLaunchKernelGGL((k_gather_probe<K, true>), grid, dim3(256), 0, p->stream, a);
+        else hipLaunchKernelGGL((k_gather_probe<K, false>), grid, dim3(256), 0, p->stream, a);
+        return (int)PTYCHO_OK;
+    });
     hipLaunchKernelGGL(k_probe_reduce, dim3(grid_for(n2 * a.K)), dim3(256), 0, p->stream, p->pnum, p->pden, chunks,
                        a.K, n2, p->numP, p->denP, accumulate ? 1 : 0);
     LAUNCHCHK();
