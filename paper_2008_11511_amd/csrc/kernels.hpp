@@ -45,13 +45,13 @@ struct ColGeom {
 };
 
 // The joint column pass runs the K transforms pass by pass together (one
-// barrier pair per pass, K exchange buffers) while their buffers fit 64 KiB
-// of LDS; beyond that (512-point columns, 3-4 modes) the transforms run one
-// after the other through a single buffer, which keeps occupancy and
-// register use down.
+// barrier pair per pass, K exchange buffers) while their buffers fit 32 KiB
+// of LDS; beyond that the transforms run one after the other through a
+// single buffer: more barriers, but more blocks per CU and fewer registers
+// (measured faster at 256 points with 3 modes and at 512 points).
 template <int N, int K>
 struct ColJoint {
-    static constexpr bool SEQ = (size_t)K * ColGeom<N>::LDS_F2 * 8 > 64 * 1024;
+    static constexpr bool SEQ = (size_t)K * ColGeom<N>::LDS_F2 * 8 > 32 * 1024;
     static constexpr int BUFS = SEQ ? 1 : K;
 };
 

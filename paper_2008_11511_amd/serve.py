@@ -34,15 +34,26 @@ SCHEDULE = (("dm", 30), ("ml", 20))
 
 
 @dataclasses.dataclass
+class Scan:
+    """Sizes of a caller-supplied reconstruction (the fields the service needs)."""
+    n: int
+    n_modes: int
+    n_frames: int
+    obj_shape: tuple
+
+
+@dataclasses.dataclass
 class Request:
     rid: int
-    arrival: float                   # seconds after the start of the trace
-    wl: object                       # synth.Workload
+    arrival: float                   # seconds after the start of the loop
+    wl: object                       # synth.Workload (synthetic data) or Scan
     schedule: tuple = SCHEDULE
+    data: Optional[dict] = None      # caller data: iobs, offsets, mask, obj0, probe0
     # filled by the scheduler
     admitted: Optional[float] = None
     done: Optional[float] = None
     result: Optional[dict] = None
+    error: Optional[BaseException] = None
 
     @property
     def latency(self) -> float:
@@ -86,20 +97,40 @@ class Scheduler:
         self.log: List[tuple] = []
 
     def run(self, requests: List[Request]) -> List[Request]:
+        """Serve a trace: each request is submitted at its arrival time."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in pending:
-            if self.ex.footprint(r) > self.budget:
-                raise ValueError(f"request {r.rid} needs {self.ex.footprint(r)} bytes, more than the budget "
-                                 f"{self.budget}")
+            self.check(r)
+
+        def poll(now):
+            out = []
+            while pending and pending[0].arrival <= now:
+                out.append(pending.pop(0))
+            return out
+
+        self.loop(poll, lambda: bool(pending))
+        return requests
+
+    def check(self, r: Request) -> None:
+        if self.ex.footprint(r) > self.budget:
+            raise ValueError(f"request {r.rid} needs {self.ex.footprint(r)} bytes, more than the budget "
+                             f"{self.budget}")
+
+    def loop(self, poll: Callable[[float], List[Request]], more: Callable[[], bool],
+             on_done: Optional[Callable[[Request], None]] = None) -> None:
+        """Run until `more()` is false and every request is done.  poll(now)
+        returns the requests that arrived since the last call (arrival times
+        on the loop's clock, seconds since `self.t0`)."""
         queue: List[Request] = []
         active = []                  # (req, handle, bytes)
         used = 0
-        t0 = self.clock()
+        t0 = self.t0 = self.clock()
         skips = 0
-        while pending or queue or active:
+        while True:
             now = self.clock() - t0
-            while pending and pending[0].arrival <= now:
-                queue.append(pending.pop(0))
+            queue.extend(poll(now))
+            if not (queue or active or more()):
+                break
             # admission: FIFO; when the head is blocked by memory only, later
             # requests that fit may go first, at most max_backfill times
             i = 0
@@ -109,7 +140,15 @@ class Scheduler:
                 if used + need <= self.budget and getattr(self.ex, "fits", lambda q: True)(r):
                     queue.pop(i)
                     r.admitted = self.clock() - t0
-                    h = self.ex.start(r)
+                    try:
+                        h = self.ex.start(r)
+                    except Exception as e:          # this request fails, the others go on
+                        r.error = e
+                        r.done = self.clock() - t0
+                        self.log.append(("error", r.rid, r.done, used))
+                        if on_done is not None:
+                            on_done(r)
+                        continue
                     active.append((r, h, need))
                     used += need
                     self.log.append(("admit", r.rid, r.admitted, used))
@@ -134,6 +173,8 @@ class Scheduler:
                     used -= need
                     self.log.append(("done", r.rid, r.done, used))
                     progressed = True
+                    if on_done is not None:
+                        on_done(r)
             running = list(active)
             if self.order == "srpt":
                 now = self.clock() - t0
@@ -149,7 +190,6 @@ class Scheduler:
                 self.ex.advance(h, slot)
             if not progressed:
                 self.idle()
-        return requests
 
 
 def summarize(reqs: List[Request], wall: float) -> dict:
@@ -278,9 +318,12 @@ class GpuExecutor:
         d = Desc(wl.n, wl.n_modes, wl.n_frames, wl.obj_shape[0], wl.obj_shape[1], 0, 1e-2, 1e-2, 1e-20, 0)
         ws = ctypes.c_size_t()
         check(lib().ptycho_workspace_bytes(ctypes.byref(d), ctypes.byref(ws)))
+        synthetic = req.data is None
+        n_ml = sum(c for kind, c in req.schedule if kind == "ml")
         parts = [("iobs", 4 * wl.n_frames * n2), ("psi", 8 * wl.n_frames * wl.n_modes * n2),
                  ("ws", int(ws.value)), ("state", 0), ("obj", 8 * no), ("probe", 8 * wl.n_modes * n2),
-                 ("obj_t", 8 * no), ("probe_t", 8 * wl.n_modes * n2), ("mask", n2), ("llk", 16)]
+                 ("obj_t", 8 * no if synthetic else 0), ("probe_t", 8 * wl.n_modes * n2 if synthetic else 0),
+                 ("mask", n2), ("llk", 16), ("hist", 8 * max(n_ml, 1))]
         return parts
 
     @staticmethod
@@ -294,13 +337,18 @@ class GpuExecutor:
         for name, nb in GpuExecutor._layout(req):
             total += (-(-(state if name == "state" else nb) // 4096)) * 4096
         # plus the Poisson draw's temporary, which goes through torch
-        return total + 4 * wl.n_frames * wl.n * wl.n
+        return total + GpuExecutor._temp_bytes(req)
+
+    @staticmethod
+    def _temp_bytes(req: Request) -> int:
+        wl = req.wl
+        return 4 * wl.n_frames * wl.n * wl.n if req.data is None else 0
 
     def fits(self, req: Request) -> bool:
         arena = getattr(self, "arena", None)
         if arena is None:
             return True
-        return arena.largest_hole() >= self.footprint(req) - 4 * req.wl.n_frames * req.wl.n * req.wl.n
+        return arena.largest_hole() >= self.footprint(req) - self._temp_bytes(req)
 
     # -- device work ------------------------------------------------------
     def start(self, req: Request) -> _Job:
@@ -312,7 +360,7 @@ class GpuExecutor:
         def mark(label):
             parts.append((label, time.perf_counter()))
 
-        h = self.host[req.rid]
+        h = self.host[req.rid] if req.data is None else req.data
         wl = req.wl
         j = _Job()
         j.req = req
@@ -320,7 +368,7 @@ class GpuExecutor:
         n, k, jj = wl.n, wl.n_modes, wl.n_frames
         region = None
         if getattr(self, "arena", None) is not None:
-            size = self.footprint(req) - 4 * jj * n * n
+            size = self.footprint(req) - self._temp_bytes(req)
             off = self.arena.alloc(size)
             if off is None:
                 raise RuntimeError("arena has no room (admission should have prevented this)")
@@ -341,50 +389,33 @@ class GpuExecutor:
         sizes = dict(self._layout(req))
         mark("alloc")
 
-        def upload(dst, arr):
-            # page-locked staging, so the copy is a DMA on the request's stream
+        def upload(dst, x):
+            # device tensors are copied on the request's stream; host arrays go
+            # through page-locked staging, so the copy is a DMA on that stream
             # and the host does not wait for it
-            dst.copy_(torch.from_numpy(arr).pin_memory(), non_blocking=True)
+            if isinstance(x, torch.Tensor) and x.is_cuda:
+                dst.copy_(x, non_blocking=True)
+                return
+            t = x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x))
+            dst.copy_(t.pin_memory(), non_blocking=True)
 
-        with torch.cuda.stream(j.stream):
-            j.iobs = carve(sizes["iobs"], torch.float32, (jj, n, n))
-            j.psi = carve(sizes["psi"], torch.complex64, (jj, k, n, n))
-            ws = carve(sizes["ws"], torch.uint8, (sizes["ws"],))
-            j.mask = None
-            if h["mask"] is not None:
-                j.mask = carve(sizes["mask"], torch.uint8, (n, n))
-                upload(j.mask, h["mask"])
-            o_t = carve(sizes["obj_t"], torch.complex64, wl.obj_shape)
-            p_t = carve(sizes["probe_t"], torch.complex64, (k, n, n))
-            upload(o_t, h["obj"])
-            upload(p_t, h["probe"])
-            mark("upload_truth")
-            # data: the forward model written into the data buffer, then the
-            # Poisson draw (the plan reads the buffer only from the first cycle on)
-            j.plan = Plan(h["offs"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws)
-            mark("plan")
-            j.plan.icalc(o_t, p_t, out=j.iobs)
-            mark("icalc")
-            gen = torch.Generator(device=self.dev)
-            gen.manual_seed(int(wl.seed))
-            j.iobs.copy_(torch.poisson(j.iobs.clamp_min_(0), generator=gen))
-            mark("poisson")
-            j.obj = carve(sizes["obj"], torch.complex64, wl.obj_shape)
-            j.probe = carve(sizes["probe"], torch.complex64, (k, n, n))
-            upload(j.obj, h["obj0"])
-            upload(j.probe, h["probe0"])
-            mark("upload_start")
-            j.plan.psi_init(j.obj, j.probe, j.psi)
-            j.state = carve(self._state_bytes(j.plan), torch.uint8, (self._state_bytes(j.plan),))
-            j.llk_buf = carve(16, torch.float64, (2,))
-            mark("psi_init")
+        try:
+            self._start_on_stream(req, j, h, carve, sizes, upload, mark)
+        except BaseException:
+            j.plan = None
+            if j.region is not None:
+                j.stream.synchronize()
+                self.arena.release(*j.region)
+            raise
         # page-locked result buffers, allocated before any work is enqueued
         j.out_obj = torch.empty(wl.obj_shape, dtype=torch.complex64, pin_memory=True)
         j.out_probe = torch.empty((k, n, n), dtype=torch.complex64, pin_memory=True)
         j.out_llk = torch.empty(2, dtype=torch.float64, pin_memory=True)
+        j.out_hist = torch.empty(j.hist.shape, dtype=torch.float64, pin_memory=True)
         mark("pinned")
         j.phase = 0
         j.left = req.schedule[0][1]
+        j.ml_done = 0
         j.last = torch.cuda.Event()
         j.last.record(j.stream)
         j.events = []
@@ -396,6 +427,54 @@ class GpuExecutor:
             j.setup_parts[label] = round(t - prev, 4)
             prev = t
         return j
+
+    def _start_on_stream(self, req, j, h, carve, sizes, upload, mark):
+        """Device buffers, data and plan of one request, enqueued on j.stream."""
+        torch = self.torch
+        from .plan import Plan
+        wl = req.wl
+        n, k, jj = wl.n, wl.n_modes, wl.n_frames
+        with torch.cuda.stream(j.stream):
+            j.iobs = carve(sizes["iobs"], torch.float32, (jj, n, n))
+            j.psi = carve(sizes["psi"], torch.complex64, (jj, k, n, n))
+            ws = carve(sizes["ws"], torch.uint8, (sizes["ws"],))
+            j.mask = None
+            if h.get("mask") is not None:
+                j.mask = carve(sizes["mask"], torch.uint8, (n, n))
+                upload(j.mask, h["mask"])
+            if req.data is None:
+                o_t = carve(sizes["obj_t"], torch.complex64, wl.obj_shape)
+                p_t = carve(sizes["probe_t"], torch.complex64, (k, n, n))
+                upload(o_t, h["obj"])
+                upload(p_t, h["probe"])
+                mark("upload_truth")
+                # data: the forward model written into the data buffer, then the
+                # Poisson draw (the plan reads the buffer only from the first cycle on)
+                j.plan = Plan(h["offs"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws)
+                mark("plan")
+                j.plan.icalc(o_t, p_t, out=j.iobs)
+                mark("icalc")
+                gen = torch.Generator(device=self.dev)
+                gen.manual_seed(int(wl.seed))
+                j.iobs.copy_(torch.poisson(j.iobs.clamp_min_(0), generator=gen))
+                mark("poisson")
+            else:
+                if h.get("ready") is not None:
+                    j.stream.wait_event(h["ready"])
+                upload(j.iobs, h["iobs"])
+                mark("upload_data")
+                j.plan = Plan(h["offsets"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws)
+                mark("plan")
+            j.obj = carve(sizes["obj"], torch.complex64, wl.obj_shape)
+            j.probe = carve(sizes["probe"], torch.complex64, (k, n, n))
+            upload(j.obj, h["obj0"])
+            upload(j.probe, h["probe0"])
+            mark("upload_start")
+            j.plan.psi_init(j.obj, j.probe, j.psi)
+            j.state = carve(self._state_bytes(j.plan), torch.uint8, (self._state_bytes(j.plan),))
+            j.llk_buf = carve(16, torch.float64, (2,))
+            j.hist = carve(sizes["hist"], torch.float64, (sizes["hist"] // 8,))
+            mark("psi_init")
 
     @staticmethod
     def _state_bytes(plan) -> int:
@@ -432,7 +511,9 @@ class GpuExecutor:
                 elif kind == "ap":
                     j.plan.ap_cycle(j.obj, j.probe, n, 3, psi=j.psi)
                 else:
-                    j.plan.ml_cycle(j.obj, j.probe, j.state, n, 3, reset=j.fresh_ml)
+                    j.plan.ml_cycle(j.obj, j.probe, j.state, n, 3, reset=j.fresh_ml,
+                                    hist=j.hist[j.ml_done:j.ml_done + n])
+                    j.ml_done += n
                     j.fresh_ml = False
                 j.left -= n
                 if j.left == 0:
@@ -448,6 +529,7 @@ class GpuExecutor:
                     j.out_obj.copy_(j.obj, non_blocking=True)
                     j.out_probe.copy_(j.probe, non_blocking=True)
                     j.out_llk.copy_(j.llk, non_blocking=True)
+                    j.out_hist.copy_(j.hist, non_blocking=True)
                     j.final = torch.cuda.Event()
                     j.final.record(j.stream)
 
@@ -455,13 +537,16 @@ class GpuExecutor:
         return j.final is not None and j.final.query()
 
     def collect(self, j: _Job) -> dict:
+        """Host results: final object and probe, LLK per unmasked pixel after
+        the last cycle and after each ML cycle, and set-up timing."""
         llk = j.out_llk.numpy()
+        hist = j.out_hist.numpy()[:j.ml_done] / llk[1]
         return {"obj": j.out_obj.numpy(), "probe": j.out_probe.numpy(), "llk": float(llk[0] / llk[1]),
-                "setup_s": j.setup_s, "setup_parts": j.setup_parts}
+                "llk_history": hist, "setup_s": j.setup_s, "setup_parts": j.setup_parts}
 
     def release(self, j: _Job) -> None:
         j.plan.close()
-        for name in ("plan", "iobs", "mask", "obj", "probe", "psi", "state", "llk", "llk_buf"):
+        for name in ("plan", "iobs", "mask", "obj", "probe", "psi", "state", "llk", "llk_buf", "hist"):
             setattr(j, name, None)
         if j.region is not None:
             # the region is reused by work enqueued after this point: every
@@ -469,6 +554,139 @@ class GpuExecutor:
             j.final.synchronize()
             self.arena.release(*j.region)
         self.host.pop(j.req.rid, None)
+
+
+class ReconstructionService:
+    """On-line service: reconstructions submitted from any thread are served
+    by one loop thread with the policy above; `submit` returns a future.
+
+        with ReconstructionService() as svc:
+            fut = svc.submit(iobs, offsets, obj0, probe0, mask)
+            res = fut.result()     # obj, probe, llk, llk_history, timings
+
+    Inputs (numpy arrays or torch tensors, host or device): iobs float32
+    [J][N][N] in FFT order, offsets int32 [J][2] window corners, obj0
+    complex64 [Ny][Nx] and probe0 complex64 [K][N][N] starting guesses, mask
+    uint8 [N][N] (1 = bad pixel) or None.  The arrays must not change until
+    the future is done.  A request whose offsets leave the object, or that
+    needs more memory than the budget, is refused in `submit`.
+    """
+
+    def __init__(self, device="cuda:0", hbm_budget: Optional[int] = None, max_active: int = 8,
+                 max_running: int = 1, order: str = "srpt", age_cap: Optional[float] = 1.0,
+                 chunk: int = 5):
+        import itertools
+        import queue
+        import threading
+        import torch
+        from ._lib import lib
+        lib()
+        self.ex = GpuExecutor(device, chunk=chunk)
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(torch.device(device))
+            hbm_budget = int(0.8 * free)
+        self.ex.attach_arena(int(hbm_budget))
+        self.sch = Scheduler(self.ex, hbm_budget, max_active=max_active, max_running=max_running, order=order,
+                             age_cap=age_cap)
+        self._in = queue.SimpleQueue()
+        self._empty = queue.Empty
+        self._closed = threading.Event()
+        self._ids = itertools.count()
+        self._futures = {}
+        self._lock = threading.Lock()
+        self._started = threading.Event()
+        self._thread = threading.Thread(target=self._run, name="ptycho-serve", daemon=True)
+        self._thread.start()
+        self._started.wait()
+
+    def submit(self, iobs, offsets, obj0, probe0, mask=None, schedule=SCHEDULE):
+        import ctypes
+        from concurrent.futures import Future
+        import torch
+        from ._lib import Desc, check, lib
+        if self._closed.is_set():
+            raise RuntimeError("the service is closed")
+        offs = np.ascontiguousarray(offsets, dtype=np.int32)
+        if iobs.ndim != 3 or iobs.shape[1] != iobs.shape[2]:
+            raise ValueError("iobs must be [J][N][N]")
+        jj, n = int(iobs.shape[0]), int(iobs.shape[1])
+        if offs.shape != (jj, 2):
+            raise ValueError("offsets must be [J][2]")
+        if probe0.ndim != 3 or tuple(probe0.shape[1:]) != (n, n):
+            raise ValueError("probe0 must be [K][N][N]")
+        if obj0.ndim != 2:
+            raise ValueError("obj0 must be [Ny][Nx]")
+        if mask is not None and tuple(mask.shape) != (n, n):
+            raise ValueError("mask must be [N][N]")
+        for kind, cycles in schedule:
+            if kind not in ("ap", "dm", "ml") or int(cycles) <= 0:
+                raise ValueError(f"bad schedule entry {(kind, cycles)}")
+        scan = Scan(n, int(probe0.shape[0]), jj, (int(obj0.shape[0]), int(obj0.shape[1])))
+        # sizes and window bounds checked by the library, without GPU work
+        d = Desc(n, scan.n_modes, jj, scan.obj_shape[0], scan.obj_shape[1], 0, 1e-2, 1e-2, 1e-20, 0)
+        tb = ctypes.c_size_t()
+        check(lib().ptycho_plan_dry_run(ctypes.byref(d), offs.ctypes.data, ctypes.byref(tb)))
+        ready = None
+        if any(isinstance(x, torch.Tensor) and x.is_cuda for x in (iobs, obj0, probe0, mask)):
+            # device inputs: the uploads wait for the caller's stream
+            ready = torch.cuda.Event()
+            ready.record(torch.cuda.current_stream(self.ex.dev))
+        r = Request(next(self._ids), 0.0, scan, tuple((k, int(c)) for k, c in schedule),
+                    data=dict(iobs=iobs, offsets=offs, obj0=obj0, probe0=probe0, mask=mask, ready=ready))
+        self.sch.check(r)
+        fut = Future()
+        with self._lock:
+            self._futures[r.rid] = fut
+        self._in.put((r, time.perf_counter()))
+        return fut
+
+    def _run(self):
+        def poll(now):
+            out = []
+            while True:
+                try:
+                    r, t = self._in.get_nowait()
+                except self._empty:
+                    return out
+                r.arrival = max(0.0, t - self.sch.t0)
+                out.append(r)
+
+        def done(r):
+            with self._lock:
+                fut = self._futures.pop(r.rid)
+            if r.error is not None:
+                fut.set_exception(r.error)
+                return
+            res = dict(r.result)
+            res["timings"] = {"queued_s": r.admitted - r.arrival, "service_s": r.done - r.admitted,
+                              "latency_s": r.done - r.arrival, "setup_s": res.pop("setup_s")}
+            res.pop("setup_parts", None)
+            fut.set_result(res)
+
+        self.sch.t0 = time.perf_counter()
+        self._started.set()
+        err = None
+        try:
+            self.sch.loop(poll, lambda: not self._closed.is_set(), done)
+        except BaseException as e:             # the loop itself failed: fail what is left
+            err = e
+        self._closed.set()
+        with self._lock:
+            left, self._futures = self._futures, {}
+        for fut in left.values():
+            fut.set_exception(err if err is not None else RuntimeError("the service closed first"))
+
+    def close(self) -> None:
+        """Finish the submitted requests, stop the loop and free the arena."""
+        self._closed.set()
+        self._thread.join()
+        self.ex.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def make_trace(n_requests: int, rate: float, seed: int = 0, max_frames: int = 2000, sizes=(128, 256, 512),

@@ -34,3 +34,95 @@ def test_results_identical_alone_and_in_the_mix():
         assert np.array_equal(a.result["probe"], b.result["probe"])
         assert a.result["llk"] == b.result["llk"]
         assert np.isfinite(a.result["llk"])
+
+
+def _scan(seed, n, k, j, side, mask_frac):
+    """A small caller-side reconstruction problem: data from the oracle's
+    forward model and a Poisson draw, starts as in the benchmarks."""
+    import oracle
+    import synth
+    obj = synth.object_truth((side, side), seed)
+    probe = synth.probe_modes(n, k, seed)
+    offs = oracle.offsets_from_positions(synth.spiral_positions(j, n / 10.0), n, (side, side))
+    probe = probe * synth.probe_photon_scale(obj, probe, offs, 1e6)
+    iobs = synth.poisson_counts(oracle.simulate_intensity(obj, probe, offs), seed).astype(np.float32)
+    mask = synth.gap_mask(n, mask_frac, seed)
+    obj0 = synth.perturb_object(obj, seed).astype(np.complex64)
+    probe0 = synth.perturb_probe(probe, seed).astype(np.complex64)
+    return dict(iobs=iobs, offsets=offs.astype(np.int32), obj0=obj0, probe0=probe0, mask=mask)
+
+
+SCHED = (("dm", 4), ("ml", 3))
+
+
+def _direct(sc, dev):
+    """The same schedule run directly on a plan."""
+    from paper_2008_11511_amd import Plan
+    iobs = torch.from_numpy(sc["iobs"]).to(dev)
+    mask = torch.from_numpy(sc["mask"]).to(dev) if sc["mask"] is not None else None
+    o = torch.from_numpy(sc["obj0"]).to(dev)
+    p = torch.from_numpy(sc["probe0"]).to(dev)
+    plan = Plan(sc["offsets"], iobs, mask, p.shape[0], tuple(o.shape))
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 4, 3)
+    st = plan.ml_state()
+    hist = torch.zeros(3, dtype=torch.float64, device=dev)
+    plan.ml_cycle(o, p, st, 3, 3, reset=True, hist=hist)
+    llk = plan.llk(o, p)
+    torch.cuda.synchronize()
+    l = llk.cpu().numpy()
+    return o.cpu().numpy(), p.cpu().numpy(), l[0] / l[1], hist.cpu().numpy() / l[1]
+
+
+def test_service_results_equal_direct_runs_and_a_low_budget_queues_requests():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_11511_amd import lib
+    from paper_2008_11511_amd.serve import ReconstructionService
+    lib()
+    dev = torch.device("cuda:0")
+    say("service: three caller-supplied scans")
+    scans = [_scan(31, 64, 1, 80, 256, 0.0), _scan(32, 128, 2, 60, 384, 0.03), _scan(33, 64, 3, 100, 288, 0.03)]
+    ref = [_direct(sc, dev) for sc in scans]
+    for budget in (None, "low"):
+        kw = {}
+        if budget == "low":
+            # room for one request at a time: the others wait for memory
+            from paper_2008_11511_amd.serve import GpuExecutor, Request, Scan
+            need = max(GpuExecutor.footprint(Request(0, 0.0, Scan(s["iobs"].shape[1], s["probe0"].shape[0],
+                                                                  s["iobs"].shape[0], s["obj0"].shape),
+                                                     SCHED, data={})) for s in scans)
+            kw = dict(hbm_budget=int(need * 1.3))
+        say(f"service: budget {budget}")
+        with ReconstructionService(**kw) as svc:
+            futs = []
+            for i, sc in enumerate(scans):
+                args = dict(sc)
+                if i == 1:             # device inputs are accepted too
+                    args["iobs"] = torch.from_numpy(sc["iobs"]).to(dev)
+                futs.append(svc.submit(schedule=SCHED, **args))
+            res = [f.result(timeout=120) for f in futs]
+            if budget == "low":
+                admits = [e for e in svc.sch.log if e[0] == "admit"]
+                assert max(e[3] for e in admits) <= int(need * 1.3)
+        for r, (o, p, llk, hist) in zip(res, ref):
+            assert np.array_equal(r["obj"], o)
+            assert np.array_equal(r["probe"], p)
+            assert r["llk"] == llk
+            np.testing.assert_array_equal(r["llk_history"], hist)
+            assert r["timings"]["latency_s"] >= r["timings"]["service_s"] > 0
+
+
+def test_service_refuses_a_scan_outside_the_object():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_11511_amd import PtychoError, lib
+    from paper_2008_11511_amd.serve import ReconstructionService
+    lib()
+    sc = _scan(34, 64, 1, 20, 256, 0.0)
+    sc["offsets"] = sc["offsets"].copy()
+    sc["offsets"][5] = (250, 0)                    # window leaves the 256 x 256 object
+    with ReconstructionService() as svc:
+        with pytest.raises(PtychoError) as e:
+            svc.submit(schedule=SCHED, **sc)
+        assert e.value.code == -2

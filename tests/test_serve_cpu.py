@@ -219,3 +219,32 @@ def test_age_cap_puts_an_old_request_ahead_of_shorter_ones():
     assert capped[0] < 0.8 < srpt[0]
     # the short ones still go first until the cap is reached
     assert capped[1] < 0.1
+
+
+class FailingExecutor(QuantumExecutor):
+    def start(self, r):
+        if r.rid == 3:
+            raise ValueError("bad request")
+        return super().start(r)
+
+
+def test_loop_reports_each_request_once_and_isolates_a_failing_start():
+    clock = FakeClock()
+    ex = FailingExecutor()
+    reqs = make_trace(8, rate=50.0, seed=6, max_frames=800)
+    pending = sorted(reqs, key=lambda r: r.arrival)
+    done = []
+
+    def poll(now):
+        out = []
+        while pending and pending[0].arrival <= now:
+            out.append(pending.pop(0))
+        return out
+
+    sch = Scheduler(ex, 10**9, max_active=4, clock=clock, idle=clock.tick, order="srpt", max_running=1)
+    sch.loop(poll, lambda: bool(pending), done.append)
+    assert sorted(r.rid for r in done) == list(range(8))
+    bad = [r for r in done if r.error is not None]
+    assert [r.rid for r in bad] == [3] and isinstance(bad[0].error, ValueError)
+    assert all(r.result is not None for r in done if r.rid != 3)
+    assert not ex.left                                    # every started request was released
