@@ -40,7 +40,7 @@ __all__ = [
     "fft2", "ifft2", "offsets_from_positions", "views", "exit_waves",
     "calc_intensity", "project_modulus", "fourier_project", "overlap_sums",
     "overlap_denominators", "overlap_update", "ap_cycle", "dm_cycle",
-    "psi_init", "llk", "llk_terms", "ml_grad", "linesearch_coefs",
+    "psi_init", "llk", "llk_terms", "llk_model_terms", "LLK_MODELS", "ml_grad", "linesearch_coefs",
     "CGState", "ml_cycle", "simulate_intensity", "UPDATE_OBJECT",
     "UPDATE_PROBE", "DEFAULT_EPS", "DEFAULT_INERTIA",
 ]
@@ -260,10 +260,35 @@ def llk_terms(icalc, iobs, eps=DEFAULT_EPS):
     return i - o + t
 
 
-def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS):
-    """(sum over unmasked pixels of all frames, number of those pixels)."""
+LLK_MODELS = ("poisson", "gaussian", "euclidean")
+
+
+def llk_model_terms(icalc, iobs, model, eps=DEFAULT_EPS):
+    """Per-pixel negative log-likelihood, up to a constant, of the three noise
+    models the paper reports the likelihood for (Section 4, after Thibault &
+    Guizar-Sicairos 2012):
+      poisson   : I - Iobs + Iobs ln(Iobs / I)        (deviance / 2)
+      gaussian  : (I - Iobs)^2 / (2 (Iobs + 1))       (variance Iobs + 1)
+      euclidean : 2 (sqrt(I) - sqrt(Iobs))^2          (amplitude variance 1/4)
+    Reading: each is the negative log of its density with the constant that
+    makes it zero at a perfect fit, so all three agree to second order near
+    the fit (about Iobs d^2 / 2 for I = Iobs (1 + d)).  I is floored at eps."""
+    i = np.maximum(np.asarray(icalc, dtype=np.float64), eps)
+    o = np.asarray(iobs, dtype=np.float64)
+    if model == "poisson":
+        return llk_terms(i, o, eps)
+    if model == "gaussian":
+        return (i - o) ** 2 / (2.0 * (o + 1.0))
+    if model == "euclidean":
+        return 2.0 * (np.sqrt(i) - np.sqrt(np.maximum(o, 0.0))) ** 2
+    raise ValueError(f"unknown noise model {model!r}")
+
+
+def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson"):
+    """(sum over unmasked pixels of all frames, number of those pixels) of
+    the chosen noise model's terms."""
     inten = calc_intensity(fft2(exit_waves(obj, probe, offsets)))
-    terms = llk_terms(inten, iobs, eps)
+    terms = llk_model_terms(inten, iobs, model, eps)
     if mask is not None:
         good = np.broadcast_to(np.asarray(mask)[None] == 0, terms.shape)
     else:

@@ -330,9 +330,40 @@ def test_llk_equals_poisson_logpmf_difference():
     assert np.all(oracle.llk_terms(iobs + 1.0, iobs + 1.0) == 0.0)
 
 
+def test_gaussian_and_euclidean_llk_are_normal_logpdf_differences():
+    # Gaussian: counts ~ N(I, Iobs + 1); Euclidean: amplitudes ~ N(sqrt(I), 1/4)
+    rng = np.random.default_rng(9)
+    icalc = rng.uniform(0.1, 50.0, 400)
+    iobs = rng.poisson(icalc * rng.uniform(0.5, 1.5, 400)).astype(np.float64)
+    sd = np.sqrt(iobs + 1.0)
+    ref_g = scipy.stats.norm.logpdf(iobs, iobs, sd) - scipy.stats.norm.logpdf(iobs, icalc, sd)
+    np.testing.assert_allclose(oracle.llk_model_terms(icalc, iobs, "gaussian"), ref_g, rtol=1e-10, atol=1e-10)
+    a_obs = np.sqrt(iobs)
+    ref_e = scipy.stats.norm.logpdf(a_obs, a_obs, 0.5) - scipy.stats.norm.logpdf(a_obs, np.sqrt(icalc), 0.5)
+    np.testing.assert_allclose(oracle.llk_model_terms(icalc, iobs, "euclidean"), ref_e, rtol=1e-10, atol=1e-10)
+    np.testing.assert_array_equal(oracle.llk_model_terms(icalc, iobs, "poisson"), oracle.llk_terms(icalc, iobs))
+    # hand values at I = 4, Iobs = 9
+    assert oracle.llk_model_terms(4.0, 9.0, "gaussian") == 25.0 / 20.0
+    assert oracle.llk_model_terms(4.0, 9.0, "euclidean") == 2.0
+    with pytest.raises(ValueError):
+        oracle.llk_model_terms(4.0, 9.0, "cauchy")
+
+
+def test_noise_models_agree_to_second_order_near_the_fit():
+    iobs = np.array([1e4, 3e4, 1e5])
+    for d in (1e-3, -2e-3):
+        target = iobs * d * d / 2.0
+        for model in oracle.LLK_MODELS:
+            t = oracle.llk_model_terms(iobs * (1.0 + d), iobs, model)
+            np.testing.assert_allclose(t, target, rtol=3e-3)
+
+
 def test_llk_sum_excludes_masked_pixels_and_is_zero_at_truth():
     o, p, offs, iobs, m = tiny_problem()
     s, nobs = oracle.llk(o, p, offs, iobs, m)
+    for model in oracle.LLK_MODELS:
+        sm, nm = oracle.llk(o, p, offs, iobs, m, model=model)
+        assert nm == nobs and abs(sm) < 1e-9 * max(1.0, float(np.abs(iobs).sum()))
     assert nobs == len(offs) * int((m == 0).sum())
     assert abs(s) < 1e-9 * iobs.sum()
     iobs2 = iobs.copy()
