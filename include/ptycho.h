@@ -160,6 +160,20 @@ int ptycho_psi_init(ptycho_plan_t plan, const float *obj_dev,
 int ptycho_llk(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                double *llk_dev);
 
+/* Noise models for reporting the likelihood (Section 4 lists Poisson,
+ * Gaussian and Euclidian models, after Thibault & Guizar-Sicairos 2012).
+ * Each term is the negative log-density difference to a perfect fit. */
+typedef enum {
+    PTYCHO_LLK_POISSON = 0,     /* I - Iobs + Iobs ln(Iobs / I)                */
+    PTYCHO_LLK_GAUSSIAN = 1,    /* (I - Iobs)^2 / (2 (Iobs + 1))               */
+    PTYCHO_LLK_EUCLIDEAN = 2    /* 2 (sqrt(I) - sqrt(Iobs))^2 (amplitudes)     */
+} ptycho_llk_model_t;
+
+/* As ptycho_llk with the terms of `model` (a ptycho_llk_model_t); an unknown
+ * model is PTYCHO_E_INVALID.  llk_dev: double[2] device, as ptycho_llk. */
+int ptycho_llk_model(ptycho_plan_t plan, const float *obj_dev,
+                     const float *probe_dev, int32_t model, double *llk_dev);
+
 /* Gradient of that LLK (maximum-likelihood operator ML):
  * g = dL/dRe + i dL/dIm, i.e. with psi_jk = IFT((1 - Iobs/I) FT(O_j P_k))
  * (zero at bad pixels):

@@ -47,6 +47,7 @@ _SIGS = {
     "ptycho_dm_cycle": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_uint32],
     "ptycho_psi_init": [_P, _P, _P, _P],
     "ptycho_llk": [_P, _P, _P, _P],
+    "ptycho_llk_model": [_P, _P, _P, ctypes.c_int32, _P],
     "ptycho_ml_grad": [_P, _P, _P, _P, _P, _P],
     "ptycho_ml_linesearch": [_P, _P, _P, _P, _P, _P],
     "ptycho_ml_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],

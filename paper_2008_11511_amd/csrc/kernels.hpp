@@ -115,6 +115,7 @@ struct StackArgs {
     float *icalc;                // [J][N][N] (icalc op)
     double *red;                 // per-block partial sums of this launch
     float eps;
+    int llk_model;               // noise model of OP_LLK (LlkModel)
 };
 
 
@@ -164,6 +165,26 @@ __device__ __forceinline__ float llk_term(float inten, float iob) {
     if (fabsf(t) < 1e-2f) f = t * t * (0.5f - t * (1.0f / 6.0f - t * (1.0f / 12.0f)));
     else f = (1.0f + t) * log1pf(t) - t;
     return inten * f;
+}
+
+// Noise models of the reported likelihood, each the negative log-density
+// difference to a perfect fit: Poisson (above), Gaussian with variance
+// Iobs + 1, and Gaussian amplitudes with variance 1/4 ("Euclidean"), whose
+// difference of square roots is formed as (I - Iobs) / (sqrt I + sqrt Iobs)
+// to keep fp32 accuracy near the fit.
+enum LlkModel { LLK_POISSON = 0, LLK_GAUSSIAN = 1, LLK_EUCLIDEAN = 2 };
+__device__ __forceinline__ float llk_model_term(int model, float inten, float iob) {
+    if (model == LLK_GAUSSIAN) {
+        const float d = inten - iob;
+        return d * d / (2.0f * (iob + 1.0f));
+    }
+    if (model == LLK_EUCLIDEAN) {
+        const float ob = fmaxf(iob, 0.0f);
+        const float den = sqrtf(inten) + sqrtf(ob);
+        const float a = den > 0.0f ? (inten - ob) / den : 0.0f;
+        return 2.0f * a * a;
+    }
+    return llk_term(inten, iob);
 }
 
 // ============================================================ row passes ===
@@ -463,7 +484,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
             const float iob = io[(size_t)q * N];
             const float ifl = fmaxf(inten, a.eps);
             if constexpr (OP == OP_LLK) {
-                acc0 += (double)llk_term(ifl, iob);
+                acc0 += (double)llk_model_term(a.llk_model, ifl, iob);
             } else {
                 const float d1 = 1.0f - iob / ifl;
                 const float d2 = (iob / ifl) / ifl;

@@ -895,7 +895,7 @@ extern "C" int ptycho_psi_init(ptycho_plan_t p, const float *obj, const float *p
 // Read-only forward passes: LLK, icalc, line search.
 template <int N, int OP>
 static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, const float *dobj,
-                        const float *dprobe, float *icalc) {
+                        const float *dprobe, float *icalc, int llk_model = LLK_POISSON) {
     const bool ls = (OP == OP_LS);
     const int J = p->d.n_frames, S = ls ? p->L.S_ls : p->L.S;
     const int nst = ls ? p->L.nstacks_ls : p->L.nstacks;
@@ -907,6 +907,7 @@ static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         a.dobj = (const float2 *)dobj;
         a.dprobe = (const float2 *)dprobe;
         a.icalc = icalc;
+        a.llk_model = llk_model;
         a.red = p->red + (size_t)sidx * maxb * (ls ? 2 : 1);
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
@@ -928,10 +929,12 @@ static int zero_red(ptycho_plan_s *p) { return zero_async(p->red, up(sizeof(doub
 // llk_dev[0] = sum of the reduction partials, llk_dev[1] = number of good pixels
 __global__ void k_copy_scalar(double *dst, const double *src) { dst[0] = src[0]; }
 
-int ptycho_llk_into(ptycho_plan_t p, const float *obj, const float *probe, double *llk) {
+static int llk_into(ptycho_plan_t p, const float *obj, const float *probe, double *llk, int model) {
     int st = zero_red(p);
     if (st) return st;
-    st = with_n(p->d.n, [&](auto nn) { return forward_pass<decltype(nn)::value, OP_LLK>(p, obj, probe, nullptr, nullptr, nullptr); });
+    st = with_n(p->d.n, [&](auto nn) {
+        return forward_pass<decltype(nn)::value, OP_LLK>(p, obj, probe, nullptr, nullptr, nullptr, model);
+    });
     if (st) return st;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
     hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, p->stream, llk + 1, p->scal + SC_NOBS);
@@ -943,7 +946,17 @@ extern "C" int ptycho_llk(ptycho_plan_t p, const float *obj, const float *probe,
     int st = check_plan_ptrs(p, obj, probe);
     if (st) return st;
     if (!llk) return fail(PTYCHO_E_INVALID, "null llk output");
-    return ptycho_llk_into(p, obj, probe, llk);
+    return llk_into(p, obj, probe, llk, LLK_POISSON);
+}
+
+extern "C" int ptycho_llk_model(ptycho_plan_t p, const float *obj, const float *probe, int32_t model,
+                                double *llk) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!llk) return fail(PTYCHO_E_INVALID, "null llk output");
+    if (model != LLK_POISSON && model != LLK_GAUSSIAN && model != LLK_EUCLIDEAN)
+        return fail(PTYCHO_E_INVALID, "unknown noise model");
+    return llk_into(p, obj, probe, llk, model);
 }
 
 extern "C" int ptycho_icalc(ptycho_plan_t p, const float *obj, const float *probe, float *icalc) {

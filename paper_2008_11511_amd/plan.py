@@ -152,12 +152,20 @@ class Plan:
         check(lib().ptycho_psi_init(self._h, _ptr(obj), _ptr(probe), _ptr(psi)))
         return psi
 
-    def llk(self, obj, probe, out=None):
-        """Device double[2]: (LLK sum, number of unmasked pixels)."""
+    LLK_MODELS = {"poisson": 0, "gaussian": 1, "euclidean": 2}
+
+    def llk(self, obj, probe, out=None, model: str = "poisson"):
+        """Device double[2]: (LLK sum, number of unmasked pixels) of the noise
+        model `model` ("poisson", "gaussian" or "euclidean")."""
         self._op(obj, probe)
+        if model not in self.LLK_MODELS:
+            raise ValueError(f"unknown noise model {model!r}")
         out = torch.empty(2, dtype=torch.float64, device=self.device) if out is None else out
         self._enter()
-        check(lib().ptycho_llk(self._h, _ptr(obj), _ptr(probe), _ptr(out)))
+        if model == "poisson":
+            check(lib().ptycho_llk(self._h, _ptr(obj), _ptr(probe), _ptr(out)))
+        else:
+            check(lib().ptycho_llk_model(self._h, _ptr(obj), _ptr(probe), self.LLK_MODELS[model], _ptr(out)))
         return out
 
     def ml_grad(self, obj, probe, g_obj=None, g_probe=None, llk=None):

@@ -106,10 +106,39 @@ def test_icalc_and_llk_match_oracle(dev, n, k, j):
     ic = host(plan.icalc(o, p))
     ic_ref = oracle.simulate_intensity(pb.obj0, pb.probe0, pb.offsets)
     assert rel_l2(ic, ic_ref) < 1e-5
-    llk = host(plan.llk(o, p))
-    ref, nobs = oracle.llk(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask)
-    assert llk[1] == nobs
-    assert abs(llk[0] - ref) <= 1e-4 * abs(ref)
+    for model in oracle.LLK_MODELS:
+        llk = host(plan.llk(o, p, model=model))
+        ref, nobs = oracle.llk(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, model=model)
+        assert llk[1] == nobs
+        assert abs(llk[0] - ref) <= 1e-4 * abs(ref), model
+
+
+def test_noise_model_llk_near_the_fit_and_unknown_model(dev):
+    """Near a perfect fit the three models agree to second order; fp32 terms
+    must keep that (the Euclidean one takes a difference of square roots)."""
+    wl = small("dm256", n=64, k=2, j=30, obj=(256, 256), step=4.0, mask_frac=0.03)
+    pb = make_problem(wl, start="truth", noiseless=True)
+    say("llk near the fit, all models")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    # a 1e-3 probe scale: I = Iobs (1 + d), d ~ 2e-3
+    p = p * (1.0 + 1e-3)
+    pp = pb.probe0 * (1.0 + 1e-3)
+    vals = {}
+    for model in oracle.LLK_MODELS:
+        llk = host(plan.llk(o, p, model=model))
+        ref, _ = oracle.llk(pb.obj0, pp.astype(np.complex64).astype(np.complex128), pb.offsets, pb.iobs,
+                            pb.mask, model=model)
+        assert abs(llk[0] - ref) <= 2e-3 * abs(ref), model
+        vals[model] = llk[0]
+    assert abs(vals["gaussian"] / vals["poisson"] - 1) < 0.05
+    assert abs(vals["euclidean"] / vals["poisson"] - 1) < 0.05
+    from paper_2008_11511_amd._lib import lib
+    from paper_2008_11511_amd.plan import _ptr
+    out = torch.empty(2, dtype=torch.float64, device=dev)
+    assert lib().ptycho_llk_model(plan._h, _ptr(o), _ptr(p), 7, _ptr(out)) == -1
+    with pytest.raises(ValueError):
+        plan.llk(o, p, model="cauchy")
 
 
 # ------------------------------------------------------------- AP / DM ----
