@@ -42,11 +42,13 @@ __all__ = [
     "overlap_denominators", "overlap_update", "ap_cycle", "dm_cycle",
     "psi_init", "llk", "llk_terms", "llk_model_terms", "LLK_MODELS", "ml_grad", "linesearch_coefs",
     "CGState", "ml_cycle", "simulate_intensity", "UPDATE_OBJECT",
-    "UPDATE_PROBE", "DEFAULT_EPS", "DEFAULT_INERTIA",
+    "UPDATE_PROBE", "UPDATE_BACKGROUND", "DEFAULT_EPS", "DEFAULT_INERTIA",
+    "model_intensity", "projection_scale", "background_update",
 ]
 
 UPDATE_OBJECT = 1
 UPDATE_PROBE = 2
+UPDATE_BACKGROUND = 4        # AP only: refine the incoherent background
 DEFAULT_EPS = 1e-20          # floor on the calculated intensity
 DEFAULT_INERTIA = 1e-2       # delta in alpha = delta * max(denominator)
 
@@ -118,25 +120,50 @@ def calc_intensity(psi_hat: np.ndarray) -> np.ndarray:
     return (np.abs(psi_hat) ** 2).sum(axis=1)
 
 
-def project_modulus(psi_hat: np.ndarray, iobs: np.ndarray,
-                    mask: Optional[np.ndarray], eps: float = DEFAULT_EPS) -> np.ndarray:
-    """Replace the Fourier modulus by the observed amplitude.
-
-    With several incoherent probe modes all modes of a pixel share one scale
-    sqrt(Iobs / I), I = sum_k |Psi_k|^2 (floored at eps), so that the
-    projected modes sum to the observed intensity and keep their phases.
-    Bad (masked) pixels are left unchanged.
-    """
+def model_intensity(psi_hat: np.ndarray, bg=None) -> np.ndarray:
+    """Model intensity: the modes' sum plus the incoherent background bg
+    [N][N] (shared by all frames, FFT order), which the Ptycho object of
+    Section 4 carries beside object and probe; bg None means zero."""
     inten = calc_intensity(psi_hat)
+    return inten if bg is None else inten + np.asarray(bg, dtype=np.float64)[None]
+
+
+def projection_scale(psi_hat, iobs, mask, eps=DEFAULT_EPS, bg=None) -> np.ndarray:
+    """s = sqrt(Iobs / I) per frame and pixel, I the model intensity floored
+    at eps; 1 at bad pixels."""
+    inten = model_intensity(psi_hat, bg)
     scale = np.sqrt(np.asarray(iobs, dtype=np.float64) / np.maximum(inten, eps))
     if mask is not None:
         scale = np.where(np.asarray(mask)[None, :, :] != 0, 1.0, scale)
-    return psi_hat * scale[:, None, :, :]
+    return scale
 
 
-def fourier_project(psi: np.ndarray, iobs, mask, eps: float = DEFAULT_EPS) -> np.ndarray:
+def project_modulus(psi_hat: np.ndarray, iobs: np.ndarray,
+                    mask: Optional[np.ndarray], eps: float = DEFAULT_EPS, bg=None) -> np.ndarray:
+    """Replace the Fourier modulus by the observed amplitude.
+
+    With several incoherent probe modes all modes of a pixel share one scale
+    sqrt(Iobs / I), I = sum_k |Psi_k|^2 (+ background) floored at eps, so
+    that the projected model (modes and background, the background taken as
+    one more incoherent mode) matches the observed intensity and the modes
+    keep their phases.  Bad (masked) pixels are left unchanged.
+    """
+    return psi_hat * projection_scale(psi_hat, iobs, mask, eps, bg)[:, None, :, :]
+
+
+def fourier_project(psi: np.ndarray, iobs, mask, eps: float = DEFAULT_EPS, bg=None) -> np.ndarray:
     """IFT * ApplyAmplitude * FT on every frame and mode (far field)."""
-    return ifft2(project_modulus(fft2(psi), iobs, mask, eps))
+    return ifft2(project_modulus(fft2(psi), iobs, mask, eps, bg))
+
+
+def background_update(bg, scale) -> np.ndarray:
+    """Incoherent background refinement of AP (Section 4, after Marchesini et
+    al. 2013).  Reading: the background is the one incoherent mode that all
+    frames share, so its projected intensity at frame j is bg * s_j^2 and the
+    new background is the mean of that over the frames:
+      bg' = bg * (1/J) sum_j s_j^2
+    (s = 1 at bad pixels, which keep their value)."""
+    return np.asarray(bg, dtype=np.float64) * (np.asarray(scale) ** 2).mean(axis=0)
 
 
 # --------------------------------------------------------------------------
@@ -222,17 +249,28 @@ def overlap_update(obj, probe, psi, offsets, update=UPDATE_OBJECT | UPDATE_PROBE
 
 def ap_cycle(obj, probe, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
              inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
-             eps=DEFAULT_EPS):
+             eps=DEFAULT_EPS, bg=None):
     """One alternating-projections cycle: views, Fourier projection of every
-    frame, then one object/probe update from all projected exit waves."""
+    frame, then one object/probe update from all projected exit waves.
+    Returns (obj, probe); with a background bg, (obj, probe, bg), the
+    background refined by `background_update` when UPDATE_BACKGROUND is set."""
+    if (update & UPDATE_BACKGROUND) and bg is None:
+        raise ValueError("a background update needs a background")
     phi = exit_waves(obj, probe, offsets)
-    psi = fourier_project(phi, iobs, mask, eps)
-    return overlap_update(obj, probe, psi, offsets, update, inertia_obj, inertia_probe)
+    phi_hat = fft2(phi)
+    scale = projection_scale(phi_hat, iobs, mask, eps, bg)
+    psi = ifft2(phi_hat * scale[:, None, :, :])
+    o, p = overlap_update(obj, probe, psi, offsets, update & (UPDATE_OBJECT | UPDATE_PROBE),
+                          inertia_obj, inertia_probe)
+    if bg is None:
+        return o, p
+    b = background_update(bg, scale) if update & UPDATE_BACKGROUND else np.asarray(bg, dtype=np.float64)
+    return o, p, b
 
 
 def dm_cycle(obj, probe, psi, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
              inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
-             eps=DEFAULT_EPS):
+             eps=DEFAULT_EPS, bg=None):
     """One difference-map cycle (beta = 1) on persistent exit waves.
 
     Phi = views of the current object and probe (the overlap projection of
@@ -241,7 +279,7 @@ def dm_cycle(obj, probe, psi, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE
     """
     phi = exit_waves(obj, probe, offsets)
     psi = np.asarray(psi, dtype=np.complex128)
-    psi_new = psi + fourier_project(2.0 * phi - psi, iobs, mask, eps) - phi
+    psi_new = psi + fourier_project(2.0 * phi - psi, iobs, mask, eps, bg) - phi
     o, p = overlap_update(obj, probe, psi_new, offsets, update, inertia_obj, inertia_probe)
     return o, p, psi_new
 
@@ -284,10 +322,10 @@ def llk_model_terms(icalc, iobs, model, eps=DEFAULT_EPS):
     raise ValueError(f"unknown noise model {model!r}")
 
 
-def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson"):
+def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson", bg=None):
     """(sum over unmasked pixels of all frames, number of those pixels) of
     the chosen noise model's terms."""
-    inten = calc_intensity(fft2(exit_waves(obj, probe, offsets)))
+    inten = model_intensity(fft2(exit_waves(obj, probe, offsets)), bg)
     terms = llk_model_terms(inten, iobs, model, eps)
     if mask is not None:
         good = np.broadcast_to(np.asarray(mask)[None] == 0, terms.shape)
@@ -296,11 +334,11 @@ def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson"):
     return float(terms[good].sum()), int(good.sum())
 
 
-def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS):
+def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None):
     """Gradient of the Poisson LLK w.r.t. object and probe.
 
     Convention: g = dL/dRe(z) + i dL/dIm(z) (= 2 dL/dz*).  With
-    Psi^_jk = F(P_k O_j), I_j = sum_k |Psi^_jk|^2 and l'(I) = 1 - Iobs/I
+    Psi^_jk = F(P_k O_j), I_j = sum_k |Psi^_jk|^2 (+ bg) and l'(I) = 1 - Iobs/I
     (0 at bad pixels), the chain rule through the unitary F gives
       psi_jk = F^-1(l'(I_j) Psi^_jk)
       g_O = 2 sum_jk S_j^T (conj(P_k) psi_jk)
@@ -311,7 +349,7 @@ def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS):
     probe = np.asarray(probe, dtype=np.complex128)
     n = probe.shape[-1]
     phi_hat = fft2(exit_waves(obj, probe, offsets))
-    inten = np.maximum(calc_intensity(phi_hat), eps)
+    inten = np.maximum(model_intensity(phi_hat, bg), eps)
     io = np.asarray(iobs, dtype=np.float64)
     dl = 1.0 - io / inten
     terms = llk_terms(inten, io, eps)
@@ -329,7 +367,7 @@ def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS):
     return g_o, g_p, float(terms.sum())
 
 
-def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_EPS):
+def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None):
     """First and second derivative of L(gamma) = LLK(O + g dO, P + g dP) at 0.
 
     The exit wave along the line is A + gamma B + gamma^2 C with
@@ -344,7 +382,7 @@ def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_
     a = fft2(exit_waves(obj, probe, offsets))
     b = fft2(exit_waves(obj, dprobe, offsets) + exit_waves(dobj, probe, offsets))
     c = fft2(exit_waves(dobj, dprobe, offsets))
-    i0 = np.maximum(calc_intensity(a), eps)
+    i0 = np.maximum(model_intensity(a, bg), eps)
     i1 = 2.0 * (np.conj(a) * b).real.sum(axis=1)
     i2 = (np.abs(b) ** 2).sum(axis=1) + 2.0 * (np.conj(a) * c).real.sum(axis=1)
     io = np.asarray(iobs, dtype=np.float64)
@@ -378,7 +416,7 @@ class CGState:
 
 
 def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
-             update=UPDATE_OBJECT, eps=DEFAULT_EPS):
+             update=UPDATE_OBJECT, eps=DEFAULT_EPS, bg=None):
     """One Polak-Ribiere (PR+) conjugate-gradient step on the Poisson LLK.
 
     The probe block of the gradient is scaled by s = max(denO) / max(denP)
@@ -391,7 +429,7 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
     """
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
-    g_o, g_p, lsum = ml_grad(obj, probe, offsets, iobs, mask, eps)
+    g_o, g_p, lsum = ml_grad(obj, probe, offsets, iobs, mask, eps, bg)
     if not update & UPDATE_OBJECT:
         g_o = np.zeros_like(g_o)
     if not update & UPDATE_PROBE:
@@ -408,7 +446,7 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
         beta = max(0.0, num / state.zg)
         d_o = -g_o + beta * state.d_obj
         d_p = -s * g_p + beta * state.d_probe
-    l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps)
+    l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps, bg)
     gamma = -l1 / l2 if (l2 > 0.0 and math.isfinite(l1) and math.isfinite(l2)) else 0.0
     state.d_obj, state.d_probe = d_o, d_p
     state.g_obj, state.g_probe = g_o, g_p
@@ -421,9 +459,9 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
 # Forward model for simulation (Section 4, simulation functions)
 # --------------------------------------------------------------------------
 
-def simulate_intensity(obj, probe, offsets, chunk: int = 64) -> np.ndarray:
-    """Noise-free far-field intensities sum_k |F(P_k O_j)|^2, float64 [J][N][N]."""
+def simulate_intensity(obj, probe, offsets, chunk: int = 64, bg=None) -> np.ndarray:
+    """Noise-free far-field intensities sum_k |F(P_k O_j)|^2 (+ bg), float64 [J][N][N]."""
     out = []
     for s in range(0, len(offsets), chunk):
-        out.append(calc_intensity(fft2(exit_waves(obj, probe, offsets[s:s + chunk]))))
+        out.append(model_intensity(fft2(exit_waves(obj, probe, offsets[s:s + chunk])), bg))
     return np.concatenate(out, axis=0)

@@ -496,3 +496,88 @@ def test_dm_stays_bounded_over_many_cycles():
         o, p, psi = oracle.dm_cycle(o, p, psi, pb.offsets, pb.iobs, pb.mask)
     assert np.abs(o).max() < 3.0
     assert oracle.llk(o, p, pb.offsets, pb.iobs, pb.mask)[0] < 2 * l0
+
+
+# ----------------------------------------------------------------------------
+# Incoherent background
+# ----------------------------------------------------------------------------
+
+def _background(n, seed=4):
+    rng = np.random.default_rng(seed)
+    return 0.5 + rng.random((n, n))
+
+
+def test_zero_background_changes_nothing():
+    o, p, offs, iobs, m = tiny_problem(noiseless=False, seed=12)
+    o0, p0 = o * 1.01, p * 0.97
+    z = np.zeros(p.shape[1:])
+    upd = oracle.UPDATE_OBJECT | oracle.UPDATE_PROBE
+    a = oracle.ap_cycle(o0, p0, offs, iobs, m, upd)
+    b = oracle.ap_cycle(o0, p0, offs, iobs, m, upd | oracle.UPDATE_BACKGROUND, bg=z)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    assert not b[2].any()
+    psi = oracle.psi_init(o0, p0, offs)
+    for x, y in zip(oracle.dm_cycle(o0, p0, psi, offs, iobs, m), oracle.dm_cycle(o0, p0, psi, offs, iobs, m, bg=z)):
+        np.testing.assert_array_equal(x, y)
+    assert oracle.llk(o0, p0, offs, iobs, m) == oracle.llk(o0, p0, offs, iobs, m, bg=z)
+    for x, y in zip(oracle.ml_grad(o0, p0, offs, iobs, m), oracle.ml_grad(o0, p0, offs, iobs, m, bg=z)):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_truth_with_background_is_a_fixed_point():
+    o, p, offs, _, m = tiny_problem(seed=13)
+    bg = _background(p.shape[-1])
+    iobs = oracle.simulate_intensity(o, p, offs, bg=bg)
+    all3 = oracle.UPDATE_OBJECT | oracle.UPDATE_PROBE | oracle.UPDATE_BACKGROUND
+    o1, p1, b1 = oracle.ap_cycle(o, p, offs, iobs, m, all3, bg=bg)
+    assert np.abs(o1 - o).max() < 1e-12 and np.abs(p1 - p).max() < 1e-12
+    assert np.abs(b1 - bg).max() < 1e-12
+    psi = oracle.psi_init(o, p, offs)
+    o2, p2, _ = oracle.dm_cycle(o, p, psi, offs, iobs, m, bg=bg)
+    assert np.abs(o2 - o).max() < 1e-12 and np.abs(p2 - p).max() < 1e-12
+    assert abs(oracle.llk(o, p, offs, iobs, m, bg=bg)[0]) < 1e-9 * iobs.sum()
+    g_o, g_p, _ = oracle.ml_grad(o, p, offs, iobs, m, bg=bg)
+    assert np.abs(g_o).max() < 1e-9 and np.abs(g_p).max() < 1e-9
+    # without the background in the model the truth is no longer a fit
+    assert oracle.llk(o, p, offs, iobs, m)[0] > 1.0
+
+
+def test_background_ap_cycle_scalar_case():
+    # one pixel, two frames at the same place, O = P = 1, background 2:
+    # I = 1 + 2 = 3 for both; Iobs = 6 and 3 give s^2 = 2 and 1, so the new
+    # background is 2 * (2 + 1) / 2 = 3, and the object sum is sqrt(2) + 1
+    # over a denominator 2 (inertia 1e-2 * 2 on both)
+    o = np.ones((1, 1), complex)
+    p = np.ones((1, 1, 1), complex)
+    offs = np.zeros((2, 2), np.int32)
+    iobs = np.array([6.0, 3.0]).reshape(2, 1, 1)
+    o1, p1, b1 = oracle.ap_cycle(o, p, offs, iobs, None, oracle.UPDATE_OBJECT | oracle.UPDATE_BACKGROUND,
+                                 bg=np.full((1, 1), 2.0))
+    assert b1[0, 0] == pytest.approx(3.0, rel=1e-15)
+    assert o1[0, 0] == pytest.approx((np.sqrt(2.0) + 1.0 + 0.02) / 2.02, rel=1e-15)
+    assert p1[0, 0, 0] == 1.0
+    with pytest.raises(ValueError):
+        oracle.ap_cycle(o, p, offs, iobs, None, oracle.UPDATE_BACKGROUND)
+
+
+def test_gradient_with_background_matches_central_differences():
+    o, p, offs, _, m = tiny_problem(seed=14)
+    bg = _background(p.shape[-1], seed=5)
+    rng = np.random.default_rng(14)
+    iobs = rng.poisson(oracle.simulate_intensity(o, p, offs, bg=bg)).astype(np.float64)
+    o0 = o * np.exp(0.2j * np.sin(np.arange(o.size).reshape(o.shape)))
+    p0 = p * 0.95
+    g_o, g_p, _ = oracle.ml_grad(o0, p0, offs, iobs, m, bg=bg)
+    lo = lambda x: oracle.llk(x, p0, offs, iobs, m, bg=bg)[0]
+    lp = lambda x: oracle.llk(o0, x, offs, iobs, m, bg=bg)[0]
+    illum = np.flatnonzero(abs(g_o) > 0)
+    _fd_check(lo, o0, g_o, rng.choice(illum, 8, replace=False), 1e-3 * np.sqrt((abs(o0) ** 2).mean()))
+    _fd_check(lp, p0, g_p, rng.choice(p0.size, 8, replace=False), 1e-3 * np.sqrt((abs(p0) ** 2).mean()))
+    d_o = o0 * 0.01j
+    d_p = p0 * 0.02
+    l1, l2 = oracle.linesearch_coefs(o0, p0, d_o, d_p, offs, iobs, m, bg=bg)
+    f = lambda g: oracle.llk(o0 + g * d_o, p0 + g * d_p, offs, iobs, m, bg=bg)[0]
+    h = 1e-3
+    assert l1 == pytest.approx((f(h) - f(-h)) / (2 * h), rel=1e-5)
+    assert l2 == pytest.approx((f(h) - 2 * f(0) + f(-h)) / (h * h), rel=1e-3)
