@@ -61,8 +61,13 @@ typedef enum {
 } ptycho_status;
 
 /* Update flags for the cycle entry points. */
-#define PTYCHO_UPDATE_OBJECT 1u
-#define PTYCHO_UPDATE_PROBE  2u
+#define PTYCHO_UPDATE_OBJECT     1u
+#define PTYCHO_UPDATE_PROBE      2u
+#define PTYCHO_UPDATE_BACKGROUND 4u   /* AP only; see ptycho_ap_cycle */
+
+/* Descriptor flags.  PTYCHO_FLAG_BACKGROUND reserves workspace for the AP
+ * background refinement (S*N*N floats and N*N doubles). */
+#define PTYCHO_FLAG_BACKGROUND 1u
 
 /* Problem description.  Supported: N in {16, 32, 64, 128, 256, 512},
  * 1 <= K <= 4, J >= 1, obj_ny >= N, obj_nx >= N. */
@@ -77,7 +82,7 @@ typedef struct {
     float obj_inertia;      /* delta_O: alpha_O = delta_O * max(denO)           */
     float probe_inertia;    /* delta_P: alpha_P = delta_P * max(denP)           */
     float icalc_floor;      /* epsilon: calculated intensity floor              */
-    uint32_t flags;         /* reserved, must be 0                              */
+    uint32_t flags;         /* PTYCHO_FLAG_* (0 or PTYCHO_FLAG_BACKGROUND)      */
 } ptycho_desc_t;
 
 typedef struct ptycho_plan_s *ptycho_plan_t;
@@ -117,6 +122,17 @@ int ptycho_plan_create(const ptycho_desc_t *desc, const int32_t *offsets_host,
 int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
                         size_t *table_bytes_out);
 
+/* Incoherent background (Section 4: the Ptycho object carries one beside the
+ * object and probe estimates): bg_dev float[N][N] in FFT order, shared by
+ * all frames, caller-owned, NULL = none.  Every operator then models the
+ * intensity as I = sum_k |FT(O_j P_k)|^2 + bg: the modulus projection (the
+ * background is scaled like one more incoherent mode), LLK, icalc, the ML
+ * gradient and line search.  ptycho_ap_cycle with PTYCHO_UPDATE_BACKGROUND
+ * refines it in place: bg <- bg * (1/J) sum_j s_j^2, s_j^2 = Iobs / I at
+ * frame j (1 at bad pixels), from the projection of that cycle (the
+ * augmented projections the paper cites for AP background optimisation). */
+int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
+
 /* Change the stream later calls enqueue on (hipStream_t). */
 int ptycho_plan_set_stream(ptycho_plan_t plan, void *stream);
 
@@ -133,7 +149,10 @@ int ptycho_plan_destroy(ptycho_plan_t plan);
  *   O <- (sum_jk conj(P_k) Psi_jk + alpha_O O) / (sum_jk |P_k|^2 + alpha_O)
  *   P_k <- (sum_j conj(O_j) Psi_jk + alpha_P P_k) / (sum_j |O_j|^2 + alpha_P)
  * (pixels with a zero denominator keep their value).
- * update: PTYCHO_UPDATE_OBJECT | PTYCHO_UPDATE_PROBE.  obj, probe: in/out.
+ * update: PTYCHO_UPDATE_OBJECT | PTYCHO_UPDATE_PROBE, and
+ * PTYCHO_UPDATE_BACKGROUND to refine the background set with
+ * ptycho_plan_set_background (the plan must have PTYCHO_FLAG_BACKGROUND;
+ * PTYCHO_E_INVALID otherwise).  obj, probe: in/out.
  * psi_dev: complex[J][K][N][N] storage for the projected exit waves, needed
  * (PTYCHO_E_INVALID otherwise) when the probe is updated, since the probe
  * update runs after the object update over all frames; may be NULL for an

@@ -18,6 +18,8 @@ STATUS = {0: "PTYCHO_OK", -1: "PTYCHO_E_INVALID", -2: "PTYCHO_E_BOUNDS",
           -3: "PTYCHO_E_UNSUPPORTED", -4: "PTYCHO_E_HIP", -5: "PTYCHO_E_WORKSPACE"}
 UPDATE_OBJECT = 1
 UPDATE_PROBE = 2
+UPDATE_BACKGROUND = 4
+FLAG_BACKGROUND = 1
 
 
 class PtychoError(RuntimeError):
@@ -41,6 +43,7 @@ _SIGS = {
     "ptycho_plan_create": [ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
     "ptycho_plan_dry_run": [ctypes.POINTER(Desc), _P, ctypes.POINTER(ctypes.c_size_t)],
     "ptycho_plan_set_stream": [_P, _P],
+    "ptycho_plan_set_background": [_P, _P],
     "ptycho_plan_stack": [_P, ctypes.POINTER(ctypes.c_int32)],
     "ptycho_plan_destroy": [_P],
     "ptycho_ap_cycle": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_uint32],

@@ -111,6 +111,8 @@ struct StackArgs {
     float2 *scr;                 // stack scratch [S][sets*K][N][N] (column tiles)
     float2 *qbuf;                // per slot sum_k conj(P_k) Psi_k, [S][N][N] row-major
     const float *iobs;           // [J][N][N]
+    const float *bg;             // incoherent background [N][N] or null
+    float *s2;                   // AP background refinement: s^2 per slot [S][N][N], or null
     const unsigned char *mask;   // [N][N] or null
     float *icalc;                // [J][N][N] (icalc op)
     double *red;                 // per-block partial sums of this launch
@@ -312,6 +314,20 @@ __global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
     }
 }
 
+// AP background refinement: bsum[i] (+)= sum over the stack's slots of s^2
+// (slot order), then bg[i] *= bsum[i] / J once all stacks are in.
+__global__ __launch_bounds__(256) void k_bg_accum(const float *s2, int S, long n2, double *bsum, int first) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long)gridDim.x * 256) {
+        double v = first ? 0.0 : bsum[i];
+        for (int s = 0; s < S; ++s) v += (double)s2[(size_t)s * n2 + i];
+        bsum[i] = v;
+    }
+}
+__global__ __launch_bounds__(256) void k_bg_finish(float *bg, const double *bsum, long n2, double J) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long)gridDim.x * 256)
+        bg[i] = (float)((double)bg[i] * (bsum[i] / J));
+}
+
 // dst = J * (number of mask pixels equal to 0); every pixel if mask is null.
 __global__ __launch_bounds__(256) void k_count_good(const unsigned char *mask, int n2, double J, double *dst) {
     double c = 0.0;
@@ -366,13 +382,14 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     // the data of the pixels this thread will own after the transform are
     // loaded now: loads cannot move across the transform's barriers
     const float *io = a.iobs + (size_t)j * N * N + c;
-    float iobv[E];
+    float iobv[E], bgv[E];
     bool badv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = out_index<N, E, -1>(t, e);
         iobv[e] = io[(size_t)q * N];
         badv[e] = a.mask != nullptr && a.mask[q * N + c] != 0;
+        bgv[e] = a.bg != nullptr ? a.bg[q * N + c] : 0.0f;
     }
     if constexpr (SEQ) {
 #pragma unroll
@@ -387,12 +404,14 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
         float inten = 0.0f;
 #pragma unroll
         for (int k = 0; k < K; ++k) inten += cnorm(u[k][e]);
-        inten *= inv_n2;
+        inten = inten * inv_n2 + bgv[e];
         const bool bad = badv[e];
         const float iob = iobv[e];
         float sc;
         if constexpr (OP == OP_PROJECT) {
-            sc = bad ? inv_n2 : sqrtf(iob / fmaxf(inten, a.eps)) * inv_n2;
+            const float r = iob / fmaxf(inten, a.eps);
+            sc = bad ? inv_n2 : sqrtf(r) * inv_n2;
+            if (a.s2 != nullptr && active) a.s2[((size_t)s * N + out_index<N, E, -1>(t, e)) * N + c] = bad ? 1.0f : r;
         } else if constexpr (OP == OP_CORR) {
             sc = bad ? 0.0f : (sqrtf(iob / fmaxf(inten, a.eps)) - 1.0f) * inv_n2;
         } else {
@@ -475,7 +494,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = out_index<N, E, -1>(t, e);
-        const float inten = i0[e] * inv_n2;
+        const float inten = i0[e] * inv_n2 + (a.bg != nullptr ? a.bg[q * N + c] : 0.0f);
         if constexpr (OP == OP_ICALC) {
             if (active) a.icalc[((size_t)j * N + q) * N + c] = inten;
         } else {

@@ -113,7 +113,7 @@ struct Layout {
     size_t nlist_ints, npslots;   // object-gather block/reduce lists, partial slots
     size_t nent_max, nfr_max, nred;
     size_t off_offs, off_order, off_lists, off_ent_fr, off_opart, off_scr, off_q, off_pint, off_numO, off_denO,
-        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, total;
+        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, off_s2, off_bsum, total;
 };
 
 // Frame chunks of the all-frame probe gather: enough blocks to fill the
@@ -178,6 +178,10 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.off_part = o; o = up(o + sizeof(float) * 2 * NPART);
     L.off_red = o; o = up(o + sizeof(double) * L.nred);
     L.off_scal = o; o = up(o + sizeof(double) * NSCAL);
+    // background refinement (AP): s^2 of a stack's frames and their sums
+    const bool bgu = (d.flags & PTYCHO_FLAG_BACKGROUND) != 0;
+    L.off_s2 = o; o = up(o + (bgu ? sizeof(float) * (size_t)L.S * n2 : 0));
+    L.off_bsum = o; o = up(o + (bgu ? sizeof(double) * n2 : 0));
     L.total = o;
     return L;
 }
@@ -208,6 +212,9 @@ struct ptycho_plan_s {
     float2 *opnum;       // object-gather chunk partials
     float *opden;
     float2 *scr, *q, *numO, *numP, *pnum;
+    float *bg = nullptr;     // caller's background [N][N] (set_background), or null
+    float *s2 = nullptr;     // [S][N][N] with PTYCHO_FLAG_BACKGROUND
+    double *bsum = nullptr;  // [N][N]
     float *pint, *denO, *denP, *pden, *part;
     double *red, *scal;
     int ntx, nty;
@@ -260,7 +267,7 @@ static int check_desc(const ptycho_desc_t *d) {
     if (d->stack < 0) return fail(PTYCHO_E_INVALID, "negative stack");
     if (!(d->obj_inertia >= 0.0f) || !(d->probe_inertia >= 0.0f)) return fail(PTYCHO_E_INVALID, "negative inertia");
     if (!(d->icalc_floor > 0.0f)) return fail(PTYCHO_E_INVALID, "icalc_floor must be > 0");
-    if (d->flags != 0) return fail(PTYCHO_E_INVALID, "flags must be 0");
+    if (d->flags & ~PTYCHO_FLAG_BACKGROUND) return fail(PTYCHO_E_INVALID, "unknown descriptor flag");
     return PTYCHO_OK;
 }
 
@@ -511,6 +518,10 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
     p->part = (float *)(p->ws + L.off_part);
     p->red = (double *)(p->ws + L.off_red);
     p->scal = (double *)(p->ws + L.off_scal);
+    if (d->flags & PTYCHO_FLAG_BACKGROUND) {
+        p->s2 = (float *)(p->ws + L.off_s2);
+        p->bsum = (double *)(p->ws + L.off_bsum);
+    }
     p->ntx = (d->obj_nx + OTILE_X - 1) / OTILE_X;
     p->nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
 
@@ -560,6 +571,12 @@ extern "C" int ptycho_plan_dry_run(const ptycho_desc_t *d, const int32_t *offset
     if (st) return st;
     *table_bytes = sizeof(int) * p.h_lists.size() + sizeof(int4) * p.h_fr.size() +
                    sizeof(int) * p.h_order.size() + sizeof(int2) * p.h_offs.size();
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_set_background(ptycho_plan_t p, float *bg) {
+    if (!p) return fail(PTYCHO_E_INVALID, "null plan");
+    p->bg = bg;
     return PTYCHO_OK;
 }
 
@@ -634,6 +651,7 @@ static StackArgs stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, 
     a.scr = p->scr;
     a.qbuf = p->q;
     a.iobs = p->iobs;
+    a.bg = p->bg;
     a.mask = p->mask;
     a.eps = p->d.icalc_floor;
     return a;
@@ -778,7 +796,7 @@ static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
 // exit waves from the scratch).
 template <int N, int K>
 static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind,
-                        unsigned acc) {
+                        unsigned acc, bool upd_bg = false) {
     const int J = p->d.n_frames, S = p->L.S;
     hipStream_t s = p->stream;
     const bool store = (psi != nullptr);
@@ -795,6 +813,7 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         a.psi = (const float2 *)psi;
         a.psi_out = (float2 *)psi;
         a.red = p->red + (size_t)sidx * p->L.maxb;
+        if (upd_bg) a.s2 = p->s2;
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
@@ -806,6 +825,12 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
             if (kind == 2) launch_cols_joint<N, K, OP_GRAD>(a, s);
             else if (kind == 1) launch_cols_joint<N, K, OP_CORR>(a, s);
             else launch_cols_joint<N, K, OP_PROJECT>(a, s);
+        }
+        if (upd_bg) {
+            const long n2 = (long)N * N;
+            Timed tm(p, TC_OTHER);
+            hipLaunchKernelGGL(k_bg_accum, dim3(grid_for(n2)), dim3(256), 0, s, p->s2, sn, n2, p->bsum,
+                               sidx == 0 ? 1 : 0);
         }
         {
             Timed tm(p, TC_ROWS_INV);
@@ -849,7 +874,11 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
     int st = check_plan_ptrs(p, obj, probe);
     if (st) return st;
     if (n_cycles < 0) return fail(PTYCHO_E_INVALID, "negative cycle count");
-    if (upd & ~3u) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    if (upd & ~(kind == 0 ? 7u : 3u)) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    const bool upd_bg = (upd & PTYCHO_UPDATE_BACKGROUND) != 0;
+    if (upd_bg && !p->bg) return fail(PTYCHO_E_INVALID, "a background update needs a background (set_background)");
+    if (upd_bg && !p->s2)
+        return fail(PTYCHO_E_INVALID, "a background update needs a plan created with PTYCHO_FLAG_BACKGROUND");
     if (kind == 1 && !psi) return fail(PTYCHO_E_INVALID, "null psi");
     if (kind == 0 && (upd & 2u) && !psi)
         return fail(PTYCHO_E_INVALID, "an AP probe update needs exit-wave storage (psi)");
@@ -860,7 +889,15 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
             for (int c = 0; c < n_cycles; ++c) {
                 int s2 = PTYCHO_OK;
                 if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
-                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, (upd & 1u) ? ACC_OBJ : 0u);
+                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, (upd & 1u) ? ACC_OBJ : 0u, upd_bg);
+                if (!s2 && upd_bg) {
+                    // every stack was projected with the old background
+                    const long n2 = (long)N * N;
+                    Timed tm(p, TC_OTHER);
+                    hipLaunchKernelGGL(k_bg_finish, dim3(grid_for(n2)), dim3(256), 0, p->stream, p->bg, p->bsum, n2,
+                                       (double)p->d.n_frames);
+                    s2 = hipGetLastError() == hipSuccess ? PTYCHO_OK : fail(PTYCHO_E_HIP, "background update launch");
+                }
                 if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
                 if (!s2 && (upd & 2u)) s2 = probe_sums(p, obj, (const float2 *)psi, 0, p->d.n_frames, false, false);
                 if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);

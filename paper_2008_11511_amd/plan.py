@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Desc, check, lib
+from ._lib import FLAG_BACKGROUND, Desc, check, lib
 
 
 def _ptr(t: torch.Tensor) -> int:
@@ -63,7 +63,8 @@ class Plan:
 
     def __init__(self, offsets, iobs: torch.Tensor, mask: Optional[torch.Tensor], n_modes: int,
                  obj_shape, stack: int = 0, obj_inertia: float = 1e-2, probe_inertia: float = 1e-2,
-                 icalc_floor: float = 1e-20, workspace: Optional[torch.Tensor] = None):
+                 icalc_floor: float = 1e-20, workspace: Optional[torch.Tensor] = None,
+                 background_update: bool = False):
         offs = np.ascontiguousarray(offsets, dtype=np.int32)
         if offs.ndim != 2 or offs.shape[1] != 2:
             raise ValueError("offsets must be [J][2]")
@@ -78,7 +79,9 @@ class Plan:
         self.n, self.k, self.j = n, int(n_modes), j
         self.obj_shape = (int(obj_shape[0]), int(obj_shape[1]))
         self.desc = Desc(n, self.k, j, self.obj_shape[0], self.obj_shape[1], int(stack),
-                         float(obj_inertia), float(probe_inertia), float(icalc_floor), 0)
+                         float(obj_inertia), float(probe_inertia), float(icalc_floor),
+                         FLAG_BACKGROUND if background_update else 0)
+        self.background = None
         nbytes = ctypes.c_size_t()
         check(lib().ptycho_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
@@ -106,6 +109,15 @@ class Plan:
     # -- helpers ---------------------------------------------------------
     def _enter(self):
         check(lib().ptycho_plan_set_stream(self._h, torch.cuda.current_stream(self.device).cuda_stream))
+
+    def set_background(self, bg: Optional[torch.Tensor]) -> None:
+        """Incoherent background float32 [N][N] (FFT order) used by every later
+        call, or None.  The plan keeps a reference; AP cycles with
+        UPDATE_BACKGROUND refine it in place."""
+        if bg is not None:
+            _need(bg, "background", torch.float32, (self.n, self.n), self.device)
+        check(lib().ptycho_plan_set_background(self._h, _ptr(bg) if bg is not None else None))
+        self.background = bg
 
     def _op(self, obj, probe):
         _need(obj, "obj", torch.complex64, self.obj_shape, self.device)

@@ -90,7 +90,7 @@ def workload(name: str) -> Workload:
 def make_rng(seed: int, stream: str) -> np.random.Generator:
     """Independent generator per (seed, stream) so streams never interleave."""
     keys = {"object": 0, "probe": 1, "positions": 2, "noise": 3, "mask": 4,
-            "start": 5, "serve": 6}
+            "start": 5, "serve": 6, "background": 7}
     ss = np.random.SeedSequence([int(seed), keys[stream]])
     return np.random.Generator(np.random.PCG64(ss))
 
@@ -173,6 +173,21 @@ def gap_mask(n: int, frac: float, seed: int) -> Optional[np.ndarray]:
         else:
             m[start:start + 6, :] = 1     # horizontal band
     return np.ascontiguousarray(np.fft.ifftshift(m))
+
+
+def background(n: int, level: float, seed: int) -> np.ndarray:
+    """Incoherent background float64 [N][N] in FFT order: a diffuse profile
+    1 / (1 + (r / (N/8))^2) about the detector centre times a smooth 0.8-1.2
+    random factor, scaled to a mean of `level` photons per pixel."""
+    rng = make_rng(seed, "background")
+    y, x = np.mgrid[0:n, 0:n] - n // 2
+    prof = 1.0 / (1.0 + (np.hypot(y, x) / (n / 8.0)) ** 2)
+    noise = rng.standard_normal((n, n))
+    k = np.fft.fftfreq(n)
+    noise = np.fft.ifft2(np.fft.fft2(noise) * np.exp(-(k[:, None] ** 2 + k[None, :] ** 2) * (n / 4.0) ** 2)).real
+    noise = 1.0 + 0.2 * noise / max(np.abs(noise).max(), 1e-12)
+    bg = prof * noise
+    return np.ascontiguousarray(np.fft.ifftshift(bg * (level / bg.mean())))
 
 
 def probe_photon_scale(obj: np.ndarray, probe: np.ndarray,

@@ -25,15 +25,19 @@ class Problem:
     mask: Optional[np.ndarray]
     obj0: np.ndarray
     probe0: np.ndarray
+    bg_true: Optional[np.ndarray] = None   # incoherent background in the data
+    bg0: Optional[np.ndarray] = None       # its starting estimate
 
 
-def make_problem(wl: synth.Workload, start: str = "apdm", noiseless: bool = False) -> Problem:
+def make_problem(wl: synth.Workload, start: str = "apdm", noiseless: bool = False,
+                 bg_level: float = 0.0) -> Problem:
     obj = synth.object_truth(wl.obj_shape, wl.seed)
     probe = synth.probe_modes(wl.n, wl.n_modes, wl.seed)
     pos = synth.spiral_positions(wl.n_frames, wl.step)
     offs = oracle.offsets_from_positions(pos, wl.n, wl.obj_shape)
     probe = probe * synth.probe_photon_scale(obj, probe, offs, wl.photons)
-    inten = oracle.simulate_intensity(obj, probe, offs)
+    bg = synth.background(wl.n, bg_level, wl.seed) if bg_level > 0 else None
+    inten = oracle.simulate_intensity(obj, probe, offs, bg=bg)
     iobs = inten.astype(np.float32) if noiseless else synth.poisson_counts(inten, wl.seed)
     mask = synth.gap_mask(wl.n, wl.mask_frac, wl.seed)
     if start == "ml":
@@ -48,7 +52,10 @@ def make_problem(wl: synth.Workload, start: str = "apdm", noiseless: bool = Fals
     # same rounded values promoted to float64
     o0 = o0.astype(np.complex64).astype(np.complex128)
     p0 = p0.astype(np.complex64).astype(np.complex128)
-    return Problem(wl, obj, probe, offs, iobs, mask, o0, p0)
+    bg0 = None
+    if bg is not None:
+        bg0 = (0.7 * bg).astype(np.float32).astype(np.float64)     # 30% low at every start
+    return Problem(wl, obj, probe, offs, iobs, mask, o0, p0, bg, bg0)
 
 
 def small(name: str, n=None, k=None, j=None, obj=None, step=None, mask_frac=None, photons=None, seed_offset=0):

@@ -363,3 +363,87 @@ def test_poisson_llk_autograd_matches_finite_differences_and_oracle(dev):
             e.flat[i] = h
             fd = complex((f(x0 + e) - f(x0 - e)) / (2 * h), (f(x0 + 1j * e) - f(x0 - 1j * e)) / (2 * h))
             assert abs(g.flat[i] - fd) <= 1e-3 * abs(g).max(), (i, g.flat[i], fd)
+
+
+# ---------------------------------------------------------- background ----
+def _bg_problem(n=64, k=2, j=50, bg_level=5.0, start="ml"):
+    side = max(256, 2 * n + 64)
+    wl = small("dm256", n=n, k=k, j=j, obj=(side, side), step=max(2.0, n / 16), mask_frac=0.03)
+    return make_problem(wl, start=start, bg_level=bg_level)
+
+
+@pytest.mark.parametrize("n,k", [(64, 2), (256, 3)])
+def test_background_in_every_operator_matches_oracle(dev, n, k):
+    pb = _bg_problem(n, k, j=40 if n == 64 else 12)
+    say(f"background: icalc/llk/grad/dm n={n} k={k}")
+    plan = make_plan(pb, dev)
+    bg = to_dev(pb.bg0, dev, torch.float32)
+    plan.set_background(bg)
+    o, p = state(pb, dev)
+    ic = host(plan.icalc(o, p))
+    assert rel_l2(ic, oracle.simulate_intensity(pb.obj0, pb.probe0, pb.offsets, bg=pb.bg0)) < 1e-5
+    for model in oracle.LLK_MODELS:
+        llk = host(plan.llk(o, p, model=model))
+        ref, _ = oracle.llk(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, model=model, bg=pb.bg0)
+        assert abs(llk[0] - ref) <= 1e-4 * abs(ref), model
+    go, gp, _ = plan.ml_grad(o, p)
+    ro, rp, _ = oracle.ml_grad(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, bg=pb.bg0)
+    assert rel_l2(host(go), ro) < 1e-4 and rel_l2(host(gp), rp) < 1e-4
+    d_o, d_p = (pb.obj0 * 0.01j).astype(np.complex64), (pb.probe0 * 0.02).astype(np.complex64)
+    c = host(plan.ml_linesearch(o, p, to_dev(d_o, dev, torch.complex64), to_dev(d_p, dev, torch.complex64)))
+    l1, l2 = oracle.linesearch_coefs(pb.obj0, pb.probe0, d_o.astype(np.complex128), d_p.astype(np.complex128),
+                                     pb.offsets, pb.iobs, pb.mask, bg=pb.bg0)
+    assert abs(c[0] - l1) <= 1e-4 * abs(l1) and abs(c[1] - l2) <= 1e-4 * abs(l2)
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 1, UPD)
+    psi0 = oracle.psi_init(pb.obj0, pb.probe0, pb.offsets)
+    ro, rp, rpsi = oracle.dm_cycle(pb.obj0, pb.probe0, psi0, pb.offsets, pb.iobs, pb.mask, bg=pb.bg0)
+    assert rel_l2(host(o), ro) < 1e-4 and rel_l2(host(p), rp) < 1e-4 and rel_l2(host(psi), rpsi) < 1e-4
+    # the background is only read
+    assert np.array_equal(host(bg), pb.bg0)
+
+
+@pytest.mark.parametrize("n,k,stack,cycles,start", [(64, 2, 0, 1, "ml"), (64, 1, 7, 1, "ml"), (128, 3, 0, 5, "ml"),
+                                                    (64, 2, 0, 3, "truth")])
+def test_ap_background_refinement_matches_oracle(dev, n, k, stack, cycles, start):
+    from paper_2008_11511_amd import Plan, UPDATE_BACKGROUND
+    pb = _bg_problem(n, k, j=45 if n == 64 else 30, bg_level=5.0 if start == "ml" else 100.0, start=start)
+    say(f"AP background refinement n={n} k={k} stack={stack} cycles={cycles} start={start}")
+    iobs = to_dev(pb.iobs, dev, torch.float32)
+    mask = to_dev(pb.mask, dev, torch.uint8)
+    plan = Plan(pb.offsets, iobs, mask, k, pb.wl.obj_shape, stack=stack, background_update=True)
+    bg = to_dev(pb.bg0, dev, torch.float32)
+    plan.set_background(bg)
+    o, p = state(pb, dev)
+    plan.ap_cycle(o, p, cycles, UPD | UPDATE_BACKGROUND)
+    ro, rp, rb = pb.obj0, pb.probe0, pb.bg0
+    for _ in range(cycles):
+        ro, rp, rb = oracle.ap_cycle(ro, rp, pb.offsets, pb.iobs, pb.mask, UPD | oracle.UPDATE_BACKGROUND, bg=rb)
+    tol = 1e-4 if cycles == 1 else 1e-3
+    assert rel_l2(host(bg), rb) < tol
+    assert rel_l2(host(o), ro) < tol and rel_l2(host(p), rp) < tol
+    if start == "truth":
+        # from the true object and probe the refinement moves the background
+        # (30% low at the start) towards the truth
+        assert rel_l2(host(bg), pb.bg_true) < rel_l2(pb.bg0, pb.bg_true) - 0.01
+
+
+def test_background_update_arguments_are_checked(dev):
+    from paper_2008_11511_amd import Plan, PtychoError, UPDATE_BACKGROUND
+    pb = _bg_problem(64, 1, j=10)
+    say("background argument checks")
+    iobs = to_dev(pb.iobs, dev, torch.float32)
+    o, p = state(pb, dev)
+    plain = Plan(pb.offsets, iobs, None, 1, pb.wl.obj_shape)
+    plain.set_background(to_dev(pb.bg0, dev, torch.float32))
+    with pytest.raises(PtychoError):           # no workspace for the refinement
+        plain.ap_cycle(o, p, 1, UPD | UPDATE_BACKGROUND)
+    flagged = Plan(pb.offsets, iobs, None, 1, pb.wl.obj_shape, background_update=True)
+    with pytest.raises(PtychoError):           # no background set
+        flagged.ap_cycle(o, p, 1, UPD | UPDATE_BACKGROUND)
+    flagged.set_background(to_dev(pb.bg0, dev, torch.float32))
+    psi = flagged.psi_init(o, p)
+    with pytest.raises(PtychoError):           # DM does not refine the background
+        flagged.dm_cycle(o, p, psi, 1, UPD | UPDATE_BACKGROUND)
+    with pytest.raises(ValueError):
+        flagged.set_background(torch.zeros((32, 32), dtype=torch.float32, device=dev))
