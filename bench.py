@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--cpu-cycles", type=int, default=2, help="DM cycles of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ml", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the LLK-fetch, noise-model, background and copy-roof figures")
     ap.add_argument("--large-cycles", default="2,5",
                     help="AP,DM cycles timed on the 4000 x 512^2 x 4-mode scan (the full chain is 20,50; "
                          "0,0 skips it)")
@@ -188,6 +190,53 @@ def main():
     llk = plan.llk(o, p).cpu().numpy()
     value = wl.n_frames * args.steps / dt
     log(f"DM: {dt / args.steps * 1e3:.3f} ms/cycle, {value:.0f} frames*cycles/s, llk/n={llk[0] / llk[1]:.4g}")
+
+    # the whole-job view with the likelihood fetched to the host every 50
+    # cycles (the paper's printing interval), and the likelihood of the three
+    # noise models and AP cycles refining an incoherent background
+    extra = {}
+    if not args.no_extra:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.dm_cycle(o, p, psi, 50, 3)
+        plan.llk(o, p).cpu()
+        extra["dm_ms_per_cycle_with_llk_fetch_every_50"] = round((time.perf_counter() - t0) / 50 * 1e3, 4)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        llk_ms = {}
+        for model in ("poisson", "gaussian", "euclidean"):
+            plan.llk(o, p, model=model)
+            ev0.record()
+            for _ in range(5):
+                plan.llk(o, p, model=model)
+            ev1.record()
+            torch.cuda.synchronize()
+            llk_ms[model] = round(ev0.elapsed_time(ev1) / 5, 4)
+        extra["llk_ms_per_call"] = llk_ms
+        bgp = P.Plan(offs, iobs, mask, wl.n_modes, wl.obj_shape, background_update=True)
+        bgt = torch.full((wl.n, wl.n), 1.0, dtype=torch.float32, device=dev)       # one photon per pixel
+        bgp.set_background(bgt)
+        psi_ap = torch.empty_like(psi)
+        for upd, name in ((3, "ap_ms_per_cycle"), (7, "ap_with_background_refinement_ms_per_cycle")):
+            bgp.ap_cycle(o, p, 1, upd, psi=psi_ap)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bgp.ap_cycle(o, p, 5, upd, psi=psi_ap)
+            torch.cuda.synchronize()
+            extra[name] = round((time.perf_counter() - t0) / 5 * 1e3, 4)
+        del bgp, psi_ap
+        # practical roof: a plain 1 GiB device-to-device copy
+        a_ = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b_ = torch.empty_like(a_)
+        a_.fill_(1.0)
+        b_.copy_(a_)
+        ev0.record()
+        for _ in range(5):
+            b_.copy_(a_)
+        ev1.record()
+        torch.cuda.synchronize()
+        extra["copy_GBs_read_plus_write"] = round(2 * (1 << 30) * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+        del a_, b_
+        log(f"extra: {extra}")
 
     nstacks = math.ceil(wl.n_frames / plan.stack)
     algo = algorithmic_bytes(wl, nstacks, "dm")
@@ -351,6 +400,7 @@ def main():
         "cycle_roofline": whole,
         "kernels": kernels,
         "ml": ml,
+        "extra": extra or None,
         "large": large,
         "serve": serve,
         "cpu_baseline": cpu,
