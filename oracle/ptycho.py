@@ -44,6 +44,7 @@ __all__ = [
     "CGState", "ml_cycle", "simulate_intensity", "UPDATE_OBJECT",
     "UPDATE_PROBE", "UPDATE_BACKGROUND", "DEFAULT_EPS", "DEFAULT_INERTIA",
     "model_intensity", "projection_scale", "background_update",
+    "object_gradient", "position_shifts", "update_positions",
 ]
 
 UPDATE_OBJECT = 1
@@ -453,6 +454,66 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
     state.zg = zg
     state.history.append(lsum)
     return obj + gamma * d_o, probe + gamma * d_p
+
+
+# --------------------------------------------------------------------------
+# Position refinement (operator Psi2PosShift; Section 4, after Odstrcil et
+# al. 2018)
+# --------------------------------------------------------------------------
+
+def object_gradient(obj):
+    """(dO/dy, dO/dx) on the object grid: centred differences inside,
+    one-sided differences on the object's border (numpy.gradient)."""
+    o = np.asarray(obj, dtype=np.complex128)
+    return np.gradient(o, axis=0), np.gradient(o, axis=1)
+
+
+def position_shifts(obj, probe, psi, offsets):
+    """Shift of every frame's illumination position from its exit waves.
+
+    A frame whose true position is r_j + d has exit waves
+    P_k O(r + r_j + d) ~ P_k O_j + d . P_k grad O_j, so the difference
+    chi_jk = Psi_jk - P_k O_j between the given exit waves and the current
+    views is fitted by least squares in the two components of d together
+    (reading: the gradient-based shift of Odstrcil et al. 2018 solved as one
+    2x2 system, since the y and x gradients of a small window correlate):
+      [S_yy S_yx] [d_y]   [sum Re(conj(G_y) chi)]
+      [S_xy S_xx] [d_x] = [sum Re(conj(G_x) chi)],  S_ab = sum Re(conj(G_a) G_b)
+    with G_a = P_k dO/da over frame j's window and the sums over modes and
+    pixels (d = 0 when the system is singular).  Also returns the frame's
+    gradient energy e_j = S_yy + S_xx, by which frames with too little
+    object contrast are left in place.
+    Returns (shifts [J][2] as (dy, dx) in pixels, e [J])."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    probe = np.asarray(probe, dtype=np.complex128)
+    psi = np.asarray(psi, dtype=np.complex128)
+    gy, gx = object_gradient(obj)
+    n = probe.shape[-1]
+    shifts = np.zeros((len(offsets), 2))
+    energy = np.zeros(len(offsets))
+    for j, (oy, ox) in enumerate(offsets):
+        win = (slice(oy, oy + n), slice(ox, ox + n))
+        chi = psi[j] - probe * obj[win][None]
+        g = [probe * gy[win][None], probe * gx[win][None]]
+        a = np.array([[float((np.conj(g[r]) * g[c]).real.sum()) for c in range(2)] for r in range(2)])
+        b = np.array([float((np.conj(g[r]) * chi).real.sum()) for r in range(2)])
+        det = a[0, 0] * a[1, 1] - a[0, 1] * a[1, 0]
+        if det > 1e-12 * a[0, 0] * a[1, 1] and det > 0:
+            shifts[j] = np.linalg.solve(a, b)
+        energy[j] = a[0, 0] + a[1, 1]
+    return shifts, energy
+
+
+def update_positions(pos, pos0, shifts, energy, mult=1.0, max_shift=2.0, min_grad=0.1):
+    """New positions pos + mult * shift, where frames whose gradient energy
+    is below min_grad times the median energy are not moved (the filter the
+    paper adds against low object contrast), and the total move from the
+    starting positions pos0 is clipped to +-max_shift pixels per axis."""
+    pos = np.asarray(pos, dtype=np.float64)
+    pos0 = np.asarray(pos0, dtype=np.float64)
+    keep = np.asarray(energy) >= min_grad * np.median(energy)
+    new = pos + mult * np.where(keep[:, None], np.asarray(shifts), 0.0)
+    return pos0 + np.clip(new - pos0, -max_shift, max_shift)
 
 
 # --------------------------------------------------------------------------

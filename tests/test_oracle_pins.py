@@ -581,3 +581,59 @@ def test_gradient_with_background_matches_central_differences():
     h = 1e-3
     assert l1 == pytest.approx((f(h) - f(-h)) / (2 * h), rel=1e-5)
     assert l2 == pytest.approx((f(h) - 2 * f(0) + f(-h)) / (h * h), rel=1e-3)
+
+
+# ----------------------------------------------------------------------------
+# Position refinement
+# ----------------------------------------------------------------------------
+
+def _fourier_shift(a, dy, dx):
+    """a(r + d) for a periodic array, by the Fourier shift theorem."""
+    ky = np.fft.fftfreq(a.shape[0])[:, None]
+    kx = np.fft.fftfreq(a.shape[1])[None, :]
+    return np.fft.ifft2(np.fft.fft2(a) * np.exp(2j * np.pi * (ky * dy + kx * dx)))
+
+
+def test_position_shifts_recover_a_subpixel_displacement():
+    # a smooth periodic object: exit waves at r_j + d built by the Fourier
+    # shift theorem (not by the gradient) are read back as d to first order
+    rng = np.random.default_rng(21)
+    ny = nx = 96
+    k = np.fft.fftfreq(ny)
+    filt = np.exp(-(k[:, None] ** 2 + k[None, :] ** 2) * (ny / 6.0) ** 2)
+
+    def field():
+        f = np.fft.ifft2(np.fft.fft2(rng.standard_normal((ny, nx))) * filt).real
+        return f / f.std()
+    # phase of 1 rad rms and 10% amplitude modulation, correlated over ~10 px,
+    # so that centred differences are close to the derivative
+    o = np.exp(1j * field()) * (1.0 + 0.1 * field())
+    n = 32
+    y, x = np.mgrid[0:n, 0:n] - n / 2
+    p = np.exp(-(x ** 2 + y ** 2) / (2 * 6.0 ** 2))[None].astype(complex)
+    offs = np.array([[20, 24], [40, 30], [32, 50]], np.int32)
+    d = np.array([[0.15, -0.1], [-0.2, 0.05], [0.0, 0.2]])
+    psi = np.zeros((3, 1, n, n), complex)
+    for j, ((oy, ox), (dy, dx)) in enumerate(zip(offs, d)):
+        psi[j, 0] = p[0] * _fourier_shift(o, dy, dx)[oy:oy + n, ox:ox + n]
+    sh, e = oracle.position_shifts(o, p, psi, offs)
+    np.testing.assert_allclose(sh, d, atol=0.01)
+    assert (e > 0).all()
+    # the current views themselves give no shift
+    sh0, _ = oracle.position_shifts(o, p, oracle.exit_waves(o, p, offs), offs)
+    assert np.abs(sh0).max() < 1e-12
+
+
+def test_flat_object_gives_no_shift_and_update_rules():
+    o = np.full((40, 40), 0.7 + 0.2j)
+    p = crandn(2, 8, 8, rng=np.random.default_rng(2))
+    offs = np.array([[3, 5], [20, 11]], np.int32)
+    psi = oracle.exit_waves(o, p, offs) * 1.3
+    sh, e = oracle.position_shifts(o, p, psi, offs)
+    assert not sh.any() and not e.any()
+    pos0 = np.zeros((4, 2))
+    pos = np.array([[0.5, 0.0], [1.9, -1.0], [0.0, 0.0], [-1.5, 0.3]])
+    shifts = np.array([[0.2, 0.1], [0.5, 0.0], [1.0, 1.0], [-1.0, 0.2]])
+    energy = np.array([1.0, 1.0, 0.01, 1.0])
+    new = oracle.update_positions(pos, pos0, shifts, energy, mult=1.0, max_shift=2.0, min_grad=0.1)
+    np.testing.assert_allclose(new, [[0.7, 0.1], [2.0, -1.0], [0.0, 0.0], [-2.0, 0.5]])
