@@ -212,6 +212,14 @@ def main():
             torch.cuda.synchronize()
             llk_ms[model] = round(ev0.elapsed_time(ev1) / 5, 4)
         extra["llk_ms_per_call"] = llk_ms
+        # position refinement: shifts of all frames from the stored exit waves
+        plan.position_shifts(o, p, psi)
+        ev0.record()
+        for _ in range(5):
+            plan.position_shifts(o, p, psi)
+        ev1.record()
+        torch.cuda.synchronize()
+        extra["position_shifts_ms_per_call"] = round(ev0.elapsed_time(ev1) / 5, 4)
         bgp = P.Plan(offs, iobs, mask, wl.n_modes, wl.obj_shape, background_update=True)
         bgt = torch.full((wl.n, wl.n), 1.0, dtype=torch.float32, device=dev)       # one photon per pixel
         bgp.set_background(bgt)

@@ -133,6 +133,21 @@ int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
  * augmented projections the paper cites for AP background optimisation). */
 int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
 
+/* Position refinement (operator Psi2PosShift, Section 4, after Odstrcil et
+ * al. 2018): for every frame j, the shift d of its illumination position
+ * that best explains the exit waves psi_dev (complex[J][K][N][N], e.g. the
+ * projected ones an AP cycle leaves) against the current views:
+ *   chi = Psi_jk - P_k O_j ~ d_y P_k dO/dy + d_x P_k dO/dx,
+ * the two components solved together by least squares over the frame's
+ * pixels and modes (d = 0 if the 2x2 system is singular), the gradient by
+ * centred differences on the object (one-sided on its border).
+ * out_dev: double[J][3] device, per frame (d_y, d_x, gradient energy
+ * S_yy + S_xx) in pixels, frames in scan order.  The caller moves the
+ * positions (the paper's filter leaves frames of low gradient energy in
+ * place) and builds a plan from the new offsets. */
+int ptycho_position_shifts(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
+                           const float *psi_dev, double *out_dev);
+
 /* Change the stream later calls enqueue on (hipStream_t). */
 int ptycho_plan_set_stream(ptycho_plan_t plan, void *stream);
 

@@ -328,6 +328,73 @@ __global__ __launch_bounds__(256) void k_bg_finish(float *bg, const double *bsum
         bg[i] = (float)((double)bg[i] * (bsum[i] / J));
 }
 
+// Position refinement (Psi2PosShift): block j accumulates, over frame j's
+// pixels and modes, the 2x2 least-squares system of its position shift,
+// chi = Psi - P O ~ d_y P dO/dy + d_x P dO/dx, with the object gradient by
+// centred differences (one-sided on the object's border), and writes
+// out[j] = (d_y, d_x, S_yy + S_xx).
+struct PosShiftArgs {
+    int N, K, Ny, Nx;
+    const int2 *offs;             // [J] (oy, ox)
+    const float2 *obj, *probe, *psi;
+    double *out;                  // [J][3]
+};
+
+__device__ __forceinline__ float2 obj_diff(const float2 *o, int i, int lo_step, int hi_step, bool at_lo,
+                                           bool at_hi) {
+    if (at_lo) return csub(o[i + hi_step], o[i]);
+    if (at_hi) return csub(o[i], o[i - lo_step]);
+    return cscale(csub(o[i + hi_step], o[i - lo_step]), 0.5f);
+}
+
+__global__ __launch_bounds__(256) void k_pos_shift(PosShiftArgs a) {
+    const int j = blockIdx.x, N = a.N;
+    const int2 o = a.offs[j];
+    const long n2 = (long)N * N;
+    double syy = 0.0, sxx = 0.0, sxy = 0.0, by = 0.0, bx = 0.0;
+    for (long idx = threadIdx.x; idx < n2; idx += 256) {
+        const int y = (int)(idx / N), x = (int)(idx % N);
+        const int Y = o.x + y, X = o.y + x;
+        const int i = Y * a.Nx + X;
+        const float2 ov = a.obj[i];
+        const float2 gy = obj_diff(a.obj, i, a.Nx, a.Nx, Y == 0, Y == a.Ny - 1);
+        const float2 gx = obj_diff(a.obj, i, 1, 1, X == 0, X == a.Nx - 1);
+        float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
+        for (int k = 0; k < a.K; ++k) {
+            const float2 p = a.probe[k * n2 + idx];
+            const float2 ps = a.psi[((size_t)j * a.K + k) * n2 + idx];
+            const float2 chi = csub(ps, cmul(p, ov));
+            const float2 Gy = cmul(p, gy), Gx = cmul(p, gx);
+            fyy += cnorm(Gy);
+            fxx += cnorm(Gx);
+            fxy += cmulc(Gy, Gx).x;
+            fby += cmulc(Gy, chi).x;
+            fbx += cmulc(Gx, chi).x;
+        }
+        syy += fyy;
+        sxx += fxx;
+        sxy += fxy;
+        by += fby;
+        bx += fbx;
+    }
+    syy = block_sum(syy);
+    sxx = block_sum(sxx);
+    sxy = block_sum(sxy);
+    by = block_sum(by);
+    bx = block_sum(bx);
+    if (threadIdx.x == 0) {
+        const double det = syy * sxx - sxy * sxy;
+        double dy = 0.0, dx = 0.0;
+        if (det > 0.0 && det > 1e-12 * syy * sxx) {
+            dy = (sxx * by - sxy * bx) / det;
+            dx = (syy * bx - sxy * by) / det;
+        }
+        a.out[3 * j] = dy;
+        a.out[3 * j + 1] = dx;
+        a.out[3 * j + 2] = syy + sxx;
+    }
+}
+
 // dst = J * (number of mask pixels equal to 0); every pixel if mask is null.
 __global__ __launch_bounds__(256) void k_count_good(const unsigned char *mask, int n2, double J, double *dst) {
     double c = 0.0;

@@ -996,6 +996,27 @@ extern "C" int ptycho_llk_model(ptycho_plan_t p, const float *obj, const float *
     return llk_into(p, obj, probe, llk, model);
 }
 
+extern "C" int ptycho_position_shifts(ptycho_plan_t p, const float *obj, const float *probe, const float *psi,
+                                      double *out) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!psi || !out) return fail(PTYCHO_E_INVALID, "null psi or output");
+    PosShiftArgs a{};
+    a.N = p->d.n;
+    a.K = p->d.n_modes;
+    a.Ny = p->d.obj_ny;
+    a.Nx = p->d.obj_nx;
+    a.offs = p->offs;
+    a.obj = (const float2 *)obj;
+    a.probe = (const float2 *)probe;
+    a.psi = (const float2 *)psi;
+    a.out = out;
+    Timed tm(p, TC_OTHER);
+    hipLaunchKernelGGL(k_pos_shift, dim3(p->d.n_frames), dim3(256), 0, p->stream, a);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
 extern "C" int ptycho_icalc(ptycho_plan_t p, const float *obj, const float *probe, float *icalc) {
     int st = check_plan_ptrs(p, obj, probe);
     if (st) return st;

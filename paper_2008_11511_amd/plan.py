@@ -39,6 +39,34 @@ def offsets_from_positions(pos_yx, n: int, obj_shape) -> np.ndarray:
     return out
 
 
+def update_positions(pos, pos0, shifts, energy, mult: float = 1.0, max_shift: float = 2.0,
+                     min_grad: float = 0.1) -> np.ndarray:
+    """Move scan positions (float [J][2], pixels) by mult * shift, except the
+    frames whose gradient energy is below min_grad times the median energy
+    (too little object contrast to tell a shift); the total move from the
+    starting positions pos0 is clipped to +-max_shift per axis."""
+    pos = np.asarray(pos, dtype=np.float64)
+    pos0 = np.asarray(pos0, dtype=np.float64)
+    energy = np.asarray(energy, dtype=np.float64)
+    keep = energy >= min_grad * np.median(energy)
+    new = pos + mult * np.where(keep[:, None], np.asarray(shifts, dtype=np.float64), 0.0)
+    return pos0 + np.clip(new - pos0, -max_shift, max_shift)
+
+
+def refine_positions(plan: "Plan", obj, probe, psi, pos, pos0, mult: float = 1.0, max_shift: float = 2.0,
+                     min_grad: float = 0.1):
+    """One position-refinement step after a cycle that left exit waves in psi:
+    shifts on the GPU, the position update on the host, and a plan rebuilt
+    on the new offsets when any frame moved to another pixel.
+    Returns (plan, new positions, new offsets)."""
+    res = plan.position_shifts(obj, probe, psi).cpu().numpy()
+    new = update_positions(pos, pos0, res[:, :2], res[:, 2], mult, max_shift, min_grad)
+    offs = offsets_from_positions(new, plan.n, plan.obj_shape)
+    if not np.array_equal(offs, plan.offsets):
+        plan = plan.rebuild(offs)
+    return plan, new, offs
+
+
 def fft2(x: torch.Tensor, inverse: bool = False) -> torch.Tensor:
     """Unitary batched 2D FFT over the last two axes (in place on a copy)."""
     if x.dtype != torch.complex64 or not x.is_cuda:
@@ -229,6 +257,30 @@ class Plan:
             check(lib().ptycho_plan_timing_read(self._h, i, ctypes.byref(ms), ctypes.byref(n)))
             out[name] = (float(ms.value), int(n.value))
         return out
+
+    def position_shifts(self, obj, probe, psi, out=None):
+        """Device double [J][3]: per frame (d_y, d_x, gradient energy) of the
+        position refinement (Psi2PosShift) from exit waves psi."""
+        self._op(obj, probe)
+        _need(psi, "psi", torch.complex64, (self.j, self.k, self.n, self.n), self.device)
+        out = torch.empty((self.j, 3), dtype=torch.float64, device=self.device) if out is None else out
+        _need(out, "shifts", torch.float64, (self.j, 3), self.device)
+        self._enter()
+        check(lib().ptycho_position_shifts(self._h, _ptr(obj), _ptr(probe), _ptr(psi), _ptr(out)))
+        return out
+
+    def rebuild(self, offsets) -> "Plan":
+        """A plan on the same data, workspace and background with new frame
+        offsets (after the positions moved).  This plan must not be used
+        afterwards: the new one owns the workspace."""
+        d = self.desc
+        new = Plan(offsets, self.iobs, self.mask, self.k, self.obj_shape, stack=d.stack,
+                   obj_inertia=d.obj_inertia, probe_inertia=d.probe_inertia, icalc_floor=d.icalc_floor,
+                   workspace=self.workspace, background_update=bool(d.flags & FLAG_BACKGROUND))
+        if self.background is not None:
+            new.set_background(self.background)
+        self.close()
+        return new
 
     def icalc(self, obj, probe, out=None):
         self._op(obj, probe)

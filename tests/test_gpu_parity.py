@@ -447,3 +447,68 @@ def test_background_update_arguments_are_checked(dev):
         flagged.dm_cycle(o, p, psi, 1, UPD | UPDATE_BACKGROUND)
     with pytest.raises(ValueError):
         flagged.set_background(torch.zeros((32, 32), dtype=torch.float32, device=dev))
+
+
+# ------------------------------------------------ position refinement ----
+def test_position_shifts_match_oracle(dev):
+    from paper_2008_11511_amd import Plan
+    wl = small("dm256", n=64, k=2, j=30, obj=(256, 256), step=5.0, mask_frac=0.03)
+    pb = make_problem(wl, start="ml")
+    # two more frames on the object's corners: one-sided gradients there
+    offs = np.concatenate([pb.offsets, [[0, 0], [256 - 64, 256 - 64]]]).astype(np.int32)
+    say("position shifts vs oracle, 32 frames incl. corners")
+    o64 = pb.obj0.astype(np.complex64)
+    p64 = pb.probe0.astype(np.complex64)
+    # exit waves from the oracle's projection of perturbed views
+    psi = oracle.fourier_project(oracle.exit_waves(pb.obj_true, pb.probe_true, offs) * 1.02,
+                                 oracle.simulate_intensity(pb.obj_true, pb.probe_true, offs), pb.mask)
+    psi64 = psi.astype(np.complex64)
+    ref, e_ref = oracle.position_shifts(o64.astype(np.complex128), p64.astype(np.complex128),
+                                        psi64.astype(np.complex128), offs)
+    iobs = torch.zeros((len(offs), 64, 64), dtype=torch.float32, device=dev)
+    plan = Plan(offs, iobs, None, 2, wl.obj_shape)
+    got = host(plan.position_shifts(to_dev(o64, dev, torch.complex64), to_dev(p64, dev, torch.complex64),
+                                    to_dev(psi64, dev, torch.complex64)))
+    scale = np.abs(ref).max()
+    assert scale > 0.05
+    assert np.abs(got[:, :2] - ref).max() <= 1e-4 * scale
+    np.testing.assert_allclose(got[:, 2], e_ref, rtol=1e-5)
+
+
+def test_position_refinement_follows_oracle(dev):
+    from paper_2008_11511_amd import Plan
+    from paper_2008_11511_amd.plan import refine_positions
+    wl = small("dm256", n=64, k=1, j=60, obj=(256, 256), step=5.0, mask_frac=0.0)
+    pb = make_problem(wl, start="truth")
+    pos_true = synth.spiral_positions(wl.n_frames, wl.step)
+    off_true = oracle.offsets_from_positions(pos_true, wl.n, wl.obj_shape)
+    rng = np.random.default_rng(1)
+    err = np.zeros_like(pos_true)
+    sel = rng.random(len(pos_true)) < 0.4
+    err[sel] = rng.choice([-0.4, 0.4], size=(sel.sum(), 2))
+    pos0 = pos_true + err
+    say("position refinement: 2 AP cycles with position updates")
+    # oracle
+    pos, o, p = pos0.copy(), pb.obj0, pb.probe0
+    for _ in range(2):
+        offs = oracle.offsets_from_positions(pos, wl.n, wl.obj_shape)
+        psi = oracle.fourier_project(oracle.exit_waves(o, p, offs), pb.iobs, pb.mask)
+        o, p = oracle.overlap_update(o, p, psi, offs, UPD)
+        sh, e = oracle.position_shifts(o, p, psi, offs)
+        pos = oracle.update_positions(pos, pos0, sh, e)
+    # GPU
+    gpos = pos0.copy()
+    plan = Plan(oracle.offsets_from_positions(gpos, wl.n, wl.obj_shape), to_dev(pb.iobs, dev, torch.float32), None,
+                1, wl.obj_shape)
+    go, gp = state(pb, dev)
+    psi_d = torch.empty((wl.n_frames, 1, 64, 64), dtype=torch.complex64, device=dev)
+    start_off = plan.offsets.copy()
+    for _ in range(2):
+        plan.ap_cycle(go, gp, 1, UPD, psi=psi_d)
+        plan, gpos, goffs = refine_positions(plan, go, gp, psi_d, gpos, pos0)
+    assert not np.array_equal(start_off, goffs)          # some frames moved to another pixel
+    assert np.abs(gpos - pos).max() < 1e-3
+    np.testing.assert_array_equal(goffs, oracle.offsets_from_positions(pos, wl.n, wl.obj_shape))
+    wrong0 = int((start_off != off_true).any(axis=1).sum())
+    wrong = int((goffs != off_true).any(axis=1).sum())
+    assert wrong < wrong0
