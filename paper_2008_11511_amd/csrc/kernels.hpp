@@ -419,10 +419,18 @@ __global__ __launch_bounds__(256) void k_probe_intensity(const float2 *probe, in
 // views alone, without reading the old exit waves again.
 enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4, OP_CORR = 5 };
 
+// Waves per SIMD a column kernel is compiled for: the DM form with up to 3
+// modes fits 128 registers without spilling, which gives 4 waves instead of
+// 3 (measured faster); the others keep the compiler's choice.
+template <int N, int K, int OP>
+struct ColMinWaves {
+    static constexpr int value = (ColJoint<N, K>::SEQ && N <= 256 && K <= 3 && OP == OP_CORR) ? 4 : 1;
+};
+
 // Column FFTs of all K modes held together in registers, the Fourier-space
 // step and (project / grad) the inverse column FFTs, written back in place.
 template <int N, int K, int OP>
-__global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a) {
+__global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP>::value)) void k_cols_joint(StackArgs a) {
     using G = ColGeom<N>;
     constexpr int E = G::E, CB = G::CB;
     extern __shared__ float2 lds_dyn[];
@@ -449,14 +457,13 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
     // the data of the pixels this thread will own after the transform are
     // loaded now: loads cannot move across the transform's barriers
     const float *io = a.iobs + (size_t)j * N * N + c;
-    float iobv[E], bgv[E];
+    float iobv[E];
     bool badv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = out_index<N, E, -1>(t, e);
         iobv[e] = io[(size_t)q * N];
         badv[e] = a.mask != nullptr && a.mask[q * N + c] != 0;
-        bgv[e] = a.bg != nullptr ? a.bg[q * N + c] : 0.0f;
     }
     if constexpr (SEQ) {
 #pragma unroll
@@ -471,7 +478,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_joint(StackArgs a)
         float inten = 0.0f;
 #pragma unroll
         for (int k = 0; k < K; ++k) inten += cnorm(u[k][e]);
-        inten = inten * inv_n2 + bgv[e];
+        // the background (L2-resident, usually absent) is read here rather
+        // than with Iobs, so that it holds no registers across the transform
+        inten = inten * inv_n2 + (a.bg != nullptr ? a.bg[out_index<N, E, -1>(t, e) * N + c] : 0.0f);
         const bool bad = badv[e];
         const float iob = iobv[e];
         float sc;
