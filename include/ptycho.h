@@ -148,6 +148,12 @@ int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
 int ptycho_position_shifts(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                            const float *psi_dev, double *out_dev);
 
+/* Failure detection: flag_dev (int32[1], device) is set to 1 if any value
+ * of the object or probe is NaN or infinite, else 0 (enqueued, so a caller
+ * can copy the flag back and read it at its next poll without waiting). */
+int ptycho_check_finite(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
+                        int32_t *flag_dev);
+
 /* Change the stream later calls enqueue on (hipStream_t). */
 int ptycho_plan_set_stream(ptycho_plan_t plan, void *stream);
 

@@ -45,6 +45,7 @@ _SIGS = {
     "ptycho_plan_set_stream": [_P, _P],
     "ptycho_plan_set_background": [_P, _P],
     "ptycho_position_shifts": [_P, _P, _P, _P, _P],
+    "ptycho_check_finite": [_P, _P, _P, _P],
     "ptycho_plan_stack": [_P, ctypes.POINTER(ctypes.c_int32)],
     "ptycho_plan_destroy": [_P],
     "ptycho_ap_cycle": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_uint32],

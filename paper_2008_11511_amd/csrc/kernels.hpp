@@ -395,6 +395,15 @@ __global__ __launch_bounds__(256) void k_pos_shift(PosShiftArgs a) {
     }
 }
 
+// flag[0] = 1 if any of a[0 .. n) is not finite (flag cleared beforehand;
+// every writer stores the same value).
+__global__ __launch_bounds__(256) void k_check_finite(const float *a, long n, int *flag) {
+    bool bad = false;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) bad |= !isfinite(a[i]);
+    if (bad) flag[0] = 1;
+}
+__global__ void k_clear_flag(int *flag) { flag[0] = 0; }
+
 // dst = J * (number of mask pixels equal to 0); every pixel if mask is null.
 __global__ __launch_bounds__(256) void k_count_good(const unsigned char *mask, int n2, double J, double *dst) {
     double c = 0.0;

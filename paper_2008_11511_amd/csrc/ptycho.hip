@@ -1017,6 +1017,19 @@ extern "C" int ptycho_position_shifts(ptycho_plan_t p, const float *obj, const f
     return PTYCHO_OK;
 }
 
+extern "C" int ptycho_check_finite(ptycho_plan_t p, const float *obj, const float *probe, int32_t *flag) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!flag) return fail(PTYCHO_E_INVALID, "null flag");
+    const long no = 2L * p->d.obj_ny * p->d.obj_nx, np = 2L * p->d.n_modes * p->d.n * p->d.n;
+    Timed tm(p, TC_OTHER);
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, p->stream, (int *)flag);
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(no)), dim3(256), 0, p->stream, obj, no, (int *)flag);
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(np)), dim3(256), 0, p->stream, probe, np, (int *)flag);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
 extern "C" int ptycho_icalc(ptycho_plan_t p, const float *obj, const float *probe, float *icalc) {
     int st = check_plan_ptrs(p, obj, probe);
     if (st) return st;

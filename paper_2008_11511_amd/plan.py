@@ -269,6 +269,15 @@ class Plan:
         check(lib().ptycho_position_shifts(self._h, _ptr(obj), _ptr(probe), _ptr(psi), _ptr(out)))
         return out
 
+    def check_finite(self, obj, probe, out=None):
+        """Device int32 [1]: 1 if the object or probe holds a NaN or inf."""
+        self._op(obj, probe)
+        out = torch.empty(1, dtype=torch.int32, device=self.device) if out is None else out
+        _need(out, "flag", torch.int32, (1,), self.device)
+        self._enter()
+        check(lib().ptycho_check_finite(self._h, _ptr(obj), _ptr(probe), _ptr(out)))
+        return out
+
     def rebuild(self, offsets) -> "Plan":
         """A plan on the same data, workspace and background with new frame
         offsets (after the positions moved).  This plan must not be used

@@ -166,7 +166,10 @@ class Scheduler:
             for entry in list(active):
                 r, h, need = entry
                 if self.ex.finished(h):
-                    r.result = self.ex.collect(h)
+                    try:
+                        r.result = self.ex.collect(h)
+                    except Exception as e:        # the request failed on the device
+                        r.error = e
                     r.done = self.clock() - t0
                     self.ex.release(h)
                     active.remove(entry)
@@ -323,7 +326,7 @@ class GpuExecutor:
         parts = [("iobs", 4 * wl.n_frames * n2), ("psi", 8 * wl.n_frames * wl.n_modes * n2),
                  ("ws", int(ws.value)), ("state", 0), ("obj", 8 * no), ("probe", 8 * wl.n_modes * n2),
                  ("obj_t", 8 * no if synthetic else 0), ("probe_t", 8 * wl.n_modes * n2 if synthetic else 0),
-                 ("mask", n2), ("llk", 16), ("hist", 8 * max(n_ml, 1))]
+                 ("mask", n2), ("llk", 16), ("hist", 8 * max(n_ml, 1)), ("flag", 4)]
         return parts
 
     @staticmethod
@@ -412,6 +415,8 @@ class GpuExecutor:
         j.out_probe = torch.empty((k, n, n), dtype=torch.complex64, pin_memory=True)
         j.out_llk = torch.empty(2, dtype=torch.float64, pin_memory=True)
         j.out_hist = torch.empty(j.hist.shape, dtype=torch.float64, pin_memory=True)
+        j.flag_host = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        j.failed = None
         mark("pinned")
         j.phase = 0
         j.left = req.schedule[0][1]
@@ -474,6 +479,7 @@ class GpuExecutor:
             j.state = carve(self._state_bytes(j.plan), torch.uint8, (self._state_bytes(j.plan),))
             j.llk_buf = carve(16, torch.float64, (2,))
             j.hist = carve(sizes["hist"], torch.float64, (sizes["hist"] // 8,))
+            j.flag = carve(4, torch.int32, (1,))
             mark("psi_init")
 
     @staticmethod
@@ -493,8 +499,12 @@ class GpuExecutor:
 
     def advance(self, j: _Job, slot: int = 0) -> None:
         torch = self.torch
+        n_before = len(j.events)
         j.events = [e for e in j.events if not e.query()]
-        if len(j.events) >= self.depth or j.phase >= len(j.req.schedule):
+        if len(j.events) < n_before and j.flag_host[0] != 0 and j.failed is None:
+            # a chunk's check found a NaN or inf: stop this request
+            j.failed = FloatingPointError(f"request {j.req.rid}: non-finite object or probe")
+        if j.failed is not None or len(j.events) >= self.depth or j.phase >= len(j.req.schedule):
             return
         while len(self.run_streams) <= slot:
             self.run_streams.append(torch.cuda.Stream(device=self.dev))
@@ -520,6 +530,9 @@ class GpuExecutor:
                     j.phase += 1
                     if j.phase < len(j.req.schedule):
                         j.left = j.req.schedule[j.phase][1]
+                # failure detection: the flag comes back with the chunk
+                j.plan.check_finite(j.obj, j.probe, out=j.flag)
+                j.flag_host.copy_(j.flag, non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(j.stream)
                 j.events.append(ev)
@@ -534,11 +547,17 @@ class GpuExecutor:
                     j.final.record(j.stream)
 
     def finished(self, j: _Job) -> bool:
+        if j.failed is not None:
+            return j.last.query()        # nothing of it left in flight
         return j.final is not None and j.final.query()
 
     def collect(self, j: _Job) -> dict:
         """Host results: final object and probe, LLK per unmasked pixel after
         the last cycle and after each ML cycle, and set-up timing."""
+        if j.failed is not None:
+            raise j.failed
+        if j.flag_host[0] != 0:
+            raise FloatingPointError(f"request {j.req.rid}: non-finite object or probe")
         llk = j.out_llk.numpy()
         hist = j.out_hist.numpy()[:j.ml_done] / llk[1]
         return {"obj": j.out_obj.numpy(), "probe": j.out_probe.numpy(), "llk": float(llk[0] / llk[1]),
@@ -550,8 +569,8 @@ class GpuExecutor:
             setattr(j, name, None)
         if j.region is not None:
             # the region is reused by work enqueued after this point: every
-            # kernel of this request precedes its final event
-            j.final.synchronize()
+            # kernel of this request precedes its final (or, failed, last) event
+            (j.final if j.final is not None else j.last).synchronize()
             self.arena.release(*j.region)
         self.host.pop(j.req.rid, None)
 

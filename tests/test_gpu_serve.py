@@ -126,3 +126,22 @@ def test_service_refuses_a_scan_outside_the_object():
         with pytest.raises(PtychoError) as e:
             svc.submit(schedule=SCHED, **sc)
         assert e.value.code == -2
+
+
+def test_service_fails_a_diverging_request_and_serves_the_others():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_11511_amd import lib
+    from paper_2008_11511_amd.serve import ReconstructionService
+    lib()
+    say("service: one request with NaN data among good ones")
+    scans = [_scan(41, 64, 1, 40, 256, 0.0), _scan(42, 64, 2, 40, 256, 0.03), _scan(43, 64, 1, 40, 256, 0.0)]
+    scans[1]["iobs"] = scans[1]["iobs"].copy()
+    scans[1]["iobs"][3, 10, 10] = np.nan
+    with ReconstructionService() as svc:
+        futs = [svc.submit(schedule=SCHED, **sc) for sc in scans]
+        with pytest.raises(FloatingPointError):
+            futs[1].result(timeout=120)
+        good = [futs[0].result(timeout=120), futs[2].result(timeout=120)]
+    for r in good:
+        assert np.isfinite(r["obj"]).all() and np.isfinite(r["llk"])
