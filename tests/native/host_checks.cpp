@@ -1,0 +1,73 @@
+// Host-side entry points of the library exercised under AddressSanitizer and
+// UndefinedBehaviorSanitizer (built by tests/test_host_sanitizers.py with the
+// sanitizers on the host pass only; nothing here touches a GPU).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "ptycho.h"
+
+static int failures = 0;
+#define EXPECT(c)                                                               \
+    do {                                                                        \
+        if (!(c)) {                                                             \
+            std::printf("FAILED %s line %d\n", #c, __LINE__);                  \
+            ++failures;                                                         \
+        }                                                                       \
+    } while (0)
+
+static std::vector<double> spiral(int j, double step) {
+    std::vector<double> p(2 * (size_t)j);
+    for (int i = 0; i < j; ++i) {
+        const double r = step * std::sqrt((double)i), t = i * M_PI * (3.0 - std::sqrt(5.0));
+        p[2 * i] = r * std::sin(t);
+        p[2 * i + 1] = r * std::cos(t);
+    }
+    return p;
+}
+
+int main() {
+    const int sizes[][6] = {  // n, K, J, ny, nx, step*10
+        {16, 1, 37, 40, 56, 20}, {32, 2, 7, 64, 64, 30}, {64, 1, 100, 256, 256, 60},
+        {128, 3, 21, 320, 288, 80}, {256, 3, 1000, 1024, 1024, 120}, {512, 4, 500, 2048, 2048, 240}};
+    for (const auto &sz : sizes) {
+        const int n = sz[0], k = sz[1], j = sz[2], ny = sz[3], nx = sz[4];
+        std::vector<double> pos = spiral(j, sz[5] / 10.0);
+        std::vector<int32_t> offs(2 * (size_t)j, -7);
+        EXPECT(ptycho_offsets_from_positions(pos.data(), j, n, ny, nx, offs.data()) == PTYCHO_OK);
+        for (int stack : {0, 1, 3, j / 2 + 1, j}) {
+            for (uint32_t flags : {0u, (uint32_t)PTYCHO_FLAG_BACKGROUND}) {
+                ptycho_desc_t d{n, k, j, ny, nx, stack, 0.01f, 0.01f, 1e-20f, flags};
+                size_t ws = 0, tb = 0;
+                EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_OK && ws > 0 && ws % 256 == 0);
+                EXPECT(ptycho_plan_dry_run(&d, offs.data(), &tb) == PTYCHO_OK && tb > 0);
+            }
+        }
+        // a window one pixel out of the object: an error, nothing written
+        std::vector<double> bad = pos;
+        bad[0] = ny / 2.0 - n / 2.0 + 0.5;
+        std::vector<int32_t> o2(2 * (size_t)j, -7);
+        EXPECT(ptycho_offsets_from_positions(bad.data(), j, n, ny, nx, o2.data()) == PTYCHO_E_BOUNDS);
+        EXPECT(o2[0] == -7 && o2[2 * j - 1] == -7);
+        EXPECT(std::strlen(ptycho_last_error()) > 0);
+        std::vector<int32_t> o3 = offs;
+        o3[2 * (j - 1)] = ny - n + 1;
+        ptycho_desc_t d{n, k, j, ny, nx, 0, 0.01f, 0.01f, 1e-20f, 0};
+        size_t tb = 0;
+        EXPECT(ptycho_plan_dry_run(&d, o3.data(), &tb) == PTYCHO_E_BOUNDS);
+    }
+    // descriptor and argument errors
+    ptycho_desc_t d{48, 1, 10, 128, 128, 0, 0.01f, 0.01f, 1e-20f, 0};
+    size_t ws = 0;
+    EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_E_UNSUPPORTED);
+    d.n = 64;
+    d.flags = 2;
+    EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_E_INVALID);
+    d.flags = 0;
+    EXPECT(ptycho_workspace_bytes(nullptr, &ws) == PTYCHO_E_INVALID);
+    EXPECT(ptycho_plan_dry_run(&d, nullptr, &ws) == PTYCHO_E_INVALID);
+    EXPECT(ptycho_plan_set_background(nullptr, nullptr) == PTYCHO_E_INVALID);
+    std::printf("host checks: %d failures\n", failures);
+    return failures == 0 ? 0 : 1;
+}
