@@ -69,7 +69,7 @@ typedef enum {
  * background refinement (S*N*N floats and N*N doubles). */
 #define PTYCHO_FLAG_BACKGROUND 1u
 
-/* Problem description.  Supported: N in {16, 32, 64, 128, 256, 512},
+/* Problem description.  Supported: N a power of two from 8 to 1024,
  * 1 <= K <= 4, J >= 1, obj_ny >= N, obj_nx >= N. */
 typedef struct {
     int32_t n;              /* frame side N (power of two)                      */

@@ -139,20 +139,21 @@ struct Dft {
 template <int N, int E>
 struct FftCfg {
     static constexpr int T = N / E;
-    static constexpr int R0 = (N == 16) ? 16 : (N == 32) ? 8 : (N == 64) ? 8 : (N == 128) ? (E == 16 ? 16 : 8)
-                            : (N == 256) ? (E == 16 ? 16 : 8) : 8;
-    static constexpr int R1 = (N == 16) ? 1 : (N == 32) ? 4 : (N == 64) ? 8 : (N == 128) ? (E == 16 ? 8 : 4)
-                            : (N == 256) ? (E == 16 ? 16 : 8) : 8;
-    static constexpr int R2 = (N == 128) ? (E == 16 ? 1 : 4) : (N == 256) ? (E == 16 ? 1 : 4) : (N == 512) ? 8 : 1;
-    static constexpr int P = (R1 == 1) ? 1 : (R2 == 1 ? 2 : 3);
-    static_assert(R0 * R1 * R2 == N, "radices must multiply to N");
-    static_assert(E % R0 == 0 && E % R1 == 0 && E % R2 == 0, "every radix must divide E");
+    static constexpr int R0 = (N == 8) ? 8 : (N == 16) ? 16 : (N == 32) ? 8 : (N == 64) ? 8
+                            : (N == 512) ? 8 : (E == 16 ? 16 : 8);
+    static constexpr int R1 = (N <= 16) ? 1 : (N == 32) ? 4 : (N == 64) ? 8 : (N == 128) ? (E == 16 ? 8 : 4)
+                            : (N == 512) ? 8 : (E == 16 ? 16 : 8);
+    static constexpr int R2 = (N == 128 || N == 256) ? (E == 16 ? 1 : 4) : (N == 512) ? 8 : (N == 1024) ? 4 : 1;
+    static constexpr int R3 = (N == 1024 && E == 8) ? 4 : 1;
+    static constexpr int P = 1 + (R1 > 1) + (R2 > 1) + (R3 > 1);
+    static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
+    static_assert(E % R0 == 0 && E % R1 == 0 && E % R2 == 0 && E % R3 == 0, "every radix must divide E");
 };
 
 template <int N, int E, int DIR, int P>
 struct Radix {
     using C = FftCfg<N, E>;
-    static constexpr int fwd(int p) { return p == 0 ? C::R0 : (p == 1 ? C::R1 : C::R2); }
+    static constexpr int fwd(int p) { return p == 0 ? C::R0 : p == 1 ? C::R1 : p == 2 ? C::R2 : C::R3; }
     static constexpr int value = DIR < 0 ? fwd(P) : fwd(C::P - 1 - P);
 };
 

@@ -35,11 +35,12 @@ struct InvRowGeom {
 };
 // Column transforms keep all K modes in registers at once, so they use 8
 // elements per thread (16 at N = 16), CB adjacent columns per block (a
-// 128-byte row segment at CB = 16).
+// 128-byte row segment at CB = 16; 4 columns at N = 1024 keep the block at
+// 512 threads, so that a thread may hold 256 registers).
 template <int N>
 struct ColGeom {
     static constexpr int E = (N == 16) ? 16 : 8, T = N / E;
-    static constexpr int CB = (N >= 256) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
+    static constexpr int CB = (N >= 1024) ? 4 : (N >= 256) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
     static constexpr int THREADS = CB * T;
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * CB : 1;   // one transform buffer
 };

@@ -69,18 +69,20 @@ static int ensure_twiddles() {
 
 // ------------------------------------------------------------- sizes -------
 static bool supported_n(int n) {
-    return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512;
+    return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
 }
 
 template <class F>
 static int with_n(int n, F &&f) {
     switch (n) {
+        case 8: return f(std::integral_constant<int, 8>());
         case 16: return f(std::integral_constant<int, 16>());
         case 32: return f(std::integral_constant<int, 32>());
         case 64: return f(std::integral_constant<int, 64>());
         case 128: return f(std::integral_constant<int, 128>());
         case 256: return f(std::integral_constant<int, 256>());
         case 512: return f(std::integral_constant<int, 512>());
+        case 1024: return f(std::integral_constant<int, 1024>());
         default: return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
     }
 }
@@ -259,7 +261,7 @@ struct Timed {
 // ---------------------------------------------------------------- validate --
 static int check_desc(const ptycho_desc_t *d) {
     if (!d) return fail(PTYCHO_E_INVALID, "null descriptor");
-    if (!supported_n(d->n)) return fail(PTYCHO_E_UNSUPPORTED, "frame size must be 16, 32, 64, 128, 256 or 512");
+    if (!supported_n(d->n)) return fail(PTYCHO_E_UNSUPPORTED, "frame size must be a power of two from 8 to 1024");
     if (d->n_modes < 1 || d->n_modes > 4) return fail(PTYCHO_E_UNSUPPORTED, "probe modes must be 1..4");
     if (d->n_frames < 1) return fail(PTYCHO_E_INVALID, "n_frames must be >= 1");
     if (d->obj_ny < d->n || d->obj_nx < d->n) return fail(PTYCHO_E_INVALID, "object smaller than a frame");

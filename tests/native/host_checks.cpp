@@ -30,7 +30,8 @@ static std::vector<double> spiral(int j, double step) {
 int main() {
     const int sizes[][6] = {  // n, K, J, ny, nx, step*10
         {16, 1, 37, 40, 56, 20}, {32, 2, 7, 64, 64, 30}, {64, 1, 100, 256, 256, 60},
-        {128, 3, 21, 320, 288, 80}, {256, 3, 1000, 1024, 1024, 120}, {512, 4, 500, 2048, 2048, 240}};
+        {128, 3, 21, 320, 288, 80}, {256, 3, 1000, 1024, 1024, 120}, {512, 4, 500, 2048, 2048, 240},
+        {8, 2, 50, 48, 48, 10}, {1024, 2, 20, 1536, 1536, 400}};
     for (const auto &sz : sizes) {
         const int n = sz[0], k = sz[1], j = sz[2], ny = sz[3], nx = sz[4];
         std::vector<double> pos = spiral(j, sz[5] / 10.0);
