@@ -97,6 +97,15 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p) {
     return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
 
+// Streaming store: data written once and not read again before much more
+// has passed through the caches: the exit waves, the forward rows' stack and
+// the per-frame object terms.  (The column pass's output, read by the next
+// pass right away, is stored normally: measured faster.)
+__device__ __forceinline__ void st_stream(float2 *p, float2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // Object tile of the atomic-free object gather.
 constexpr int OTILE_Y = 16, OTILE_X = 64;
 
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
         float2 *dst = a.scr + ((size_t)s * SETS * a.K + set * a.K + k) * N * N;
         if (active) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) dst[scr_at<N>(y, out_index<N, E, -1>(t, e))] = u[set][e];
+            for (int e = 0; e < E; ++e) st_stream(dst + scr_at<N>(y, out_index<N, E, -1>(t, e)), u[set][e]);
         }
     }
 }
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
         }
         if (active) {
             if constexpr (MODE == OUT_SCR) src[scr_at<N>(y, x)] = v;
-            if constexpr (MODE == OUT_STORE || MODE == OUT_DM) a.psi_out[prow_psi + x] = v;
+            if constexpr (MODE == OUT_STORE || MODE == OUT_DM) st_stream(a.psi_out + prow_psi + x, v);
         }
         if constexpr (WQ) qk[e] = cmulc(prow[x], v);
     }
@@ -309,7 +318,7 @@ __global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
                 float2 q = RowLds<N>(lds, rr).ld(x);
 #pragma unroll
                 for (int m = 1; m < K; ++m) q = cadd(q, RowLds<N>(lds, m * RQ + rr).ld(x));
-                qrow[x] = q;
+                st_stream(qrow + x, q);
             }
         }
     }
