@@ -1,4 +1,4 @@
-"""Plain FP64 reference for the far-field ptychography hot path.
+"""Plain FP64 reference for the ptychography hot path (far and near field).
 
 TEST INFRASTRUCTURE ONLY.  Only `tests/`, `__graft_entry__.smoke()` and the
 CPU-baseline leg of `bench.py` may import this module.  It shares no code,
@@ -17,12 +17,18 @@ Notation: J frames, K probe modes, N x N frames, object Ny x Nx.
   obj     [Ny][Nx]        complex
   probe   [K][N][N]       complex
   offsets [J][2]          int   top-left corner (oy, ox) of each frame's window
-  iobs    [J][N][N]       float observed intensity, FFT order (q = 0 at [0, 0])
+  iobs    [J][N][N]       float observed intensity; far field: FFT order (q = 0 at
+                          [0, 0]); near field: detector pixels in natural order
   mask    [N][N] or None  uint8, 1 = bad detector pixel (shared by all frames)
   psi     [J][K][N][N]    complex exit waves
 
+The near-field geometry (`nf` arguments: Fresnel parameters, see
+`near_field_transfer`) replaces the far-field FT by the unitary near-field
+propagation; every other step is unchanged.
+
 Pins (tests/test_oracle_*.py) tie every function to something other than
-itself: brute-force DFT sums, Parseval, idempotence of the modulus
+itself: brute-force DFT sums, Parseval, the paraxial Gaussian beam and the
+Talbot self-image for the near-field propagation, idempotence of the modulus
 projection, least-squares solutions, fixed points at the truth, the
 scipy.stats Poisson log-pmf, and central finite differences.  The CG and DM
 *trajectories* over many cycles have no closed form: parity unpinned for the
@@ -45,6 +51,7 @@ __all__ = [
     "UPDATE_PROBE", "UPDATE_BACKGROUND", "DEFAULT_EPS", "DEFAULT_INERTIA",
     "model_intensity", "projection_scale", "background_update",
     "object_gradient", "position_shifts", "update_positions",
+    "fresnel_pair", "near_field_transfer", "propagate_near_field", "to_detector", "from_detector",
 ]
 
 UPDATE_OBJECT = 1
@@ -71,6 +78,50 @@ def fft2(x: np.ndarray) -> np.ndarray:
 def ifft2(x: np.ndarray) -> np.ndarray:
     """Unitary inverse 2D DFT over the last two axes."""
     return np.fft.ifft2(np.asarray(x, dtype=np.complex128), norm="ortho")
+
+
+def fresnel_pair(nf) -> tuple:
+    """(f_y, f_x) from a scalar (square pixels) or a pair."""
+    f = np.broadcast_to(np.asarray(nf, dtype=np.float64), (2,))
+    return float(f[0]), float(f[1])
+
+
+def near_field_transfer(n: int, nf) -> np.ndarray:
+    """Fresnel transfer function on the N x N DFT grid (FFT order):
+    Q[u, v] = exp(-i (f_y u'^2 + f_x v'^2)), u' = u for u < N/2 else u - N.
+
+    Operator PropagateNearField.  The paper names the operator but not its
+    formula; the reading taken is the paraxial (Fresnel) transfer function
+    exp(-i pi lambda z |q|^2) of a field with exp(+ikz) dependence, the
+    constant exp(ikz) dropped.  With q = u'/(N dx) the phase is f u'^2 with the
+    dimensionless f = pi lambda z / (N dx)^2 per axis; a magnified (cone-beam)
+    geometry enters through its effective distance.
+    """
+    fy, fx = fresnel_pair(nf)
+    u = np.fft.fftfreq(n) * n
+    return np.exp(-1j * (fy * u[:, None] ** 2 + fx * u[None, :] ** 2))
+
+
+def propagate_near_field(x: np.ndarray, nf, direction: int = 1) -> np.ndarray:
+    """Near-field propagation over the last two axes: F^-1 Q F (direction +1,
+    sample to detector) or F^-1 conj(Q) F (-1, back to the sample).  Unitary,
+    and the two directions are each other's inverse."""
+    q = near_field_transfer(np.asarray(x).shape[-1], nf)
+    if direction < 0:
+        q = np.conj(q)
+    return ifft2(fft2(x) * q)
+
+
+def to_detector(x: np.ndarray, nf=None) -> np.ndarray:
+    """Sample plane -> detector plane: the far-field FT (nf None), else
+    near-field propagation with Fresnel parameter(s) nf.  Both are unitary,
+    so every formula below holds with either in place of F."""
+    return fft2(x) if nf is None else propagate_near_field(x, nf, +1)
+
+
+def from_detector(x: np.ndarray, nf=None) -> np.ndarray:
+    """Inverse (= adjoint) of `to_detector`."""
+    return ifft2(x) if nf is None else propagate_near_field(x, nf, -1)
 
 
 # --------------------------------------------------------------------------
@@ -152,9 +203,11 @@ def project_modulus(psi_hat: np.ndarray, iobs: np.ndarray,
     return psi_hat * projection_scale(psi_hat, iobs, mask, eps, bg)[:, None, :, :]
 
 
-def fourier_project(psi: np.ndarray, iobs, mask, eps: float = DEFAULT_EPS, bg=None) -> np.ndarray:
-    """IFT * ApplyAmplitude * FT on every frame and mode (far field)."""
-    return ifft2(project_modulus(fft2(psi), iobs, mask, eps, bg))
+def fourier_project(psi: np.ndarray, iobs, mask, eps: float = DEFAULT_EPS, bg=None, nf=None) -> np.ndarray:
+    """PropagateApplyAmplitude on every frame and mode: IFT * ApplyAmplitude *
+    FT in the far field, or the same with near-field propagation both ways
+    (nf given), the amplitude then replaced in the detector plane."""
+    return from_detector(project_modulus(to_detector(psi, nf), iobs, mask, eps, bg), nf)
 
 
 def background_update(bg, scale) -> np.ndarray:
@@ -250,17 +303,19 @@ def overlap_update(obj, probe, psi, offsets, update=UPDATE_OBJECT | UPDATE_PROBE
 
 def ap_cycle(obj, probe, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
              inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
-             eps=DEFAULT_EPS, bg=None):
+             eps=DEFAULT_EPS, bg=None, nf=None):
     """One alternating-projections cycle: views, Fourier projection of every
     frame, then one object/probe update from all projected exit waves.
     Returns (obj, probe); with a background bg, (obj, probe, bg), the
-    background refined by `background_update` when UPDATE_BACKGROUND is set."""
+    background refined by `background_update` when UPDATE_BACKGROUND is set.
+    nf: near-field Fresnel parameter(s) (`near_field_transfer`), None = far
+    field."""
     if (update & UPDATE_BACKGROUND) and bg is None:
         raise ValueError("a background update needs a background")
     phi = exit_waves(obj, probe, offsets)
-    phi_hat = fft2(phi)
+    phi_hat = to_detector(phi, nf)
     scale = projection_scale(phi_hat, iobs, mask, eps, bg)
-    psi = ifft2(phi_hat * scale[:, None, :, :])
+    psi = from_detector(phi_hat * scale[:, None, :, :], nf)
     o, p = overlap_update(obj, probe, psi, offsets, update & (UPDATE_OBJECT | UPDATE_PROBE),
                           inertia_obj, inertia_probe)
     if bg is None:
@@ -271,7 +326,7 @@ def ap_cycle(obj, probe, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROB
 
 def dm_cycle(obj, probe, psi, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
              inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
-             eps=DEFAULT_EPS, bg=None):
+             eps=DEFAULT_EPS, bg=None, nf=None):
     """One difference-map cycle (beta = 1) on persistent exit waves.
 
     Phi = views of the current object and probe (the overlap projection of
@@ -280,7 +335,7 @@ def dm_cycle(obj, probe, psi, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE
     """
     phi = exit_waves(obj, probe, offsets)
     psi = np.asarray(psi, dtype=np.complex128)
-    psi_new = psi + fourier_project(2.0 * phi - psi, iobs, mask, eps, bg) - phi
+    psi_new = psi + fourier_project(2.0 * phi - psi, iobs, mask, eps, bg, nf) - phi
     o, p = overlap_update(obj, probe, psi_new, offsets, update, inertia_obj, inertia_probe)
     return o, p, psi_new
 
@@ -323,10 +378,10 @@ def llk_model_terms(icalc, iobs, model, eps=DEFAULT_EPS):
     raise ValueError(f"unknown noise model {model!r}")
 
 
-def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson", bg=None):
+def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson", bg=None, nf=None):
     """(sum over unmasked pixels of all frames, number of those pixels) of
     the chosen noise model's terms."""
-    inten = model_intensity(fft2(exit_waves(obj, probe, offsets)), bg)
+    inten = model_intensity(to_detector(exit_waves(obj, probe, offsets), nf), bg)
     terms = llk_model_terms(inten, iobs, model, eps)
     if mask is not None:
         good = np.broadcast_to(np.asarray(mask)[None] == 0, terms.shape)
@@ -335,7 +390,7 @@ def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson", bg=No
     return float(terms[good].sum()), int(good.sum())
 
 
-def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None):
+def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None):
     """Gradient of the Poisson LLK w.r.t. object and probe.
 
     Convention: g = dL/dRe(z) + i dL/dIm(z) (= 2 dL/dz*).  With
@@ -344,12 +399,13 @@ def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None):
       psi_jk = F^-1(l'(I_j) Psi^_jk)
       g_O = 2 sum_jk S_j^T (conj(P_k) psi_jk)
       g_P_k = 2 sum_j conj(O_j) psi_jk
-    Returns (g_obj, g_probe, llk_sum).
+    In the near field (nf given) F is the unitary propagation and F^-1 its
+    adjoint.  Returns (g_obj, g_probe, llk_sum).
     """
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
     n = probe.shape[-1]
-    phi_hat = fft2(exit_waves(obj, probe, offsets))
+    phi_hat = to_detector(exit_waves(obj, probe, offsets), nf)
     inten = np.maximum(model_intensity(phi_hat, bg), eps)
     io = np.asarray(iobs, dtype=np.float64)
     dl = 1.0 - io / inten
@@ -358,7 +414,7 @@ def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None):
         bad = np.asarray(mask)[None] != 0
         dl = np.where(bad, 0.0, dl)
         terms = np.where(bad, 0.0, terms)
-    psi = ifft2(dl[:, None] * phi_hat)
+    psi = from_detector(dl[:, None] * phi_hat, nf)
     g_o = np.zeros(obj.shape, dtype=np.complex128)
     g_p = np.zeros(probe.shape, dtype=np.complex128)
     for j, (oy, ox) in enumerate(offsets):
@@ -368,7 +424,7 @@ def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None):
     return g_o, g_p, float(terms.sum())
 
 
-def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None):
+def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None):
     """First and second derivative of L(gamma) = LLK(O + g dO, P + g dP) at 0.
 
     The exit wave along the line is A + gamma B + gamma^2 C with
@@ -380,9 +436,9 @@ def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_
     quadratic line search of the Poisson ML conjugate gradient the paper
     cites, Thibault & Guizar-Sicairos 2012).
     """
-    a = fft2(exit_waves(obj, probe, offsets))
-    b = fft2(exit_waves(obj, dprobe, offsets) + exit_waves(dobj, probe, offsets))
-    c = fft2(exit_waves(dobj, dprobe, offsets))
+    a = to_detector(exit_waves(obj, probe, offsets), nf)
+    b = to_detector(exit_waves(obj, dprobe, offsets) + exit_waves(dobj, probe, offsets), nf)
+    c = to_detector(exit_waves(dobj, dprobe, offsets), nf)
     i0 = np.maximum(model_intensity(a, bg), eps)
     i1 = 2.0 * (np.conj(a) * b).real.sum(axis=1)
     i2 = (np.abs(b) ** 2).sum(axis=1) + 2.0 * (np.conj(a) * c).real.sum(axis=1)
@@ -417,7 +473,7 @@ class CGState:
 
 
 def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
-             update=UPDATE_OBJECT, eps=DEFAULT_EPS, bg=None):
+             update=UPDATE_OBJECT, eps=DEFAULT_EPS, bg=None, nf=None):
     """One Polak-Ribiere (PR+) conjugate-gradient step on the Poisson LLK.
 
     The probe block of the gradient is scaled by s = max(denO) / max(denP)
@@ -430,7 +486,7 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
     """
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
-    g_o, g_p, lsum = ml_grad(obj, probe, offsets, iobs, mask, eps, bg)
+    g_o, g_p, lsum = ml_grad(obj, probe, offsets, iobs, mask, eps, bg, nf)
     if not update & UPDATE_OBJECT:
         g_o = np.zeros_like(g_o)
     if not update & UPDATE_PROBE:
@@ -447,7 +503,7 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
         beta = max(0.0, num / state.zg)
         d_o = -g_o + beta * state.d_obj
         d_p = -s * g_p + beta * state.d_probe
-    l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps, bg)
+    l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps, bg, nf)
     gamma = -l1 / l2 if (l2 > 0.0 and math.isfinite(l1) and math.isfinite(l2)) else 0.0
     state.d_obj, state.d_probe = d_o, d_p
     state.g_obj, state.g_probe = g_o, g_p
@@ -520,9 +576,11 @@ def update_positions(pos, pos0, shifts, energy, mult=1.0, max_shift=2.0, min_gra
 # Forward model for simulation (Section 4, simulation functions)
 # --------------------------------------------------------------------------
 
-def simulate_intensity(obj, probe, offsets, chunk: int = 64, bg=None) -> np.ndarray:
-    """Noise-free far-field intensities sum_k |F(P_k O_j)|^2 (+ bg), float64 [J][N][N]."""
+def simulate_intensity(obj, probe, offsets, chunk: int = 64, bg=None, nf=None) -> np.ndarray:
+    """Noise-free intensities sum_k |F(P_k O_j)|^2 (+ bg), float64 [J][N][N]:
+    far field (FFT order), or near field with Fresnel parameter(s) nf
+    (detector pixels in natural order)."""
     out = []
     for s in range(0, len(offsets), chunk):
-        out.append(model_intensity(fft2(exit_waves(obj, probe, offsets[s:s + chunk])), bg))
+        out.append(model_intensity(to_detector(exit_waves(obj, probe, offsets[s:s + chunk]), nf), bg))
     return np.concatenate(out, axis=0)

@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for far-field ptychography workloads.
+"""Seeded synthetic inputs for far- and near-field ptychography workloads.
 
 This module only draws and shapes the *inputs* of a reconstruction: the
 ground-truth object, the probe modes, the scan positions, the detector gap
@@ -23,6 +23,13 @@ them with the same shapes and value ranges:
   requested fraction of a frame, generated in detector-centred coordinates
   and returned in FFT order (zero frequency at [0, 0]), 1 = bad pixel.
 
+Near-field workloads (Table 1: 17 frames of 2048x2048, one probe) use a broad
+structured illumination instead of the focused spot: a soft-edged aperture
+over most of the frame times a smooth random amplitude and phase (a
+diffuser), a few scan positions drawn uniformly in a small square, and the
+detector in natural pixel order.  Their Fresnel parameter f = pi lambda z /
+(N dx)^2 is part of the workload.
+
 All randomness comes from ``numpy.random.SeedSequence`` so that a workload is
 reproducible bit for bit from its seed.
 """
@@ -40,6 +47,7 @@ __all__ = [
     "probe_modes", "spiral_positions", "gap_mask", "start_object",
     "start_probe", "perturb_object", "perturb_probe", "probe_photon_scale",
     "serve_requests", "mode_weights", "poisson_counts",
+    "near_field_probe", "random_positions", "fresnel_parameter",
 ]
 
 BASE_SEED = 20081151
@@ -60,6 +68,8 @@ class Workload:
     algorithm: str         # "ap", "dm", "ml", "ap+dm"
     cycles: tuple          # cycle counts for the algorithm chain
     seed: int
+    geometry: str = "far"  # "far" or "near"
+    fresnel: float = 0.0   # near field: f = pi lambda z / (N dx)^2 (both axes)
 
     def scaled(self, n_frames: int) -> "Workload":
         """Same model with fewer scan positions (parity tests, samples)."""
@@ -80,7 +90,28 @@ WORKLOADS = {
     # Large: 512x512 frames, 4 modes, 4000 positions, 3% mask, 20 AP + 50 DM.
     "apdm512": Workload("apdm512", 512, 4, 4000, (4096, 4096), 24.0, 1e9,
                         0.03, "ap+dm", (20, 50), BASE_SEED + 3),
+    # Near field (Table 1): 17 frames of 2048x2048, one probe, positions in a
+    # 256 px square, 1e4 photons per pixel, no detector gaps, DM then ML.
+    # `step` is the side of the position square.
+    "nf2048": Workload("nf2048", 2048, 1, 17, (2368, 2368), 256.0, 1e4 * 2048 ** 2, 0.0,
+                       "dm+ml", (400, 100), BASE_SEED + 5, "near", 0.0),
+    # The same geometry at 1024x1024 frames (the same Fresnel number per pixel).
+    "nf1024": Workload("nf1024", 1024, 1, 17, (1344, 1344), 256.0, 1e4 * 1024 ** 2, 0.0,
+                       "dm+ml", (400, 100), BASE_SEED + 6, "near", 0.0),
 }
+
+# Fresnel number per pixel, dx^2 / (lambda z), of the near-field workloads.
+NEAR_FIELD_NF_PIXEL = 4e-3
+
+
+def fresnel_parameter(n: int, fresnel_number: float = NEAR_FIELD_NF_PIXEL) -> float:
+    """f = pi lambda z / (N dx)^2 = pi / (N^2 N_F) for a Fresnel number per
+    pixel N_F = dx^2 / (lambda z)."""
+    return math.pi / (n * n * fresnel_number)
+
+
+for _name in ("nf2048", "nf1024"):
+    WORKLOADS[_name] = dataclasses.replace(WORKLOADS[_name], fresnel=fresnel_parameter(WORKLOADS[_name].n))
 
 
 def workload(name: str) -> Workload:
@@ -151,6 +182,47 @@ def probe_modes(n: int, k: int, seed: int) -> np.ndarray:
     return np.stack([np.sqrt(w[i]) * modes[i] for i in range(k)])
 
 
+def random_positions(n_frames: int, extent: float, seed: int) -> np.ndarray:
+    """Near-field scan: the first position at (0, 0), the others uniform in
+    the square [-extent/2, extent/2)^2, (y, x) in pixels."""
+    rng = make_rng(seed, "positions")
+    pos = rng.uniform(-extent / 2.0, extent / 2.0, size=(n_frames, 2))
+    pos[0] = 0.0
+    return pos
+
+
+def near_field_probe(n: int, k: int, seed: int) -> np.ndarray:
+    """Near-field illumination modes [K][N][N] (complex128), unit total
+    intensity: a square aperture over 90% of the frame with Gaussian-softened
+    edges (sigma N/64), times a diffuser: amplitude 1 + 0.3 u and phase
+    1.0 v rad, with u, v white noise smoothed over N/128 px and scaled to unit
+    peak / unit std.  Extra modes are mode 0 times x, y, xy (in units of N/4),
+    orthonormalised and weighted as in `probe_modes`."""
+    rng = make_rng(seed, "probe")
+    y, x = _grid(n)
+    half = 0.45 * n
+    ap = ((np.abs(y) <= half) & (np.abs(x) <= half)).astype(np.float64)
+    ap = scipy.ndimage.gaussian_filter(ap, n / 64.0, mode="constant")
+    sm = max(1.0, n / 128.0)
+    u = scipy.ndimage.gaussian_filter(rng.standard_normal((n, n)), sm, mode="wrap")
+    v = scipy.ndimage.gaussian_filter(rng.standard_normal((n, n)), sm, mode="wrap")
+    u = u / np.abs(u).max()
+    v = (v - v.mean()) / v.std()
+    p0 = ap * (1.0 + 0.3 * u) * np.exp(1j * v)
+    s = n / 4.0
+    basis = [np.ones_like(x), x / s, y / s, x * y / s ** 2]
+    if k > len(basis):
+        raise ValueError("at most 4 probe modes are generated")
+    modes = []
+    for i in range(k):
+        w = p0 * basis[i]
+        for m in modes:
+            w = w - np.vdot(m, w) * m
+        modes.append(w / np.sqrt(np.vdot(w, w).real))
+    wt = mode_weights(k)
+    return np.stack([np.sqrt(wt[i]) * modes[i] for i in range(k)])
+
+
 def spiral_positions(n_frames: int, step: float) -> np.ndarray:
     """Fermat spiral scan positions (y, x) in pixels, centred on (0, 0)."""
     i = np.arange(n_frames, dtype=np.float64)
@@ -159,8 +231,9 @@ def spiral_positions(n_frames: int, step: float) -> np.ndarray:
     return np.stack([r * np.sin(th), r * np.cos(th)], axis=1)
 
 
-def gap_mask(n: int, frac: float, seed: int) -> Optional[np.ndarray]:
-    """Detector-gap mask u8 [N][N] in FFT order (1 = bad), or None."""
+def gap_mask(n: int, frac: float, seed: int, fft_order: bool = True) -> Optional[np.ndarray]:
+    """Detector-gap mask u8 [N][N] (1 = bad), or None: in FFT order for the
+    far field, in natural order (fft_order False) for the near field."""
     if frac <= 0:
         return None
     rng = make_rng(seed, "mask")
@@ -172,7 +245,7 @@ def gap_mask(n: int, frac: float, seed: int) -> Optional[np.ndarray]:
             m[:, start:start + 6] = 1     # vertical band
         else:
             m[start:start + 6, :] = 1     # horizontal band
-    return np.ascontiguousarray(np.fft.ifftshift(m))
+    return np.ascontiguousarray(np.fft.ifftshift(m) if fft_order else m)
 
 
 def background(n: int, level: float, seed: int) -> np.ndarray:
