@@ -1,6 +1,6 @@
 /*
- * ptycho.h - C ABI of the far-field ptychography hot path for AMD MI355X
- * (gfx950).
+ * ptycho.h - C ABI of the ptychography hot path (far and near field) for
+ * AMD MI355X (gfx950).
  *
  * The library implements the data-parallel core of operator-based
  * ptychographic reconstruction as described in Favre-Nicolin et al., "PyNX:
@@ -9,7 +9,9 @@
  * ptychography operators: exit waves (ObjProbe2Psi), far-field propagation
  * (FT / IFT), the modulus constraint (ApplyAmplitude), the object and probe
  * update (Psi2ObjProbe), the AP and DM cycles, the Poisson log-likelihood
- * (LLK) and the conjugate-gradient ML refinement built on its gradient.
+ * (LLK) and the conjugate-gradient ML refinement built on its gradient, in
+ * the far-field geometry or, with PTYCHO_FLAG_NEAR_FIELD, the near-field one
+ * (PropagateNearField in place of FT / IFT).
  *
  * Conventions shared by every entry point
  * ----------------------------------------
@@ -19,11 +21,15 @@
  *  - obj   : complex[obj_ny][obj_nx]          object O
  *    probe : complex[K][N][N]                 probe modes P_k
  *    psi   : complex[J][K][N][N]              exit waves (DM state)
- *    iobs  : float[J][N][N]                   observed counts, FFT order
- *                                              (zero frequency at [0][0])
+ *    iobs  : float[J][N][N]                   observed counts; far field: FFT
+ *                                              order (zero frequency at
+ *                                              [0][0]); near field: detector
+ *                                              pixels in natural order
  *    mask  : uint8[N][N]                      1 = bad detector pixel, shared
  *                                              by all frames; NULL = none
- *  - The 2D transforms are unitary, forward sign -1.
+ *  - The 2D transforms are unitary, forward sign -1.  Near-field
+ *    propagation is F^-1 Q F with the Fresnel transfer function Q (see
+ *    ptycho_plan_set_near_field), unitary as well.
  *  - Frame j covers obj[oy_j .. oy_j+N-1][ox_j .. ox_j+N-1] with integer
  *    top-left offsets (oy_j, ox_j); exit wave Psi_jk[y][x] =
  *    O[oy_j+y][ox_j+x] * P_k[y][x].
@@ -66,8 +72,12 @@ typedef enum {
 #define PTYCHO_UPDATE_BACKGROUND 4u   /* AP only; see ptycho_ap_cycle */
 
 /* Descriptor flags.  PTYCHO_FLAG_BACKGROUND reserves workspace for the AP
- * background refinement (S*N*N floats and N*N doubles). */
+ * background refinement (S*N*N floats and N*N doubles).
+ * PTYCHO_FLAG_NEAR_FIELD selects the near-field geometry (2*N complex of
+ * workspace for the transfer function); such a plan needs
+ * ptycho_plan_set_near_field before any call that propagates. */
 #define PTYCHO_FLAG_BACKGROUND 1u
+#define PTYCHO_FLAG_NEAR_FIELD 2u
 
 /* Problem description.  Supported: N a power of two from 8 to 1024,
  * 1 <= K <= 4, J >= 1, obj_ny >= N, obj_nx >= N. */
@@ -82,7 +92,7 @@ typedef struct {
     float obj_inertia;      /* delta_O: alpha_O = delta_O * max(denO)           */
     float probe_inertia;    /* delta_P: alpha_P = delta_P * max(denP)           */
     float icalc_floor;      /* epsilon: calculated intensity floor              */
-    uint32_t flags;         /* PTYCHO_FLAG_* (0 or PTYCHO_FLAG_BACKGROUND)      */
+    uint32_t flags;         /* PTYCHO_FLAG_* (BACKGROUND, NEAR_FIELD; OR-ed)    */
 } ptycho_desc_t;
 
 typedef struct ptycho_plan_s *ptycho_plan_t;
@@ -121,6 +131,22 @@ int ptycho_plan_create(const ptycho_desc_t *desc, const int32_t *offsets_host,
  * (without the device pointers); for capacity planning and tests. */
 int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
                         size_t *table_bytes_out);
+
+/* Near-field geometry (Section 4: near and far-field geometries; operator
+ * PropagateNearField of the ptychography-operator table, which the paper
+ * names without a formula).  Reading: the paraxial Fresnel transfer
+ * function, Q[u][v] = exp(-i (fy u'^2 + fx v'^2)) on the DFT grid with
+ * u' = u for u < N/2 else u - N, i.e. exp(-i pi lambda z |q|^2) with the
+ * constant phase exp(ikz) dropped: fy = pi lambda z / (N dy)^2 and
+ * fx = pi lambda z / (N dx)^2 for pixel sizes dy, dx (a magnified geometry
+ * enters through its effective distance).  Every operator of the plan then
+ * propagates with D = F^-1 Q F (sample to detector) and its inverse
+ * F^-1 conj(Q) F, and takes iobs and mask in natural pixel order.  The plan
+ * must have been created with PTYCHO_FLAG_NEAR_FIELD (PTYCHO_E_INVALID
+ * otherwise, and for non-finite parameters).  The table Q/N is computed on
+ * the host in double precision and uploaded on the plan's stream without
+ * waiting; calls may change it between cycles (e.g. another distance). */
+int ptycho_plan_set_near_field(ptycho_plan_t plan, double fy, double fx);
 
 /* Incoherent background (Section 4: the Ptycho object carries one beside the
  * object and probe estimates): bg_dev float[N][N] in FFT order, shared by

@@ -20,6 +20,7 @@ UPDATE_OBJECT = 1
 UPDATE_PROBE = 2
 UPDATE_BACKGROUND = 4
 FLAG_BACKGROUND = 1
+FLAG_NEAR_FIELD = 2
 
 
 class PtychoError(RuntimeError):
@@ -44,6 +45,7 @@ _SIGS = {
     "ptycho_plan_dry_run": [ctypes.POINTER(Desc), _P, ctypes.POINTER(ctypes.c_size_t)],
     "ptycho_plan_set_stream": [_P, _P],
     "ptycho_plan_set_background": [_P, _P],
+    "ptycho_plan_set_near_field": [_P, ctypes.c_double, ctypes.c_double],
     "ptycho_position_shifts": [_P, _P, _P, _P, _P],
     "ptycho_check_finite": [_P, _P, _P, _P],
     "ptycho_plan_stack": [_P, ctypes.POINTER(ctypes.c_int32)],

@@ -1,4 +1,4 @@
-// kernels.hpp - gfx950 kernels of the far-field ptychography hot path.
+// kernels.hpp - gfx950 kernels of the ptychography hot path.
 //
 // One cycle over a stack of S frames runs as
 //   rows_fwd : object view x probe (or 2*Phi - Psi for DM), 1D FFT along x
@@ -12,6 +12,15 @@
 //              each output pixel summed by exactly one thread in a fixed
 //              frame order (no atomics, bitwise reproducible)
 // and, once per cycle, max-reductions and the normalisation with inertia.
+//
+// Near field (template flag NF): the detector sees D = F^-1 Q F instead of F,
+// with the Fresnel transfer function Q(u, v) = Qy(u) Qx(v) separable, so
+// D = Dy Dx with Dx = F_x^-1 Qx F_x acting on rows alone and Dy on columns
+// alone.  Each row or column pass then runs its forward transform, the
+// transfer-function factor and the inverse transform back to back in
+// registers, and the detector-plane step sits between the column pass's two
+// propagations: the same three passes over memory as the far field, twice the
+// transforms.
 #pragma once
 
 #include "fft.hpp"
@@ -124,6 +133,7 @@ struct StackArgs {
     const float *bg;             // incoherent background [N][N] or null
     float *s2;                   // AP background refinement: s^2 per slot [S][N][N], or null
     const unsigned char *mask;   // [N][N] or null
+    const float2 *prop;          // near field: [2][N] Qy(u) / N, Qx(v) / N (FFT order), or null
     float *icalc;                // [J][N][N] (icalc op)
     double *red;                 // per-block partial sums of this launch
     float eps;
@@ -205,7 +215,7 @@ enum RowIn { IN_PHI = 0, IN_DM = 1, IN_LS = 2, IN_DATA = 3 };
 // Forward row FFT of the stack's exit waves.  Block = RB consecutive rows of
 // the flattened (slot, y) row index of one probe mode (blockIdx.y); thread =
 // (row, t).  The object view is re-read per mode from the caches.
-template <int N, int MODE>
+template <int N, int MODE, bool NF>
 __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     using G = RowGeom<N>;
     constexpr int E = G::E, T = G::T, RB = G::RB;
@@ -246,10 +256,20 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
 #pragma unroll
     for (int set = 0; set < SETS; ++set) {
         fft1d<N, E, -1>(u[set], t, L);
+        if constexpr (NF) {
+            // Dx: the x factor of the transfer function, then back to x
+            const float2 *qx = a.prop + N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) u[set][e] = cmul(u[set][e], qx[out_index<N, E, -1>(t, e)]);
+            fft1d<N, E, +1>(u[set], t, L);
+        }
         float2 *dst = a.scr + ((size_t)s * SETS * a.K + set * a.K + k) * N * N;
         if (active) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) st_stream(dst + scr_at<N>(y, out_index<N, E, -1>(t, e)), u[set][e]);
+            for (int e = 0; e < E; ++e) {
+                const int x = NF ? out_index<N, E, +1>(t, e) : out_index<N, E, -1>(t, e);
+                st_stream(dst + scr_at<N>(y, x), u[set][e]);
+            }
         }
     }
 }
@@ -264,7 +284,7 @@ enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2, OUT_NONE = 3 };
 // the frame's term of the object numerator, to qbuf, so that the object
 // gather reads one plane per frame instead of K exit waves and K probe
 // values.
-template <int N, int K, int MODE, bool WQ>
+template <int N, int K, int MODE, bool WQ, bool NF>
 __global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
     using G = InvRowGeom<N>;
     constexpr int E = G::E, T = G::T, RQ = G::RQ;
@@ -280,7 +300,14 @@ __global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
     float2 *src = a.scr + ((size_t)s * K + k) * N * N;
     float2 u[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = src[scr_at<N>(y, in_index<N, E, +1>(t, e))];
+    for (int e = 0; e < E; ++e) u[e] = src[scr_at<N>(y, NF ? in_index<N, E, -1>(t, e) : in_index<N, E, +1>(t, e))];
+    if constexpr (NF) {
+        // Dx^-1: forward transform, the conjugate x factor, inverse below
+        fft1d<N, E, -1>(u, t, L);
+        const float2 *qx = a.prop + N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) u[e] = cmulc(qx[out_index<N, E, -1>(t, e)], u[e]);
+    }
     fft1d<N, E, +1>(u, t, L);
     const float2 *prow = a.probe + ((size_t)k * N + y) * N;
     const size_t prow_psi = (((size_t)j * K + k) * N + y) * N;
@@ -441,15 +468,47 @@ enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4, O
 // Waves per SIMD a column kernel is compiled for: the DM form with up to 3
 // modes fits 128 registers without spilling, which gives 4 waves instead of
 // 3 (measured faster); the others keep the compiler's choice.
-template <int N, int K, int OP>
+template <int N, int K, int OP, bool NF>
 struct ColMinWaves {
-    static constexpr int value = (ColJoint<N, K>::SEQ && N <= 256 && K <= 3 && OP == OP_CORR) ? 4 : 1;
+    static constexpr int value = (!NF && ColJoint<N, K>::SEQ && N <= 256 && K <= 3 && OP == OP_CORR) ? 4 : 1;
 };
+
+// Row (y) index of register e of thread t at the detector-plane step: after
+// the forward transform in the far field (a frequency), after the forward
+// and inverse transforms in the near field (a pixel).
+template <int N, int E, bool NF>
+__device__ __forceinline__ int det_row(int t, int e) {
+    return NF ? in_index<N, E, -1>(t, e) : out_index<N, E, -1>(t, e);
+}
+
+// The column transforms of all K modes, forward (DIR -1) or inverse (+1):
+// joint pass by pass, or one mode after the other through one buffer.
+template <int N, int E, int DIR, int K, bool SEQ, class Lds>
+__device__ __forceinline__ void col_transforms(float2 (&u)[K][E], int t, Lds *L) {
+    if constexpr (SEQ) {
+        __syncthreads();     // earlier transforms' last LDS reads are done
+#pragma unroll
+        for (int k = 0; k < K; ++k) fft1d<N, E, DIR>(u[k], t, L[k]);
+    } else {
+        fftk<N, E, DIR, K>(u, t, L);
+    }
+}
+
+// Near field: multiply the column spectra by Qy (CONJ: its conjugate).
+template <int N, int E, int K, int NSET, bool CONJ>
+__device__ __forceinline__ void apply_qy(float2 (&u)[K][E], const float2 *qy, int t) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float2 w = qy[out_index<N, E, -1>(t, e)];
+#pragma unroll
+        for (int k = 0; k < NSET; ++k) u[k][e] = CONJ ? cmulc(w, u[k][e]) : cmul(u[k][e], w);
+    }
+}
 
 // Column FFTs of all K modes held together in registers, the Fourier-space
 // step and (project / grad) the inverse column FFTs, written back in place.
-template <int N, int K, int OP>
-__global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP>::value)) void k_cols_joint(StackArgs a) {
+template <int N, int K, int OP, bool NF>
+__global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP, NF>::value)) void k_cols_joint(StackArgs a) {
     using G = ColGeom<N>;
     constexpr int E = G::E, CB = G::CB;
     extern __shared__ float2 lds_dyn[];
@@ -464,7 +523,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP>::value)
     ColLds<N, CB> L[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) L[k] = ColLds<N, CB>(lds_dyn + (SEQ ? 0 : k) * G::LDS_F2, cl);
-    constexpr float inv_n2 = 1.0f / ((float)N * (float)N);
+    // far field: the unitary 1/N^2 of the forward and inverse 2D transforms;
+    // near field: folded into the transfer-function factors
+    constexpr float nrm = NF ? 1.0f : 1.0f / ((float)N * (float)N);
 
     float2 u[K][E];
 #pragma unroll
@@ -480,15 +541,15 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP>::value)
     bool badv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int q = out_index<N, E, -1>(t, e);
+        const int q = det_row<N, E, NF>(t, e);
         iobv[e] = io[(size_t)q * N];
         badv[e] = a.mask != nullptr && a.mask[q * N + c] != 0;
     }
-    if constexpr (SEQ) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) fft1d<N, E, -1>(u[k], t, L[k]);
-    } else {
-        fftk<N, E, -1, K>(u, t, L);
+    col_transforms<N, E, -1, K, SEQ>(u, t, L);
+    if constexpr (NF) {
+        // Dy: to the detector plane
+        apply_qy<N, E, K, K, false>(u, a.prop, t);
+        col_transforms<N, E, +1, K, SEQ>(u, t, L);
     }
 
     double acc = 0.0;
@@ -499,31 +560,30 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP>::value)
         for (int k = 0; k < K; ++k) inten += cnorm(u[k][e]);
         // the background (L2-resident, usually absent) is read here rather
         // than with Iobs, so that it holds no registers across the transform
-        inten = inten * inv_n2 + (a.bg != nullptr ? a.bg[out_index<N, E, -1>(t, e) * N + c] : 0.0f);
+        inten = inten * nrm + (a.bg != nullptr ? a.bg[det_row<N, E, NF>(t, e) * N + c] : 0.0f);
         const bool bad = badv[e];
         const float iob = iobv[e];
         float sc;
         if constexpr (OP == OP_PROJECT) {
             const float r = iob / fmaxf(inten, a.eps);
-            sc = bad ? inv_n2 : sqrtf(r) * inv_n2;
-            if (a.s2 != nullptr && active) a.s2[((size_t)s * N + out_index<N, E, -1>(t, e)) * N + c] = bad ? 1.0f : r;
+            sc = bad ? nrm : sqrtf(r) * nrm;
+            if (a.s2 != nullptr && active) a.s2[((size_t)s * N + det_row<N, E, NF>(t, e)) * N + c] = bad ? 1.0f : r;
         } else if constexpr (OP == OP_CORR) {
-            sc = bad ? 0.0f : (sqrtf(iob / fmaxf(inten, a.eps)) - 1.0f) * inv_n2;
+            sc = bad ? 0.0f : (sqrtf(iob / fmaxf(inten, a.eps)) - 1.0f) * nrm;
         } else {
             const float ifl = fmaxf(inten, a.eps);
-            sc = bad ? 0.0f : (1.0f - iob / ifl) * inv_n2;
+            sc = bad ? 0.0f : (1.0f - iob / ifl) * nrm;
             if (!bad && active) acc += (double)llk_term(ifl, iob);
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) u[k][e] = cscale(u[k][e], sc);
     }
-    if constexpr (SEQ) {
-        __syncthreads();     // the forward transforms' last LDS reads are done
-#pragma unroll
-        for (int k = 0; k < K; ++k) fft1d<N, E, +1>(u[k], t, L[k]);
-    } else {
-        fftk<N, E, +1, K>(u, t, L);
+    if constexpr (NF) {
+        // Dy^-1: back from the detector plane (the inverse transform below)
+        col_transforms<N, E, -1, K, SEQ>(u, t, L);
+        apply_qy<N, E, K, K, true>(u, a.prop, t);
     }
+    col_transforms<N, E, +1, K, SEQ>(u, t, L);
     if (active) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -540,7 +600,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP>::value)
 
 // Column FFTs one mode at a time for the read-only Fourier-space steps:
 // LLK, calculated intensity, and the line-search terms I0, I1, I2.
-template <int N, int OP>
+template <int N, int OP, bool NF>
 __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     using G = ColGeom<N>;
     constexpr int E = G::E, CB = G::CB;
@@ -553,7 +613,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     const int s = gg / N, c = gg % N;
     const int j = a.order[a.s0 + s];
     ColLds<N, CB> L(lds_dyn, cl);
-    constexpr float inv_n2 = 1.0f / ((float)N * (float)N);
+    constexpr float nrm = NF ? 1.0f : 1.0f / ((float)N * (float)N);
     constexpr int SETS = (OP == OP_LS) ? 3 : 1;
 
     float i0[E], i1[E], i2[E];
@@ -573,6 +633,10 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
             for (int e = 0; e < E; ++e) u[set][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
         }
         fftk<N, E, -1, SETS>(u, t, Ls);
+        if constexpr (NF) {
+            apply_qy<N, E, SETS, SETS, false>(u, a.prop, t);
+            fftk<N, E, +1, SETS>(u, t, Ls);
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             i0[e] += cnorm(u[0][e]);
@@ -588,8 +652,8 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int q = out_index<N, E, -1>(t, e);
-        const float inten = i0[e] * inv_n2 + (a.bg != nullptr ? a.bg[q * N + c] : 0.0f);
+        const int q = det_row<N, E, NF>(t, e);
+        const float inten = i0[e] * nrm + (a.bg != nullptr ? a.bg[q * N + c] : 0.0f);
         if constexpr (OP == OP_ICALC) {
             if (active) a.icalc[((size_t)j * N + q) * N + c] = inten;
         } else {
@@ -602,7 +666,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
             } else {
                 const float d1 = 1.0f - iob / ifl;
                 const float d2 = (iob / ifl) / ifl;
-                const float j1 = i1[e] * inv_n2, j2 = i2[e] * inv_n2;
+                const float j1 = i1[e] * nrm, j2 = i2[e] * nrm;
                 acc0 += (double)(d1 * j1);
                 acc1 += (double)(d2 * j1 * j1 + 2.0f * d1 * j2);
             }

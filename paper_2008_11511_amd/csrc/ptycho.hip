@@ -115,7 +115,7 @@ struct Layout {
     size_t nlist_ints, npslots;   // object-gather block/reduce lists, partial slots
     size_t nent_max, nfr_max, nred;
     size_t off_offs, off_order, off_lists, off_ent_fr, off_opart, off_scr, off_q, off_pint, off_numO, off_denO,
-        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, off_s2, off_bsum, total;
+        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, off_s2, off_bsum, off_prop, total;
 };
 
 // Frame chunks of the all-frame probe gather: enough blocks to fill the
@@ -184,6 +184,9 @@ static Layout layout_for(const ptycho_desc_t &d) {
     const bool bgu = (d.flags & PTYCHO_FLAG_BACKGROUND) != 0;
     L.off_s2 = o; o = up(o + (bgu ? sizeof(float) * (size_t)L.S * n2 : 0));
     L.off_bsum = o; o = up(o + (bgu ? sizeof(double) * n2 : 0));
+    // near field: the transfer-function factors Qy / N, Qx / N
+    const bool nfg = (d.flags & PTYCHO_FLAG_NEAR_FIELD) != 0;
+    L.off_prop = o; o = up(o + (nfg ? sizeof(float2) * 2 * (size_t)N : 0));
     L.total = o;
     return L;
 }
@@ -217,6 +220,9 @@ struct ptycho_plan_s {
     float *bg = nullptr;     // caller's background [N][N] (set_background), or null
     float *s2 = nullptr;     // [S][N][N] with PTYCHO_FLAG_BACKGROUND
     double *bsum = nullptr;  // [N][N]
+    float2 *prop = nullptr;  // [2][N] with PTYCHO_FLAG_NEAR_FIELD
+    bool nf_ready = false;   // Fresnel parameters set
+    std::vector<float2> h_prop;
     float *pint, *denO, *denP, *pden, *part;
     double *red, *scal;
     int ntx, nty;
@@ -269,7 +275,8 @@ static int check_desc(const ptycho_desc_t *d) {
     if (d->stack < 0) return fail(PTYCHO_E_INVALID, "negative stack");
     if (!(d->obj_inertia >= 0.0f) || !(d->probe_inertia >= 0.0f)) return fail(PTYCHO_E_INVALID, "negative inertia");
     if (!(d->icalc_floor > 0.0f)) return fail(PTYCHO_E_INVALID, "icalc_floor must be > 0");
-    if (d->flags & ~PTYCHO_FLAG_BACKGROUND) return fail(PTYCHO_E_INVALID, "unknown descriptor flag");
+    if (d->flags & ~(PTYCHO_FLAG_BACKGROUND | PTYCHO_FLAG_NEAR_FIELD))
+        return fail(PTYCHO_E_INVALID, "unknown descriptor flag");
     return PTYCHO_OK;
 }
 
@@ -524,6 +531,7 @@ extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets
         p->s2 = (float *)(p->ws + L.off_s2);
         p->bsum = (double *)(p->ws + L.off_bsum);
     }
+    if (d->flags & PTYCHO_FLAG_NEAR_FIELD) p->prop = (float2 *)(p->ws + L.off_prop);
     p->ntx = (d->obj_nx + OTILE_X - 1) / OTILE_X;
     p->nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
 
@@ -580,6 +588,43 @@ extern "C" int ptycho_plan_set_background(ptycho_plan_t p, float *bg) {
     if (!p) return fail(PTYCHO_E_INVALID, "null plan");
     p->bg = bg;
     return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_set_near_field(ptycho_plan_t p, double fy, double fx) {
+    if (!p) return fail(PTYCHO_E_INVALID, "null plan");
+    if (!p->prop) return fail(PTYCHO_E_INVALID, "a near-field plan needs PTYCHO_FLAG_NEAR_FIELD");
+    if (!std::isfinite(fy) || !std::isfinite(fx)) return fail(PTYCHO_E_INVALID, "non-finite Fresnel parameter");
+    const int N = p->d.n;
+    // exp(-i f u'^2) / N in double, the phase reduced modulo 2 pi first
+    std::vector<float2> h(2 * (size_t)N);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int axis = 0; axis < 2; ++axis) {
+        const double f = axis == 0 ? fy : fx;
+        for (int u = 0; u < N; ++u) {
+            const double us = (u < N / 2) ? u : u - N;
+            const double ph = std::fmod(f * us * us, two_pi);
+            h[(size_t)axis * N + u] = make_float2((float)(std::cos(ph) / N), (float)(-std::sin(ph) / N));
+        }
+    }
+    p->h_prop.swap(h);
+    hipError_t e = upload_tables({{p->prop, p->h_prop.data(), sizeof(float2) * p->h_prop.size()}}, p->stream);
+    if (e != hipSuccess) return fail(PTYCHO_E_HIP, std::string("near-field table upload: ") + hipGetErrorString(e));
+    p->nf_ready = true;
+    return PTYCHO_OK;
+}
+
+// Entry points that propagate need the Fresnel parameters of a near-field plan.
+static int check_geometry(const ptycho_plan_s *p) {
+    if (p->prop && !p->nf_ready)
+        return fail(PTYCHO_E_INVALID, "near-field plan without Fresnel parameters (ptycho_plan_set_near_field)");
+    return PTYCHO_OK;
+}
+
+// Calls f(std::true_type) on a near-field plan, f(std::false_type) otherwise.
+template <class F>
+static int with_nf(const ptycho_plan_s *p, F &&f) {
+    if (p->prop) return f(std::true_type{});
+    return f(std::false_type{});
 }
 
 extern "C" int ptycho_plan_set_stream(ptycho_plan_t p, void *stream) {
@@ -655,6 +700,7 @@ static StackArgs stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, 
     a.iobs = p->iobs;
     a.bg = p->bg;
     a.mask = p->mask;
+    a.prop = p->prop;
     a.eps = p->d.icalc_floor;
     return a;
 }
@@ -675,19 +721,20 @@ static int cols_blocks(int sn) {
     return (int)(((long)sn * N + ColGeom<N>::CB - 1) / ColGeom<N>::CB);
 }
 
-template <int N, int K, int OP>
+template <int N, int K, int OP, bool NF>
 static void launch_cols_joint(const StackArgs &a, hipStream_t s) {
     const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * ColJoint<N, K>::BUFS;
-    static const hipError_t attr = set_dyn_lds(k_cols_joint<N, K, OP>, lds);
+    static const hipError_t attr = set_dyn_lds(k_cols_joint<N, K, OP, NF>, lds);
     (void)attr;
-    hipLaunchKernelGGL((k_cols_joint<N, K, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
+    hipLaunchKernelGGL((k_cols_joint<N, K, OP, NF>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s,
+                       a);
 }
-template <int N, int OP>
+template <int N, int OP, bool NF>
 static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
     const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * (OP == OP_LS ? 3 : 1);
-    static const hipError_t attr = set_dyn_lds(k_cols_seq<N, OP>, lds);
+    static const hipError_t attr = set_dyn_lds(k_cols_seq<N, OP, NF>, lds);
     (void)attr;
-    hipLaunchKernelGGL((k_cols_seq<N, OP>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
+    hipLaunchKernelGGL((k_cols_seq<N, OP, NF>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
 }
 
 // log2 of the tile width of exit waves at psi: the stack scratch is stored in
@@ -782,11 +829,11 @@ static int zero_sums(ptycho_plan_s *p, unsigned acc) {
     return st;
 }
 
-template <int N, int K, int MODE>
+template <int N, int K, int MODE, bool NF>
 static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
     const dim3 grid((unsigned)(((long)a.S * N + InvRowGeom<N>::RQ - 1) / InvRowGeom<N>::RQ));
-    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true>), grid, dim3(64 * K), 0, s, a);
-    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false>), grid, dim3(64 * K), 0, s, a);
+    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true, NF>), grid, dim3(64 * K), 0, s, a);
+    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false, NF>), grid, dim3(64 * K), 0, s, a);
 }
 
 // One pass over all stacks: forward rows, column op, inverse rows and the
@@ -796,7 +843,7 @@ static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
 // (from the inverse row pass's per-frame terms), the probe sums (only for
 // the gradient, whose two sums are taken at the same point; they read the
 // exit waves from the scratch).
-template <int N, int K>
+template <int N, int K, bool NF>
 static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind,
                         unsigned acc, bool upd_bg = false) {
     const int J = p->d.n_frames, S = p->L.S;
@@ -819,14 +866,14 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
-            if (kind == 1) hipLaunchKernelGGL((k_rows_fwd<N, IN_DM>), rg, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), rg, dim3(256), 0, s, a);
+            if (kind == 1) hipLaunchKernelGGL((k_rows_fwd<N, IN_DM, NF>), rg, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI, NF>), rg, dim3(256), 0, s, a);
         }
         {
             Timed tm(p, TC_COLS);
-            if (kind == 2) launch_cols_joint<N, K, OP_GRAD>(a, s);
-            else if (kind == 1) launch_cols_joint<N, K, OP_CORR>(a, s);
-            else launch_cols_joint<N, K, OP_PROJECT>(a, s);
+            if (kind == 2) launch_cols_joint<N, K, OP_GRAD, NF>(a, s);
+            else if (kind == 1) launch_cols_joint<N, K, OP_CORR, NF>(a, s);
+            else launch_cols_joint<N, K, OP_PROJECT, NF>(a, s);
         }
         if (upd_bg) {
             const long n2 = (long)N * N;
@@ -836,10 +883,10 @@ static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         }
         {
             Timed tm(p, TC_ROWS_INV);
-            if (kind == 1) launch_rows_inv<N, K, OUT_DM>(a, wq, s);
-            else if (store) launch_rows_inv<N, K, OUT_STORE>(a, wq, s);
-            else if (acc & ACC_PROBE) launch_rows_inv<N, K, OUT_SCR>(a, wq, s);
-            else launch_rows_inv<N, K, OUT_NONE>(a, wq, s);
+            if (kind == 1) launch_rows_inv<N, K, OUT_DM, NF>(a, wq, s);
+            else if (store) launch_rows_inv<N, K, OUT_STORE, NF>(a, wq, s);
+            else if (acc & ACC_PROBE) launch_rows_inv<N, K, OUT_SCR, NF>(a, wq, s);
+            else launch_rows_inv<N, K, OUT_NONE, NF>(a, wq, s);
         }
         LAUNCHCHK();
         int st = PTYCHO_OK;
@@ -869,11 +916,17 @@ static int check_plan_ptrs(ptycho_plan_t p, const void *a, const void *b) {
     return PTYCHO_OK;
 }
 
+// The same for the entry points that propagate to the detector.
+static int check_prop_ptrs(ptycho_plan_t p, const void *a, const void *b) {
+    const int st = check_plan_ptrs(p, a, b);
+    return st ? st : check_geometry(p);
+}
+
 // AP (kind 0) or DM (kind 1) cycles: projection with the per-stack object
 // sums, object normalisation, then the probe sums over all frames with the
 // new object and the probe normalisation.
 static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int n_cycles, uint32_t upd, int kind) {
-    int st = check_plan_ptrs(p, obj, probe);
+    int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (n_cycles < 0) return fail(PTYCHO_E_INVALID, "negative cycle count");
     if (upd & ~(kind == 0 ? 7u : 3u)) return fail(PTYCHO_E_INVALID, "unknown update flag");
@@ -891,7 +944,11 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
             for (int c = 0; c < n_cycles; ++c) {
                 int s2 = PTYCHO_OK;
                 if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
-                if (!s2) s2 = project_pass<N, K>(p, obj, probe, psi, kind, (upd & 1u) ? ACC_OBJ : 0u, upd_bg);
+                if (!s2)
+                    s2 = with_nf(p, [&](auto nf) {
+                        return project_pass<N, K, decltype(nf)::value>(p, obj, probe, psi, kind,
+                                                                        (upd & 1u) ? ACC_OBJ : 0u, upd_bg);
+                    });
                 if (!s2 && upd_bg) {
                     // every stack was projected with the old background
                     const long n2 = (long)N * N;
@@ -932,7 +989,7 @@ extern "C" int ptycho_psi_init(ptycho_plan_t p, const float *obj, const float *p
 }
 
 // Read-only forward passes: LLK, icalc, line search.
-template <int N, int OP>
+template <int N, int OP, bool NF>
 static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, const float *dobj,
                         const float *dprobe, float *icalc, int llk_model = LLK_POISSON) {
     const bool ls = (OP == OP_LS);
@@ -951,12 +1008,12 @@ static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, 
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
-            if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS>), rg, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI>), rg, dim3(256), 0, s, a);
+            if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS, NF>), rg, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI, NF>), rg, dim3(256), 0, s, a);
         }
         {
             Timed tm(p, TC_COLS);
-            launch_cols_seq<N, OP>(a, s);
+            launch_cols_seq<N, OP, NF>(a, s);
         }
         LAUNCHCHK();
     }
@@ -972,7 +1029,10 @@ static int llk_into(ptycho_plan_t p, const float *obj, const float *probe, doubl
     int st = zero_red(p);
     if (st) return st;
     st = with_n(p->d.n, [&](auto nn) {
-        return forward_pass<decltype(nn)::value, OP_LLK>(p, obj, probe, nullptr, nullptr, nullptr, model);
+        return with_nf(p, [&](auto nf) {
+            return forward_pass<decltype(nn)::value, OP_LLK, decltype(nf)::value>(p, obj, probe, nullptr, nullptr,
+                                                                                  nullptr, model);
+        });
     });
     if (st) return st;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
@@ -982,7 +1042,7 @@ static int llk_into(ptycho_plan_t p, const float *obj, const float *probe, doubl
 }
 
 extern "C" int ptycho_llk(ptycho_plan_t p, const float *obj, const float *probe, double *llk) {
-    int st = check_plan_ptrs(p, obj, probe);
+    int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (!llk) return fail(PTYCHO_E_INVALID, "null llk output");
     return llk_into(p, obj, probe, llk, LLK_POISSON);
@@ -990,7 +1050,7 @@ extern "C" int ptycho_llk(ptycho_plan_t p, const float *obj, const float *probe,
 
 extern "C" int ptycho_llk_model(ptycho_plan_t p, const float *obj, const float *probe, int32_t model,
                                 double *llk) {
-    int st = check_plan_ptrs(p, obj, probe);
+    int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (!llk) return fail(PTYCHO_E_INVALID, "null llk output");
     if (model != LLK_POISSON && model != LLK_GAUSSIAN && model != LLK_EUCLIDEAN)
@@ -1033,11 +1093,14 @@ extern "C" int ptycho_check_finite(ptycho_plan_t p, const float *obj, const floa
 }
 
 extern "C" int ptycho_icalc(ptycho_plan_t p, const float *obj, const float *probe, float *icalc) {
-    int st = check_plan_ptrs(p, obj, probe);
+    int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (!icalc) return fail(PTYCHO_E_INVALID, "null icalc output");
     return with_n(p->d.n, [&](auto nn) {
-        return forward_pass<decltype(nn)::value, OP_ICALC>(p, obj, probe, nullptr, nullptr, icalc);
+        return with_nf(p, [&](auto nf) {
+            return forward_pass<decltype(nn)::value, OP_ICALC, decltype(nf)::value>(p, obj, probe, nullptr, nullptr,
+                                                                                    icalc);
+        });
     });
 }
 
@@ -1049,14 +1112,17 @@ static int grad_pass(ptycho_plan_s *p, const float *obj, const float *probe) {
     return with_n(p->d.n, [&](auto nn) {
         constexpr int N = decltype(nn)::value;
         return with_k(p->d.n_modes, [&](auto kk) {
-            return project_pass<N, decltype(kk)::value>(p, obj, probe, nullptr, 2, ACC_OBJ | ACC_PROBE);
+            return with_nf(p, [&](auto nf) {
+                return project_pass<N, decltype(kk)::value, decltype(nf)::value>(p, obj, probe, nullptr, 2,
+                                                                                 ACC_OBJ | ACC_PROBE);
+            });
         });
     });
 }
 
 extern "C" int ptycho_ml_grad(ptycho_plan_t p, const float *obj, const float *probe, float *g_obj, float *g_probe,
                               double *llk) {
-    int st = check_plan_ptrs(p, obj, probe);
+    int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (!g_obj || !g_probe) return fail(PTYCHO_E_INVALID, "null gradient output");
     st = grad_pass(p, obj, probe);
@@ -1077,7 +1143,10 @@ static int ls_pass(ptycho_plan_s *p, const float *obj, const float *probe, const
     int st = zero_red(p);
     if (st) return st;
     st = with_n(p->d.n, [&](auto nn) {
-        return forward_pass<decltype(nn)::value, OP_LS>(p, obj, probe, dobj, dprobe, nullptr);
+        return with_nf(p, [&](auto nf) {
+            return forward_pass<decltype(nn)::value, OP_LS, decltype(nf)::value>(p, obj, probe, dobj, dprobe,
+                                                                                 nullptr);
+        });
     });
     if (st) return st;
     const long n = (long)p->L.nred / 2;
@@ -1089,7 +1158,7 @@ static int ls_pass(ptycho_plan_s *p, const float *obj, const float *probe, const
 
 extern "C" int ptycho_ml_linesearch(ptycho_plan_t p, const float *obj, const float *probe, const float *dobj,
                                     const float *dprobe, double *coef) {
-    int st = check_plan_ptrs(p, obj, probe);
+    int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (!dobj || !dprobe || !coef) return fail(PTYCHO_E_INVALID, "null direction or output");
     return ls_pass(p, obj, probe, dobj, dprobe, coef);
@@ -1110,7 +1179,7 @@ extern "C" int ptycho_ml_state_bytes(ptycho_plan_t p, size_t *bytes) {
 
 extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *state, int32_t n_cycles,
                                uint32_t upd, int32_t reset, double *hist) {
-    int st = check_plan_ptrs(p, obj, probe);
+    int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (!state) return fail(PTYCHO_E_INVALID, "null state");
     if (((uintptr_t)state) % ALIGN) return fail(PTYCHO_E_WORKSPACE, "state not 256-byte aligned");

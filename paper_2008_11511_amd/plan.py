@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FLAG_BACKGROUND, Desc, check, lib
+from ._lib import FLAG_BACKGROUND, FLAG_NEAR_FIELD, Desc, check, lib
 
 
 def _ptr(t: torch.Tensor) -> int:
@@ -84,15 +84,18 @@ def fft2(x: torch.Tensor, inverse: bool = False) -> torch.Tensor:
 class Plan:
     """One scan: positions, observed intensities and mask on one device.
 
-    Tensors: iobs float32 [J][N][N] (FFT order), mask uint8 [N][N] or None,
-    obj complex64 [Ny][Nx], probe complex64 [K][N][N], psi complex64
-    [J][K][N][N].  Work is enqueued on the current torch stream at call time.
+    Tensors: iobs float32 [J][N][N] (FFT order; near field: natural pixel
+    order), mask uint8 [N][N] or None, obj complex64 [Ny][Nx], probe
+    complex64 [K][N][N], psi complex64 [J][K][N][N].  Work is enqueued on the
+    current torch stream at call time.  near_field: Fresnel parameter f, or
+    (f_y, f_x), selecting the near-field geometry (f = pi lambda z / (N dx)^2);
+    None = far field.
     """
 
     def __init__(self, offsets, iobs: torch.Tensor, mask: Optional[torch.Tensor], n_modes: int,
                  obj_shape, stack: int = 0, obj_inertia: float = 1e-2, probe_inertia: float = 1e-2,
                  icalc_floor: float = 1e-20, workspace: Optional[torch.Tensor] = None,
-                 background_update: bool = False):
+                 background_update: bool = False, near_field=None):
         offs = np.ascontiguousarray(offsets, dtype=np.int32)
         if offs.ndim != 2 or offs.shape[1] != 2:
             raise ValueError("offsets must be [J][2]")
@@ -108,7 +111,8 @@ class Plan:
         self.obj_shape = (int(obj_shape[0]), int(obj_shape[1]))
         self.desc = Desc(n, self.k, j, self.obj_shape[0], self.obj_shape[1], int(stack),
                          float(obj_inertia), float(probe_inertia), float(icalc_floor),
-                         FLAG_BACKGROUND if background_update else 0)
+                         (FLAG_BACKGROUND if background_update else 0) |
+                         (FLAG_NEAR_FIELD if near_field is not None else 0))
         self.background = None
         nbytes = ctypes.c_size_t()
         check(lib().ptycho_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
@@ -133,10 +137,21 @@ class Plan:
         st = ctypes.c_int32()
         check(lib().ptycho_plan_stack(self._h, ctypes.byref(st)))
         self.stack = int(st.value)
+        self.near_field = None
+        if near_field is not None:
+            self.set_near_field(near_field)
 
     # -- helpers ---------------------------------------------------------
     def _enter(self):
         check(lib().ptycho_plan_set_stream(self._h, torch.cuda.current_stream(self.device).cuda_stream))
+
+    def set_near_field(self, f) -> None:
+        """Fresnel parameter(s) of a near-field plan: f or (f_y, f_x)."""
+        fy, fx = (float(f), float(f)) if np.ndim(f) == 0 else (float(f[0]), float(f[1]))
+        with torch.cuda.device(self.device):
+            self._enter()
+            check(lib().ptycho_plan_set_near_field(self._h, fy, fx))
+        self.near_field = (fy, fx)
 
     def set_background(self, bg: Optional[torch.Tensor]) -> None:
         """Incoherent background float32 [N][N] (FFT order) used by every later
@@ -285,7 +300,8 @@ class Plan:
         d = self.desc
         new = Plan(offsets, self.iobs, self.mask, self.k, self.obj_shape, stack=d.stack,
                    obj_inertia=d.obj_inertia, probe_inertia=d.probe_inertia, icalc_floor=d.icalc_floor,
-                   workspace=self.workspace, background_update=bool(d.flags & FLAG_BACKGROUND))
+                   workspace=self.workspace, background_update=bool(d.flags & FLAG_BACKGROUND),
+                   near_field=self.near_field)
         if self.background is not None:
             new.set_background(self.background)
         self.close()

@@ -63,12 +63,18 @@ int main() {
     size_t ws = 0;
     EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_E_UNSUPPORTED);
     d.n = 64;
-    d.flags = 2;
+    d.flags = 4;
     EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_E_INVALID);
+    d.flags = PTYCHO_FLAG_NEAR_FIELD | PTYCHO_FLAG_BACKGROUND;
+    size_t ws_nf = 0;
+    EXPECT(ptycho_workspace_bytes(&d, &ws_nf) == PTYCHO_OK);
     d.flags = 0;
+    EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_OK);
+    EXPECT(ws_nf >= ws + 2 * 64 * 8);
     EXPECT(ptycho_workspace_bytes(nullptr, &ws) == PTYCHO_E_INVALID);
     EXPECT(ptycho_plan_dry_run(&d, nullptr, &ws) == PTYCHO_E_INVALID);
     EXPECT(ptycho_plan_set_background(nullptr, nullptr) == PTYCHO_E_INVALID);
+    EXPECT(ptycho_plan_set_near_field(nullptr, 0.1, 0.1) == PTYCHO_E_INVALID);
     std::printf("host checks: %d failures\n", failures);
     return failures == 0 ? 0 : 1;
 }

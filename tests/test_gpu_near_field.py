@@ -1,0 +1,228 @@
+"""Near-field geometry on the GPU against the FP64 oracle (operator
+PropagateNearField in place of FT / IFT in every operator).
+
+Same bar as the far field: relative L2 <= 1e-4 after one cycle or one
+gradient, <= 1e-3 after many cycles.  Every case prints its name first.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from cases import make_problem, rel_l2, small
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+UPD = oracle.UPDATE_OBJECT | oracle.UPDATE_PROBE
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2008_11511_amd as P
+    P.lib()        # raises if the HIP library is missing: no fallback
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dev, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64)
+
+
+def near(n, k, j, f_pixel=0.02, mask_frac=0.0, seed_offset=0, start="apdm", fxy=None):
+    """A small near-field problem: positions in a square of side n/2, object
+    n + n/2 + 32, Fresnel number f_pixel per pixel (fxy overrides (f_y, f_x))."""
+    side = n + n // 2 + 32
+    f = synth.fresnel_parameter(n, f_pixel)
+    wl = small("nf1024", n=n, k=k, j=j, obj=(side, side), step=n / 2.0, mask_frac=mask_frac,
+               photons=1e4 * n * n, fresnel=f, seed_offset=seed_offset)
+    pb = make_problem(wl, start=start)
+    if fxy is not None:
+        # the same truth seen at another (anisotropic) distance
+        pb.nf = fxy
+        pb.iobs = synth.poisson_counts(oracle.simulate_intensity(pb.obj_true, pb.probe_true, pb.offsets, nf=fxy),
+                                       wl.seed)
+    return pb
+
+
+def make_plan(pb, dev, stack=0):
+    from paper_2008_11511_amd import Plan
+    iobs = to_dev(pb.iobs, dev, torch.float32)
+    mask = to_dev(pb.mask, dev, torch.uint8) if pb.mask is not None else None
+    return Plan(pb.offsets, iobs, mask, pb.wl.n_modes, pb.wl.obj_shape, stack=stack, near_field=pb.nf)
+
+
+def state(pb, dev):
+    return (to_dev(pb.obj0, dev, torch.complex64).contiguous(),
+            to_dev(pb.probe0, dev, torch.complex64).contiguous())
+
+
+@pytest.mark.parametrize("n,k,j,mask", [(8, 1, 9, 0.0), (16, 2, 11, 0.0), (64, 1, 13, 0.05), (128, 3, 7, 0.03),
+                                        (256, 1, 5, 0.0), (512, 2, 3, 0.0), (1024, 1, 2, 0.0)])
+def test_near_field_icalc_and_llk_match_oracle(dev, n, k, j, mask):
+    pb = near(n, k, j, mask_frac=mask)
+    say(f"near field icalc/llk n={n} k={k} j={j}")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    ic = host(plan.icalc(o, p))
+    ic_ref = oracle.simulate_intensity(pb.obj0, pb.probe0, pb.offsets, nf=pb.nf)
+    assert rel_l2(ic, ic_ref) < 1e-5
+    for model in oracle.LLK_MODELS:
+        llk = host(plan.llk(o, p, model=model))
+        ref, nobs = oracle.llk(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, model=model, nf=pb.nf)
+        assert llk[1] == nobs
+        assert abs(llk[0] - ref) <= 1e-4 * abs(ref), model
+
+
+def test_near_field_anisotropic_distances(dev):
+    """Different Fresnel parameters on y and x: catches an axis swap."""
+    f = synth.fresnel_parameter(64, 0.02)
+    pb = near(64, 2, 9, fxy=(f, 2.5 * f))
+    say("near field anisotropic n=64 k=2")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    ic = host(plan.icalc(o, p))
+    assert rel_l2(ic, oracle.simulate_intensity(pb.obj0, pb.probe0, pb.offsets, nf=pb.nf)) < 1e-5
+    swapped = oracle.simulate_intensity(pb.obj0, pb.probe0, pb.offsets, nf=(pb.nf[1], pb.nf[0]))
+    assert rel_l2(ic, swapped) > 1e-2
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 1, UPD)
+    psi0 = oracle.psi_init(pb.obj0, pb.probe0, pb.offsets)
+    ro, rp, rpsi = oracle.dm_cycle(pb.obj0, pb.probe0, psi0, pb.offsets, pb.iobs, pb.mask, UPD, nf=pb.nf)
+    assert rel_l2(host(psi), rpsi) < 1e-4
+    assert rel_l2(host(o), ro) < 1e-4
+
+
+@pytest.mark.parametrize("n,k,j,stack", [(16, 2, 13, 5), (64, 1, 17, 0), (128, 3, 9, 4), (256, 1, 6, 0),
+                                         (512, 1, 3, 2), (1024, 1, 2, 0)])
+def test_near_field_dm_and_ap_one_cycle(dev, n, k, j, stack):
+    pb = near(n, k, j, mask_frac=0.03 if n >= 64 else 0.0)
+    say(f"near field DM one cycle n={n} k={k} j={j} stack={stack}")
+    plan = make_plan(pb, dev, stack=stack)
+    o, p = state(pb, dev)
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 1, UPD)
+    psi0 = oracle.psi_init(pb.obj0, pb.probe0, pb.offsets)
+    ro, rp, rpsi = oracle.dm_cycle(pb.obj0, pb.probe0, psi0, pb.offsets, pb.iobs, pb.mask, UPD, nf=pb.nf)
+    assert rel_l2(host(psi), rpsi) < 1e-4
+    assert rel_l2(host(o), ro) < 1e-4
+    assert rel_l2(host(p), rp) < 1e-4
+    say(f"near field AP one cycle n={n} k={k} j={j} stack={stack}")
+    o, p = state(pb, dev)
+    psi_ap = torch.empty_like(psi)
+    plan.ap_cycle(o, p, 1, UPD, psi=psi_ap)
+    ro, rp = oracle.ap_cycle(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, UPD, nf=pb.nf)
+    assert rel_l2(host(o), ro) < 1e-4
+    assert rel_l2(host(p), rp) < 1e-4
+
+
+def test_near_field_dm_many_cycles(dev):
+    pb = near(64, 1, 12, mask_frac=0.03)
+    say("near field DM 50 cycles n=64 k=1 j=12")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 50, UPD)
+    ro, rp = pb.obj0, pb.probe0
+    rpsi = oracle.psi_init(ro, rp, pb.offsets)
+    for _ in range(50):
+        ro, rp, rpsi = oracle.dm_cycle(ro, rp, rpsi, pb.offsets, pb.iobs, pb.mask, UPD, nf=pb.nf)
+    assert rel_l2(host(o), ro) < 1e-3
+    assert rel_l2(host(p), rp) < 1e-3
+
+
+@pytest.mark.parametrize("n,k,j", [(64, 1, 11), (256, 2, 5)])
+def test_near_field_ml_grad_linesearch_and_cycles(dev, n, k, j):
+    pb = near(n, k, j, mask_frac=0.03, start="ml")
+    say(f"near field ML grad n={n} k={k} j={j}")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    go, gp, llk = plan.ml_grad(o, p)
+    ro, rp, rl = oracle.ml_grad(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, nf=pb.nf)
+    assert rel_l2(host(go), ro) < 1e-4
+    assert rel_l2(host(gp), rp) < 1e-4
+    assert abs(host(llk)[0] - rl) < 1e-4 * abs(rl)
+    rng = np.random.default_rng(5)
+    d_o = (rng.standard_normal(pb.obj0.shape) + 1j * rng.standard_normal(pb.obj0.shape)).astype(np.complex64) * 1e-2
+    d_p = (rng.standard_normal(pb.probe0.shape) + 1j * rng.standard_normal(pb.probe0.shape)).astype(np.complex64)
+    d_p *= 1e-2 * np.abs(pb.probe0).max()
+    say(f"near field ML line search n={n}")
+    coef = host(plan.ml_linesearch(o, p, to_dev(d_o, dev, torch.complex64), to_dev(d_p, dev, torch.complex64)))
+    r1, r2 = oracle.linesearch_coefs(pb.obj0, pb.probe0, d_o, d_p, pb.offsets, pb.iobs, pb.mask, nf=pb.nf)
+    assert abs(coef[0] - r1) <= 1e-4 * abs(r1)
+    assert abs(coef[1] - r2) <= 1e-4 * abs(r2)
+    say(f"near field ML 5 cycles n={n}")
+    o, p = state(pb, dev)
+    st = plan.ml_state()
+    hist = torch.zeros(5, dtype=torch.float64, device=dev)
+    plan.ml_cycle(o, p, st, 5, UPD, reset=True, hist=hist)
+    cg = oracle.CGState()
+    ro, rp = pb.obj0, pb.probe0
+    for _ in range(5):
+        ro, rp = oracle.ml_cycle(ro, rp, cg, pb.offsets, pb.iobs, pb.mask, update=UPD, nf=pb.nf)
+    # the first entry is one step from the same state (the per-step bar);
+    # later ones follow the fp32 trajectory, which the fast LLK descent of
+    # the near-field problem amplifies (the many-cycle bar)
+    h = host(hist)
+    np.testing.assert_allclose(h[0], cg.history[0], rtol=1e-4)
+    np.testing.assert_allclose(h, cg.history, rtol=1e-3)
+    assert rel_l2(host(o), ro) < 1e-3
+    assert rel_l2(host(p), rp) < 1e-3
+
+
+def test_near_field_zero_distance_sees_the_exit_waves(dev):
+    pb = near(32, 1, 5)
+    say("near field f=0 n=32")
+    from paper_2008_11511_amd import Plan
+    plan = Plan(pb.offsets, to_dev(pb.iobs, dev, torch.float32), None, 1, pb.wl.obj_shape, near_field=0.0)
+    o, p = state(pb, dev)
+    ic = host(plan.icalc(o, p))
+    ref = (np.abs(oracle.exit_waves(pb.obj0, pb.probe0, pb.offsets)) ** 2).sum(axis=1)
+    assert rel_l2(ic, ref) < 1e-6
+
+
+def test_near_field_arguments_are_checked(dev):
+    from paper_2008_11511_amd import Plan, PtychoError
+    from paper_2008_11511_amd._lib import FLAG_NEAR_FIELD, check, lib
+    pb = near(32, 1, 5)
+    say("near field argument checks")
+    iobs = to_dev(pb.iobs, dev, torch.float32)
+    far = Plan(pb.offsets, iobs, None, 1, pb.wl.obj_shape)
+    with pytest.raises(PtychoError, match="PTYCHO_FLAG_NEAR_FIELD"):
+        far.set_near_field(0.1)
+    plan = Plan(pb.offsets, iobs, None, 1, pb.wl.obj_shape, near_field=0.1)
+    with pytest.raises(PtychoError, match="non-finite"):
+        plan.set_near_field(float("nan"))
+    # a near-field plan whose parameters were never set refuses to propagate
+    raw = Plan(pb.offsets, iobs, None, 1, pb.wl.obj_shape)
+    raw.close()
+    import ctypes
+    d = plan.desc
+    d2 = type(d).from_buffer_copy(d)
+    d2.flags = FLAG_NEAR_FIELD
+    h = ctypes.c_void_p()
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    offs = np.ascontiguousarray(pb.offsets, dtype=np.int32)
+    check(lib().ptycho_plan_create(ctypes.byref(d2), offs.ctypes.data, iobs.data_ptr(), None, ws.data_ptr(),
+                                   plan.workspace_bytes, torch.cuda.current_stream(dev).cuda_stream,
+                                   ctypes.byref(h)))
+    try:
+        o, p = state(pb, dev)
+        out = torch.zeros(2, dtype=torch.float64, device=dev)
+        rc = lib().ptycho_llk(h, o.data_ptr(), p.data_ptr(), out.data_ptr())
+        assert rc == -1 and b"Fresnel" in lib().ptycho_last_error()
+    finally:
+        lib().ptycho_plan_destroy(h)

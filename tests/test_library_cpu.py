@@ -73,12 +73,17 @@ def test_workspace_query_and_descriptor_validation():
     assert h.ptycho_workspace_bytes(ctypes.byref(_desc(n=48)), ctypes.byref(sz)) == -3
     assert h.ptycho_workspace_bytes(ctypes.byref(_desc(n_modes=5)), ctypes.byref(sz)) == -3
     assert h.ptycho_workspace_bytes(ctypes.byref(_desc(obj_nx=32)), ctypes.byref(sz)) == -1
-    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(flags=2)), ctypes.byref(sz)) == -1
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(flags=4)), ctypes.byref(sz)) == -1
     # the background flag reserves S*N*N floats and N*N doubles more
     plain, bgu = ctypes.c_size_t(), ctypes.c_size_t()
     assert h.ptycho_workspace_bytes(ctypes.byref(_desc()), ctypes.byref(plain)) == 0
     assert h.ptycho_workspace_bytes(ctypes.byref(_desc(flags=1)), ctypes.byref(bgu)) == 0
     assert bgu.value >= plain.value + 4 * 10 * 64 * 64 + 8 * 64 * 64
+    # the near-field flag reserves the 2 N transfer-function factors
+    nfw, both = ctypes.c_size_t(), ctypes.c_size_t()
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(flags=2)), ctypes.byref(nfw)) == 0
+    assert h.ptycho_workspace_bytes(ctypes.byref(_desc(flags=3)), ctypes.byref(both)) == 0
+    assert nfw.value >= plain.value + 8 * 2 * 64 and both.value >= bgu.value + 8 * 2 * 64
     assert h.ptycho_workspace_bytes(ctypes.byref(_desc(icalc_floor=0.0)), ctypes.byref(sz)) == -1
     # larger problems need more workspace
     big = ctypes.c_size_t()
