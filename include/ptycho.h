@@ -79,7 +79,7 @@ typedef enum {
 #define PTYCHO_FLAG_BACKGROUND 1u
 #define PTYCHO_FLAG_NEAR_FIELD 2u
 
-/* Problem description.  Supported: N a power of two from 8 to 1024,
+/* Problem description.  Supported: N a power of two from 8 to 2048,
  * 1 <= K <= 4, J >= 1, obj_ny >= N, obj_nx >= N. */
 typedef struct {
     int32_t n;              /* frame side N (power of two)                      */

@@ -140,10 +140,11 @@ template <int N, int E>
 struct FftCfg {
     static constexpr int T = N / E;
     static constexpr int R0 = (N == 8) ? 8 : (N == 16) ? 16 : (N == 32) ? 8 : (N == 64) ? 8
-                            : (N == 512) ? 8 : (E == 16 ? 16 : 8);
+                            : (N == 512) ? 8 : (N == 2048) ? 16 : (E == 16 ? 16 : 8);
     static constexpr int R1 = (N <= 16) ? 1 : (N == 32) ? 4 : (N == 64) ? 8 : (N == 128) ? (E == 16 ? 8 : 4)
-                            : (N == 512) ? 8 : (E == 16 ? 16 : 8);
-    static constexpr int R2 = (N == 128 || N == 256) ? (E == 16 ? 1 : 4) : (N == 512) ? 8 : (N == 1024) ? 4 : 1;
+                            : (N == 512) ? 8 : (N == 2048) ? 16 : (E == 16 ? 16 : 8);
+    static constexpr int R2 = (N == 128 || N == 256) ? (E == 16 ? 1 : 4) : (N == 512) ? 8 : (N == 1024) ? 4
+                            : (N == 2048) ? 8 : 1;
     static constexpr int R3 = (N == 1024 && E == 8) ? 4 : 1;
     static constexpr int P = 1 + (R1 > 1) + (R2 > 1) + (R3 > 1);
     static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
@@ -173,14 +174,14 @@ __device__ __forceinline__ int in_index(int t, int e) { return elem_index<N, E, 
 template <int N, int E, int DIR>
 __device__ __forceinline__ int out_index(int t, int e) { return elem_index<N, E, LastRadix<N, E, DIR>::value>(t, e); }
 
-// Twiddle table exp(-2 pi i m / 1024), m = 0..1023, filled once per device
+// Twiddle table exp(-2 pi i m / 2048), m = 0..2047, filled once per device
 // (read-only for kernels, so loads can be shared between probe modes).
-constexpr int TW_MAX = 1024;
+constexpr int TW_MAX = 2048;
 extern __constant__ float2 g_twiddle[TW_MAX];
 
 template <int DIR>
-__device__ __forceinline__ float2 twiddle(int m_of_1024) {
-    float2 w = g_twiddle[m_of_1024];
+__device__ __forceinline__ float2 twiddle(int m_of_table) {
+    float2 w = g_twiddle[m_of_table];
     if constexpr (DIR > 0) w.y = -w.y;
     return w;
 }
@@ -188,8 +189,8 @@ __device__ __forceinline__ float2 twiddle(int m_of_1024) {
 // w[r] = w1^r for r = 1..R-1 from one table load, by a balanced product tree
 // (at most 4 multiplications deep).
 template <int R, int DIR>
-__device__ __forceinline__ void twiddle_powers(int m_of_1024, float2 *w) {
-    w[1] = twiddle<DIR>(m_of_1024);
+__device__ __forceinline__ void twiddle_powers(int m_of_table, float2 *w) {
+    w[1] = twiddle<DIR>(m_of_table);
     if constexpr (R > 2) {
         w[2] = cmul(w[1], w[1]);
         w[3] = cmul(w[2], w[1]);
@@ -227,7 +228,7 @@ __device__ __forceinline__ void fft_pass(float2 *u, int t, Lds &lds) {
         if constexpr (L > 1) {
             const int i = t + b * T;
             const int k = i & (L - 1);
-            // exp(DIR 2 pi i r k / (R L)) = (table[k * 1024 / (R L)])^r
+            // exp(DIR 2 pi i r k / (R L)) = (table[k * TW_MAX / (R L)])^r
             float2 w[R];
             twiddle_powers<R, DIR>(k * (TW_MAX / (R * L)), w);
 #pragma unroll

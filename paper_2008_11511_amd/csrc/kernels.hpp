@@ -37,18 +37,20 @@ struct RowGeom {
 };
 // The inverse row pass runs one wavefront per probe mode over the same
 // RQ rows, so that the modes of a pixel meet in one block.
+// (Rows longer than 64 x 16 elements use N/64 elements per thread, so that a
+// row still fits one wavefront.)
 template <int N>
 struct InvRowGeom {
-    static constexpr int E = RowGeom<N>::E, T = N / E, RQ = 64 / T;
+    static constexpr int E = (N / RowGeom<N>::E > 64) ? N / 64 : RowGeom<N>::E, T = N / E, RQ = 64 / T;
     static constexpr int ROW_F2 = N + N / 16;        // one RowLds row
 };
 // Column transforms keep all K modes in registers at once, so they use 8
-// elements per thread (16 at N = 16), CB adjacent columns per block (a
-// 128-byte row segment at CB = 16; 4 columns at N = 1024 keep the block at
-// 512 threads, so that a thread may hold 256 registers).
+// elements per thread (16 at N = 16 and N = 2048), CB adjacent columns per
+// block (a 128-byte row segment at CB = 16; 4 columns from N = 1024 keep the
+// block at 512 threads, so that a thread may hold 256 registers).
 template <int N>
 struct ColGeom {
-    static constexpr int E = (N == 16) ? 16 : 8, T = N / E;
+    static constexpr int E = (N == 16 || N >= 2048) ? 16 : 8, T = N / E;
     static constexpr int CB = (N >= 1024) ? 4 : (N >= 256) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
     static constexpr int THREADS = CB * T;
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * CB : 1;   // one transform buffer
@@ -113,6 +115,14 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p) {
 __device__ __forceinline__ void st_stream(float2 *p, float2 v) {
     __builtin_nontemporal_store(v.x, &p->x);
     __builtin_nontemporal_store(v.y, &p->y);
+}
+
+// An opaque copy of an index: transforms chained back to back (near field)
+// then cannot share their twiddle loads, which would keep the twiddles of one
+// transform in registers through the next ones.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
 // Object tile of the atomic-free object gather.
@@ -259,9 +269,10 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
         if constexpr (NF) {
             // Dx: the x factor of the transfer function, then back to x
             const float2 *qx = a.prop + N;
+            const int t1 = opaque(t);
 #pragma unroll
-            for (int e = 0; e < E; ++e) u[set][e] = cmul(u[set][e], qx[out_index<N, E, -1>(t, e)]);
-            fft1d<N, E, +1>(u[set], t, L);
+            for (int e = 0; e < E; ++e) u[set][e] = cmul(u[set][e], qx[out_index<N, E, -1>(t1, e)]);
+            fft1d<N, E, +1>(u[set], t1, L);
         }
         float2 *dst = a.scr + ((size_t)s * SETS * a.K + set * a.K + k) * N * N;
         if (active) {
@@ -465,6 +476,15 @@ __global__ __launch_bounds__(256) void k_probe_intensity(const float2 *probe, in
 // views alone, without reading the old exit waves again.
 enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4, OP_CORR = 5 };
 
+// Exchange buffers of the read-only column pass: the line search's three
+// transforms of a mode run pass by pass together while their buffers fit
+// 96 KiB of LDS, one after the other through one buffer beyond that.
+template <int N, int OP>
+struct ColSeqBufs {
+    static constexpr int SETS = (OP == OP_LS) ? 3 : 1;
+    static constexpr int value = ((size_t)SETS * ColGeom<N>::LDS_F2 * 8 <= 96 * 1024) ? SETS : 1;
+};
+
 // Waves per SIMD a column kernel is compiled for: the DM form with up to 3
 // modes fits 128 registers without spilling, which gives 4 waves instead of
 // 3 (measured faster); the others keep the compiler's choice.
@@ -548,8 +568,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP, NF>::va
     col_transforms<N, E, -1, K, SEQ>(u, t, L);
     if constexpr (NF) {
         // Dy: to the detector plane
-        apply_qy<N, E, K, K, false>(u, a.prop, t);
-        col_transforms<N, E, +1, K, SEQ>(u, t, L);
+        const int t1 = opaque(t);
+        apply_qy<N, E, K, K, false>(u, a.prop, t1);
+        col_transforms<N, E, +1, K, SEQ>(u, t1, L);
     }
 
     double acc = 0.0;
@@ -578,12 +599,14 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP, NF>::va
 #pragma unroll
         for (int k = 0; k < K; ++k) u[k][e] = cscale(u[k][e], sc);
     }
+    const int t3 = NF ? opaque(t) : t;
     if constexpr (NF) {
         // Dy^-1: back from the detector plane (the inverse transform below)
-        col_transforms<N, E, -1, K, SEQ>(u, t, L);
-        apply_qy<N, E, K, K, true>(u, a.prop, t);
+        const int t2 = opaque(t);
+        col_transforms<N, E, -1, K, SEQ>(u, t2, L);
+        apply_qy<N, E, K, K, true>(u, a.prop, t2);
     }
-    col_transforms<N, E, +1, K, SEQ>(u, t, L);
+    col_transforms<N, E, +1, K, SEQ>(u, t3, L);
     if (active) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -614,7 +637,8 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     const int j = a.order[a.s0 + s];
     ColLds<N, CB> L(lds_dyn, cl);
     constexpr float nrm = NF ? 1.0f : 1.0f / ((float)N * (float)N);
-    constexpr int SETS = (OP == OP_LS) ? 3 : 1;
+    constexpr int SETS = ColSeqBufs<N, OP>::SETS;
+    constexpr bool ONE_BUF = ColSeqBufs<N, OP>::value == 1 && SETS > 1;
 
     float i0[E], i1[E], i2[E];
 #pragma unroll
@@ -622,7 +646,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     // the SETS transforms of a mode run pass by pass together
     ColLds<N, CB> Ls[SETS];
 #pragma unroll
-    for (int set = 0; set < SETS; ++set) Ls[set] = ColLds<N, CB>(lds_dyn + set * G::LDS_F2, cl);
+    for (int set = 0; set < SETS; ++set) Ls[set] = ColLds<N, CB>(lds_dyn + (ONE_BUF ? 0 : set) * G::LDS_F2, cl);
     (void)L;
     for (int k = 0; k < a.K; ++k) {
         float2 u[SETS][E];
@@ -632,10 +656,11 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
 #pragma unroll
             for (int e = 0; e < E; ++e) u[set][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
         }
-        fftk<N, E, -1, SETS>(u, t, Ls);
+        col_transforms<N, E, -1, SETS, ONE_BUF>(u, t, Ls);
         if constexpr (NF) {
-            apply_qy<N, E, SETS, SETS, false>(u, a.prop, t);
-            fftk<N, E, +1, SETS>(u, t, Ls);
+            const int t1 = opaque(t);
+            apply_qy<N, E, SETS, SETS, false>(u, a.prop, t1);
+            col_transforms<N, E, +1, SETS, ONE_BUF>(u, t1, Ls);
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {

@@ -69,7 +69,7 @@ static int ensure_twiddles() {
 
 // ------------------------------------------------------------- sizes -------
 static bool supported_n(int n) {
-    return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
+    return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048;
 }
 
 template <class F>
@@ -83,6 +83,7 @@ static int with_n(int n, F &&f) {
         case 256: return f(std::integral_constant<int, 256>());
         case 512: return f(std::integral_constant<int, 512>());
         case 1024: return f(std::integral_constant<int, 1024>());
+        case 2048: return f(std::integral_constant<int, 2048>());
         default: return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
     }
 }
@@ -267,7 +268,7 @@ struct Timed {
 // ---------------------------------------------------------------- validate --
 static int check_desc(const ptycho_desc_t *d) {
     if (!d) return fail(PTYCHO_E_INVALID, "null descriptor");
-    if (!supported_n(d->n)) return fail(PTYCHO_E_UNSUPPORTED, "frame size must be a power of two from 8 to 1024");
+    if (!supported_n(d->n)) return fail(PTYCHO_E_UNSUPPORTED, "frame size must be a power of two from 8 to 2048");
     if (d->n_modes < 1 || d->n_modes > 4) return fail(PTYCHO_E_UNSUPPORTED, "probe modes must be 1..4");
     if (d->n_frames < 1) return fail(PTYCHO_E_INVALID, "n_frames must be >= 1");
     if (d->obj_ny < d->n || d->obj_nx < d->n) return fail(PTYCHO_E_INVALID, "object smaller than a frame");
@@ -731,7 +732,7 @@ static void launch_cols_joint(const StackArgs &a, hipStream_t s) {
 }
 template <int N, int OP, bool NF>
 static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * (OP == OP_LS ? 3 : 1);
+    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * ColSeqBufs<N, OP>::value;
     static const hipError_t attr = set_dyn_lds(k_cols_seq<N, OP, NF>, lds);
     (void)attr;
     hipLaunchKernelGGL((k_cols_seq<N, OP, NF>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);

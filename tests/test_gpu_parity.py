@@ -55,7 +55,7 @@ def host(t):
 
 
 # ---------------------------------------------------------------- FFT -----
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024, 2048])
 def test_fft2_matches_oracle(dev, n):
     from paper_2008_11511_amd import fft2
     rng = np.random.default_rng(n)
@@ -96,7 +96,7 @@ def test_views_are_bit_exact(dev):
 
 # ------------------------------------------------- forward model / LLK ----
 @pytest.mark.parametrize("n,k,j", [(8, 2, 25), (16, 1, 37), (32, 2, 7), (64, 1, 100), (128, 3, 21), (256, 3, 12),
-                                   (512, 4, 5), (1024, 2, 3)])
+                                   (512, 4, 5), (1024, 2, 3), (2048, 1, 2)])
 def test_icalc_and_llk_match_oracle(dev, n, k, j):
     side = max(256, 2 * n + 64)
     wl = small("dm256", n=n, k=k, j=j, obj=(side, side), step=max(2.0, n / 16), mask_frac=0.03 if n >= 64 else 0)
@@ -175,7 +175,8 @@ def test_ap_ten_cycles_full_ap64(dev):
 
 
 @pytest.mark.parametrize("n,k,j,stack", [(64, 3, 60, 0), (128, 3, 33, 7), (256, 3, 24, 0), (512, 4, 6, 4),
-                                         (16, 2, 37, 5), (32, 1, 9, 3), (8, 3, 30, 4), (1024, 4, 3, 2)])
+                                         (16, 2, 37, 5), (32, 1, 9, 3), (8, 3, 30, 4), (1024, 4, 3, 2),
+                                         (2048, 2, 2, 0)])
 def test_dm_one_cycle(dev, n, k, j, stack):
     side = max(256, 2 * n + 64)
     wl = small("dm256", n=n, k=k, j=j, obj=(side, side), step=max(2.0, n / 16), mask_frac=0.03 if n >= 64 else 0)
