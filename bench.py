@@ -51,21 +51,27 @@ def build_workload(wl, torch, dev, start):
     """Seeded inputs of one workload, resident on the GPU."""
     import synth
     import paper_2008_11511_amd as P
+    near = wl.geometry == "near"
+    nf = wl.fresnel if near else None
     obj_t = synth.object_truth(wl.obj_shape, wl.seed)
-    probe_t = synth.probe_modes(wl.n, wl.n_modes, wl.seed)
-    pos = synth.spiral_positions(wl.n_frames, wl.step)
+    if near:
+        probe_t = synth.near_field_probe(wl.n, wl.n_modes, wl.seed)
+        pos = synth.random_positions(wl.n_frames, wl.step, wl.seed)
+    else:
+        probe_t = synth.probe_modes(wl.n, wl.n_modes, wl.seed)
+        pos = synth.spiral_positions(wl.n_frames, wl.step)
     offs = P.offsets_from_positions(pos, wl.n, wl.obj_shape)
     probe_t = probe_t * synth.probe_photon_scale(obj_t, probe_t, offs, wl.photons)
     o_t = torch.from_numpy(obj_t.astype(np.complex64)).to(dev)
     p_t = torch.from_numpy(probe_t.astype(np.complex64)).to(dev)
     zero = torch.zeros((wl.n_frames, wl.n, wl.n), dtype=torch.float32, device=dev)
-    sim = P.Plan(offs, zero, None, wl.n_modes, wl.obj_shape)
+    sim = P.Plan(offs, zero, None, wl.n_modes, wl.obj_shape, near_field=nf)
     inten = sim.icalc(o_t, p_t)
     gen = torch.Generator(device=dev)
     gen.manual_seed(wl.seed)
     iobs = torch.poisson(inten.clamp_min(0), generator=gen).contiguous()
     del sim, zero, inten
-    m = synth.gap_mask(wl.n, wl.mask_frac, wl.seed)
+    m = synth.gap_mask(wl.n, wl.mask_frac, wl.seed, fft_order=not near)
     mask = torch.from_numpy(m).to(dev) if m is not None else None
     if start == "ml":
         o0 = synth.perturb_object(obj_t, wl.seed)
@@ -160,6 +166,9 @@ def main():
     ap.add_argument("--large-cycles", default="2,5",
                     help="AP,DM cycles timed on the 4000 x 512^2 x 4-mode scan (the full chain is 20,50; "
                          "0,0 skips it)")
+    ap.add_argument("--near-cycles", default="20,10",
+                    help="DM,ML cycles timed on the near-field scan (17 x 2048^2, one probe; the paper's chain "
+                         "is 400,100; 0,0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the served mixed workload (0 = skip)")
     ap.add_argument("--serve-seed", type=int, default=7, help="seed of the arrival trace")
@@ -341,6 +350,53 @@ def main():
         del plan3, psi3, iobs3, o3, p3
         torch.cuda.empty_cache()
 
+    near = None
+    n_ndm, n_nml = (int(x) for x in args.near_cycles.split(","))
+    if n_ndm + n_nml > 0:
+        torch.cuda.empty_cache()
+        wl4 = synth.workload("nf2048")
+        log(f"building {wl4.name}: {wl4.n_frames} frames {wl4.n}x{wl4.n}, {wl4.n_modes} mode, object "
+            f"{wl4.obj_shape[0]}x{wl4.obj_shape[1]}, Fresnel parameter {wl4.fresnel:.3e}")
+        offs4, iobs4, mask4, o4, p4, _ = build_workload(wl4, torch, dev, "apdm")
+        plan4 = P.Plan(offs4, iobs4, mask4, wl4.n_modes, wl4.obj_shape, near_field=wl4.fresnel)
+        near = {"workload": "nf2048: near field, 17 frames 2048x2048, 1 probe mode, object 2368x2368, "
+                            "1e4 photons/pixel, Fresnel number 4e-3 per pixel",
+                "frames": wl4.n_frames, "frame": wl4.n, "modes": wl4.n_modes, "stack": plan4.stack}
+        if n_ndm:
+            psi4 = plan4.psi_init(o4, p4)
+            dt4, per4 = timed_dm(plan4, o4, p4, psi4, n_ndm, 2, torch)
+            algo4 = algorithmic_bytes(wl4, 0, "dm")
+            k4 = {}
+            for name, (ms, n) in per4.items():
+                if n:
+                    k4[name] = {"avg_us": round(1e3 * ms / n, 2), "launches": n}
+                    if name in algo4:
+                        k4[name]["alg_GBs"] = round(algo4[name] * n_ndm / n / (ms / n * 1e-3) / 1e9, 1)
+            near.update({"dm_cycles": n_ndm, "dm_ms_per_cycle": round(dt4 / n_ndm * 1e3, 3),
+                         "dm_frames_cycles_per_s": round(wl4.n_frames * n_ndm / dt4, 1), "dm_kernels": k4})
+            del psi4
+        if n_nml:
+            o4, p4 = build_workload(wl4, torch, dev, "ml")[3:5]
+            st4 = plan4.ml_state()
+            plan4.ml_cycle(o4, p4, st4, 1, 3, reset=True)                 # warm-up
+            hist4 = torch.zeros(n_nml, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan4.ml_cycle(o4, p4, st4, n_nml, 3, reset=True, hist=hist4)
+            torch.cuda.synchronize()
+            t_ml4 = time.perf_counter() - t0
+            h4 = hist4.cpu().numpy()
+            near.update({"ml_cycles": n_nml, "ml_ms_per_cycle": round(t_ml4 / n_nml * 1e3, 3),
+                         "ml_frames_cycles_per_s": round(wl4.n_frames * n_nml / t_ml4, 1),
+                         "llk_first": float(h4[0]), "llk_last": float(h4[-1])})
+            del st4
+        near["paper_context"] = {"dm_ms_per_cycle": 39, "ml_ms_per_cycle": 84,
+                                 "note": "near field, 17 frames 2048x2048, 1 probe, one NVIDIA V100 (Table 1); "
+                                         "other hardware, context only"}
+        log(f"near field: DM {near.get('dm_ms_per_cycle')} ms/cycle, ML {near.get('ml_ms_per_cycle')} ms/cycle")
+        del plan4, iobs4, o4, p4
+        torch.cuda.empty_cache()
+
     serve = None
     if args.serve_requests > 0:
         from paper_2008_11511_amd.serve import serve_trace
@@ -410,6 +466,7 @@ def main():
         "ml": ml,
         "extra": extra or None,
         "large": large,
+        "near_field": near,
         "serve": serve,
         "cpu_baseline": cpu,
         "paper_context": {"value": 22727, "unit": "frames*cycles/s",

@@ -243,43 +243,54 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     constexpr int SETS = (MODE == IN_LS) ? 3 : 1;
     const float2 *prow = a.probe + ((size_t)k * N + y) * N;
     const float2 *drow = (MODE == IN_LS) ? a.dprobe + ((size_t)k * N + y) * N : nullptr;
-    float2 u[SETS][E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int x = in_index<N, E, -1>(t, e);
-        const float2 ov = a.obj[orow + x];
-        const float2 p = prow[x];
-        if constexpr (MODE == IN_LS) {
-            const float2 dv = a.dobj[orow + x];
-            const float2 dp = drow[x];
-            u[0][e] = cmul(ov, p);
-            u[1][e] = cadd(cmul(dv, p), cmul(ov, dp));
-            u[2][e] = cmul(dv, dp);
-        } else if constexpr (MODE == IN_DM) {
-            const float2 phi = cmul(ov, p);
-            const float2 ps = a.psi[(((size_t)j * a.K + k) * N + y) * N + x];
-            u[0][e] = make_float2(2.0f * phi.x - ps.x, 2.0f * phi.y - ps.y);
-        } else {
-            u[0][e] = cmul(ov, p);
-        }
-    }
+    // The three line-search rows held together need 3E complex registers;
+    // at 2048 points each set is formed and transformed on its own instead
+    // (the object and probe rows are read again, from the caches).
+    constexpr bool SPLIT = (MODE == IN_LS) && N >= 2048;
+    float2 u[SPLIT ? 1 : SETS][E];
 #pragma unroll
     for (int set = 0; set < SETS; ++set) {
-        fft1d<N, E, -1>(u[set], t, L);
+        const int sl = SPLIT ? 0 : set;
+        if (SPLIT || set == 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int x = in_index<N, E, -1>(t, e);
+                const float2 ov = a.obj[orow + x];
+                const float2 p = prow[x];
+                if constexpr (SPLIT) {
+                    const float2 dv = a.dobj[orow + x], dp = drow[x];
+                    u[0][e] = set == 0 ? cmul(ov, p) : set == 1 ? cadd(cmul(dv, p), cmul(ov, dp)) : cmul(dv, dp);
+                } else if constexpr (MODE == IN_LS) {
+                    const float2 dv = a.dobj[orow + x];
+                    const float2 dp = drow[x];
+                    u[0][e] = cmul(ov, p);
+                    u[1][e] = cadd(cmul(dv, p), cmul(ov, dp));
+                    u[2][e] = cmul(dv, dp);
+                } else if constexpr (MODE == IN_DM) {
+                    const float2 phi = cmul(ov, p);
+                    const float2 ps = a.psi[(((size_t)j * a.K + k) * N + y) * N + x];
+                    u[0][e] = make_float2(2.0f * phi.x - ps.x, 2.0f * phi.y - ps.y);
+                } else {
+                    u[0][e] = cmul(ov, p);
+                }
+            }
+        }
+        const int tt = SPLIT ? opaque(t) : t;
+        fft1d<N, E, -1>(u[sl], tt, L);
         if constexpr (NF) {
             // Dx: the x factor of the transfer function, then back to x
             const float2 *qx = a.prop + N;
-            const int t1 = opaque(t);
+            const int t1 = opaque(tt);
 #pragma unroll
-            for (int e = 0; e < E; ++e) u[set][e] = cmul(u[set][e], qx[out_index<N, E, -1>(t1, e)]);
-            fft1d<N, E, +1>(u[set], t1, L);
+            for (int e = 0; e < E; ++e) u[sl][e] = cmul(u[sl][e], qx[out_index<N, E, -1>(t1, e)]);
+            fft1d<N, E, +1>(u[sl], t1, L);
         }
         float2 *dst = a.scr + ((size_t)s * SETS * a.K + set * a.K + k) * N * N;
         if (active) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int x = NF ? out_index<N, E, +1>(t, e) : out_index<N, E, -1>(t, e);
-                st_stream(dst + scr_at<N>(y, x), u[set][e]);
+                st_stream(dst + scr_at<N>(y, x), u[sl][e]);
             }
         }
     }
@@ -490,7 +501,8 @@ struct ColSeqBufs {
 // 3 (measured faster); the others keep the compiler's choice.
 template <int N, int K, int OP, bool NF>
 struct ColMinWaves {
-    static constexpr int value = (!NF && ColJoint<N, K>::SEQ && N <= 256 && K <= 3 && OP == OP_CORR) ? 4 : 1;
+    static constexpr int value = ((!NF && ColJoint<N, K>::SEQ && N <= 256 && K <= 3 && OP == OP_CORR) ||
+                                  (NF && N >= 2048 && K == 1)) ? 4 : 1;
 };
 
 // Row (y) index of register e of thread t at the detector-plane step: after
@@ -649,6 +661,35 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     for (int set = 0; set < SETS; ++set) Ls[set] = ColLds<N, CB>(lds_dyn + (ONE_BUF ? 0 : set) * G::LDS_F2, cl);
     (void)L;
     for (int k = 0; k < a.K; ++k) {
+        if constexpr (ONE_BUF) {
+            // one transform at a time (large N): keep A, fold B and C into
+            // the sums as soon as each is transformed
+            float2 A[1][E], V[1][E];
+            auto load_transform = [&](float2 (&v)[1][E], int set) {
+                const float2 *src = a.scr + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + scr_at<N>(0, c);
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[0][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
+                const int t0 = opaque(t);
+                col_transforms<N, E, -1, 1, false>(v, t0, Ls);
+                if constexpr (NF) {
+                    const int t1 = opaque(t);
+                    apply_qy<N, E, 1, 1, false>(v, a.prop, t1);
+                    col_transforms<N, E, +1, 1, false>(v, t1, Ls);
+                }
+            };
+            load_transform(A, 0);
+            load_transform(V, 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                i0[e] += cnorm(A[0][e]);
+                i1[e] += 2.0f * cmulc(A[0][e], V[0][e]).x;
+                i2[e] += cnorm(V[0][e]);
+            }
+            load_transform(V, 2);
+#pragma unroll
+            for (int e = 0; e < E; ++e) i2[e] += 2.0f * cmulc(A[0][e], V[0][e]).x;
+            continue;
+        }
         float2 u[SETS][E];
 #pragma unroll
         for (int set = 0; set < SETS; ++set) {
