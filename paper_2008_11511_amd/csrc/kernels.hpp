@@ -28,9 +28,19 @@
 namespace ptycho {
 
 // ------------------------------------------------------------- geometry ---
+// The size rules as plain functions of N (the host uses them for the
+// workspace layout; the geometry structs below use them for the kernels).
+constexpr int row_e(int n) { return (n >= 128 || n == 16) ? 16 : 8; }
+constexpr int row_rb(int n) { return 256 / (n / row_e(n)); }
+constexpr int col_e(int n) { return (n == 16 || n >= 2048) ? 16 : 8; }
+constexpr int col_cb(int n) {
+    return (n >= 1024) ? 4 : (n >= 256) ? 8 : ((256 / (n / col_e(n))) > 16 ? 256 / (n / col_e(n)) : 16);
+}
+constexpr int scr_tile_w(int n) { return col_cb(n) < n ? col_cb(n) : n; }
+
 // Row transforms: 16 elements per thread from N = 128 up (fewer LDS passes),
 // RB rows per 256-thread block.
-template <int N, int E_ = ((N >= 128 || N == 16) ? 16 : 8)>
+template <int N, int E_ = row_e(N)>
 struct RowGeom {
     static constexpr int E = E_, T = N / E, RB = 256 / T, THREADS = 256;
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? RB * (N + N / 16) : 1;
@@ -50,8 +60,8 @@ struct InvRowGeom {
 // block at 512 threads, so that a thread may hold 256 registers).
 template <int N>
 struct ColGeom {
-    static constexpr int E = (N == 16 || N >= 2048) ? 16 : 8, T = N / E;
-    static constexpr int CB = (N >= 1024) ? 4 : (N >= 256) ? 8 : ((256 / T) > 16 ? 256 / T : 16);
+    static constexpr int E = col_e(N), T = N / E;
+    static constexpr int CB = col_cb(N);
     static constexpr int THREADS = CB * T;
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * CB : 1;   // one transform buffer
 };
@@ -77,7 +87,7 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 // exit waves the caller stores are always row-major.
 template <int N>
 struct ScrTile {
-    static constexpr int W = ColGeom<N>::CB < N ? ColGeom<N>::CB : N;
+    static constexpr int W = scr_tile_w(N);
     static constexpr int LW = ilog2(W);
     static_assert((1 << LW) == W, "tile width is a power of two");
 };

@@ -72,20 +72,28 @@ static bool supported_n(int n) {
     return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048;
 }
 
+// Kernel dispatch by frame size.  PTYCHO_KERNEL_N_MAX (a build option of
+// the host-only sanitizer test, whose program launches nothing) limits the
+// sizes whose kernels are compiled; the library is built with all of them.
+#ifndef PTYCHO_KERNEL_N_MAX
+#define PTYCHO_KERNEL_N_MAX 2048
+#endif
 template <class F>
 static int with_n(int n, F &&f) {
+    if (n > PTYCHO_KERNEL_N_MAX) return fail(PTYCHO_E_UNSUPPORTED, "frame size not compiled into this build");
     switch (n) {
         case 8: return f(std::integral_constant<int, 8>());
-        case 16: return f(std::integral_constant<int, 16>());
-        case 32: return f(std::integral_constant<int, 32>());
-        case 64: return f(std::integral_constant<int, 64>());
-        case 128: return f(std::integral_constant<int, 128>());
-        case 256: return f(std::integral_constant<int, 256>());
-        case 512: return f(std::integral_constant<int, 512>());
-        case 1024: return f(std::integral_constant<int, 1024>());
-        case 2048: return f(std::integral_constant<int, 2048>());
-        default: return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
+        case 16: if constexpr (16 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 16>()); break;
+        case 32: if constexpr (32 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 32>()); break;
+        case 64: if constexpr (64 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 64>()); break;
+        case 128: if constexpr (128 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 128>()); break;
+        case 256: if constexpr (256 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 256>()); break;
+        case 512: if constexpr (512 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 512>()); break;
+        case 1024: if constexpr (1024 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 1024>()); break;
+        case 2048: if constexpr (2048 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 2048>()); break;
+        default: break;
     }
+    return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
 }
 template <class F>
 static int with_k(int k, F &&f) {
@@ -98,12 +106,6 @@ static int with_k(int k, F &&f) {
     }
 }
 
-static int col_cb(int n) {
-    return with_n(n, [](auto nn) { return ColGeom<decltype(nn)::value>::CB; });
-}
-static int row_rb(int n) {
-    return with_n(n, [](auto nn) { return RowGeom<decltype(nn)::value>::RB; });
-}
 
 static constexpr size_t ALIGN = 256;
 static size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -743,7 +745,7 @@ static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
 static int psi_tile_log2(const ptycho_plan_s *p, const float2 *psi) {
     const int n = p->d.n;
     if (psi != p->scr) return ilog2(n);
-    return with_n(n, [&](auto nn) { return ScrTile<decltype(nn)::value>::LW; });
+    return ilog2(scr_tile_w(n));
 }
 
 // Object sums of one stack, added to the running sums, from the stack's
