@@ -45,13 +45,14 @@ struct RowGeom {
     static constexpr int E = E_, T = N / E, RB = 256 / T, THREADS = 256;
     static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? RB * (N + N / 16) : 1;
 };
-// The inverse row pass runs one wavefront per probe mode over the same
-// RQ rows, so that the modes of a pixel meet in one block.
-// (Rows longer than 64 x 16 elements use N/64 elements per thread, so that a
-// row still fits one wavefront.)
+// The inverse row pass runs whole wavefronts per probe mode over the same RQ
+// rows (one wavefront while a row has at most 64 threads, else T threads),
+// so that the modes of a pixel meet in one block.
 template <int N>
 struct InvRowGeom {
-    static constexpr int E = (N / RowGeom<N>::E > 64) ? N / 64 : RowGeom<N>::E, T = N / E, RQ = 64 / T;
+    static constexpr int E = RowGeom<N>::E, T = N / E;
+    static constexpr int TPM = T > 64 ? T : 64;     // threads per mode
+    static constexpr int RQ = TPM / T;
     static constexpr int ROW_F2 = N + N / 16;        // one RowLds row
 };
 // Column transforms keep all K modes in registers at once, so they use 8
@@ -309,7 +310,8 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
 enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2, OUT_NONE = 3 };
 
 // Inverse row FFT of the stack scratch and the real-space epilogue.  A block
-// has one wavefront per probe mode, all on the same RQ rows.  Outputs:
+// has TPM threads (whole wavefronts) per probe mode, all on the same RQ rows.
+// Outputs:
 // OUT_SCR the exit waves back into the scratch, OUT_STORE into psi_out
 // [J][K][N][N], OUT_DM Phi + u into psi_out, OUT_NONE nothing.  With WQ the
 // block also writes q = sum_k conj(P_k) Psi_k (the modes summed through LDS),
@@ -317,11 +319,11 @@ enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2, OUT_NONE = 3 };
 // gather reads one plane per frame instead of K exit waves and K probe
 // values.
 template <int N, int K, int MODE, bool WQ, bool NF>
-__global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
+__global__ __launch_bounds__(InvRowGeom<N>::TPM * K) void k_rows_inv(StackArgs a) {
     using G = InvRowGeom<N>;
     constexpr int E = G::E, T = G::T, RQ = G::RQ;
     __shared__ float2 lds[K * RQ * G::ROW_F2];
-    const int k = threadIdx.x / 64, lane = threadIdx.x % 64, rr = lane / T, t = lane % T;
+    const int k = threadIdx.x / G::TPM, lane = threadIdx.x % G::TPM, rr = lane / T, t = lane % T;
     const int g = xcd_block(blockIdx.x, gridDim.x) * RQ + rr;
     const bool active = g < a.S * N;
     const int gg = active ? g : a.S * N - 1;
@@ -367,7 +369,8 @@ __global__ __launch_bounds__(64 * K) void k_rows_inv(StackArgs a) {
 #pragma unroll
         for (int e = 0; e < E; ++e) L.st(out_index<N, E, +1>(t, e), qk[e]);
         __syncthreads();
-        // wave k sums and writes the pixels of its elements e = k, k + K, ...
+        // the threads of mode k sum and write the pixels of their elements
+        // e = k, k + K, ...
         if (active) {
             float2 *qrow = a.qbuf + ((size_t)s * N + y) * N;
 #pragma unroll

@@ -835,8 +835,9 @@ static int zero_sums(ptycho_plan_s *p, unsigned acc) {
 template <int N, int K, int MODE, bool NF>
 static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
     const dim3 grid((unsigned)(((long)a.S * N + InvRowGeom<N>::RQ - 1) / InvRowGeom<N>::RQ));
-    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true, NF>), grid, dim3(64 * K), 0, s, a);
-    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false, NF>), grid, dim3(64 * K), 0, s, a);
+    const dim3 block(InvRowGeom<N>::TPM * K);
+    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true, NF>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false, NF>), grid, block, 0, s, a);
 }
 
 // One pass over all stacks: forward rows, column op, inverse rows and the
