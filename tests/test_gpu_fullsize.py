@@ -9,6 +9,8 @@ times (automatic stack size).
   which depend only on their own data, are compared one by one, and (b) the
   truth is a fixed point of an AP cycle on noise-free data (a property that
   holds at any size).
+* Near field, 17 frames 2048x2048, one probe: one whole DM cycle and the ML
+  gradient against the oracle.
 """
 import sys
 
@@ -125,3 +127,31 @@ def test_apdm512_sampled_frames_and_fixed_point(dev):
     _, _, ref = oracle.dm_cycle(o0, p0, psi0, offs[sample], ref_i, mask, update=0)
     for i in range(len(sample)):
         assert rel_l2(got[i], ref[i]) < 1e-4, sample[i]
+
+
+def test_nf2048_full_dm_cycle_and_gradient(dev):
+    """Near field, 17 frames 2048x2048, one probe, object 2368x2368: one whole
+    DM cycle and the ML gradient against the oracle (every output)."""
+    from paper_2008_11511_amd import Plan
+    wl = synth.workload("nf2048")
+    pb = make_problem(wl, start="ml")
+    say("full size near field: 17 frames 2048x2048, 1 mode")
+    plan = Plan(pb.offsets, torch.from_numpy(pb.iobs).to(dev), None, 1, wl.obj_shape, near_field=wl.fresnel)
+    o = torch.from_numpy(pb.obj0.astype(np.complex64)).to(dev)
+    p = torch.from_numpy(pb.probe0.astype(np.complex64)).to(dev)
+    g_o, g_p, llk = plan.ml_grad(o, p)
+    gg_o, gg_p, gl = host(g_o), host(g_p), host(llk)[0]
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 1, 3)
+    g_psi, d_o, d_p = host(psi), host(o), host(p)
+    del psi, plan
+    ro, rp, rl = oracle.ml_grad(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, nf=pb.nf)
+    assert rel_l2(gg_o, ro) < 1e-4
+    assert rel_l2(gg_p, rp) < 1e-4
+    assert abs(gl - rl) < 1e-4 * abs(rl)
+    del ro, rp
+    psi0 = oracle.psi_init(pb.obj0, pb.probe0, pb.offsets)
+    ro, rp, rpsi = oracle.dm_cycle(pb.obj0, pb.probe0, psi0, pb.offsets, pb.iobs, pb.mask, nf=pb.nf)
+    assert rel_l2(g_psi, rpsi) < 1e-4
+    assert rel_l2(d_o, ro) < 1e-4
+    assert rel_l2(d_p, rp) < 1e-4

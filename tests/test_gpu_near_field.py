@@ -245,3 +245,41 @@ def test_near_field_arguments_are_checked(dev):
         assert rc == -1 and b"Fresnel" in lib().ptycho_last_error()
     finally:
         lib().ptycho_plan_destroy(h)
+
+
+def test_near_field_background_matches_oracle(dev):
+    """An incoherent background in natural pixel order, in every operator and
+    in the AP refinement, near field."""
+    from paper_2008_11511_amd import Plan, UPDATE_BACKGROUND
+    side = 64 + 32 + 32
+    wl = small("nf1024", n=64, k=2, j=12, obj=(side, side), step=32.0, mask_frac=0.03, photons=1e4 * 64 * 64,
+               fresnel=synth.fresnel_parameter(64, 0.02))
+    pb = make_problem(wl, start="ml", bg_level=500.0)
+    say("near field background n=64 k=2")
+    iobs = to_dev(pb.iobs, dev, torch.float32)
+    mask = to_dev(pb.mask, dev, torch.uint8)
+    plan = Plan(pb.offsets, iobs, mask, 2, wl.obj_shape, near_field=pb.nf, background_update=True)
+    bg = to_dev(pb.bg0, dev, torch.float32)
+    plan.set_background(bg)
+    o, p = state(pb, dev)
+    ic = host(plan.icalc(o, p))
+    assert rel_l2(ic, oracle.simulate_intensity(pb.obj0, pb.probe0, pb.offsets, bg=pb.bg0, nf=pb.nf)) < 1e-5
+    for model in oracle.LLK_MODELS:
+        llk = host(plan.llk(o, p, model=model))
+        ref, _ = oracle.llk(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, model=model, bg=pb.bg0, nf=pb.nf)
+        assert abs(llk[0] - ref) <= 1e-4 * abs(ref), model
+    go, gp, _ = plan.ml_grad(o, p)
+    ro, rp, _ = oracle.ml_grad(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, bg=pb.bg0, nf=pb.nf)
+    assert rel_l2(host(go), ro) < 1e-4 and rel_l2(host(gp), rp) < 1e-4
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 1, UPD)
+    psi0 = oracle.psi_init(pb.obj0, pb.probe0, pb.offsets)
+    ro, rp, rpsi = oracle.dm_cycle(pb.obj0, pb.probe0, psi0, pb.offsets, pb.iobs, pb.mask, bg=pb.bg0, nf=pb.nf)
+    assert rel_l2(host(o), ro) < 1e-4 and rel_l2(host(p), rp) < 1e-4 and rel_l2(host(psi), rpsi) < 1e-4
+    say("near field AP background refinement n=64 k=2")
+    o, p = state(pb, dev)
+    plan.ap_cycle(o, p, 1, UPD | UPDATE_BACKGROUND)
+    ro, rp, rb = oracle.ap_cycle(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, UPD | oracle.UPDATE_BACKGROUND,
+                                 bg=pb.bg0, nf=pb.nf)
+    assert rel_l2(host(bg), rb) < 1e-4
+    assert rel_l2(host(o), ro) < 1e-4 and rel_l2(host(p), rp) < 1e-4
