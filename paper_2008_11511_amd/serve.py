@@ -40,6 +40,14 @@ class Scan:
     n_modes: int
     n_frames: int
     obj_shape: tuple
+    near_field: object = None        # Fresnel parameter(s) of a near-field scan, None = far field
+
+
+def near_field_of(wl):
+    """The near-field Fresnel parameter(s) of a request's scan, or None."""
+    if isinstance(wl, Scan):
+        return wl.near_field
+    return wl.fresnel if getattr(wl, "geometry", "far") == "near" else None
 
 
 @dataclasses.dataclass
@@ -318,7 +326,9 @@ class GpuExecutor:
         wl = req.wl
         n2 = wl.n * wl.n
         no = wl.obj_shape[0] * wl.obj_shape[1]
-        d = Desc(wl.n, wl.n_modes, wl.n_frames, wl.obj_shape[0], wl.obj_shape[1], 0, 1e-2, 1e-2, 1e-20, 0)
+        from ._lib import FLAG_NEAR_FIELD
+        flags = FLAG_NEAR_FIELD if near_field_of(wl) is not None else 0
+        d = Desc(wl.n, wl.n_modes, wl.n_frames, wl.obj_shape[0], wl.obj_shape[1], 0, 1e-2, 1e-2, 1e-20, flags)
         ws = ctypes.c_size_t()
         check(lib().ptycho_workspace_bytes(ctypes.byref(d), ctypes.byref(ws)))
         synthetic = req.data is None
@@ -455,7 +465,8 @@ class GpuExecutor:
                 mark("upload_truth")
                 # data: the forward model written into the data buffer, then the
                 # Poisson draw (the plan reads the buffer only from the first cycle on)
-                j.plan = Plan(h["offs"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws)
+                j.plan = Plan(h["offs"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws,
+                              near_field=near_field_of(wl))
                 mark("plan")
                 j.plan.icalc(o_t, p_t, out=j.iobs)
                 mark("icalc")
@@ -468,7 +479,8 @@ class GpuExecutor:
                     j.stream.wait_event(h["ready"])
                 upload(j.iobs, h["iobs"])
                 mark("upload_data")
-                j.plan = Plan(h["offsets"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws)
+                j.plan = Plan(h["offsets"], j.iobs, j.mask, k, wl.obj_shape, workspace=ws,
+                              near_field=near_field_of(wl))
                 mark("plan")
             j.obj = carve(sizes["obj"], torch.complex64, wl.obj_shape)
             j.probe = carve(sizes["probe"], torch.complex64, (k, n, n))
@@ -586,9 +598,11 @@ class ReconstructionService:
     Inputs (numpy arrays or torch tensors, host or device): iobs float32
     [J][N][N] in FFT order, offsets int32 [J][2] window corners, obj0
     complex64 [Ny][Nx] and probe0 complex64 [K][N][N] starting guesses, mask
-    uint8 [N][N] (1 = bad pixel) or None.  The arrays must not change until
-    the future is done.  A request whose offsets leave the object, or that
-    needs more memory than the budget, is refused in `submit`.
+    uint8 [N][N] (1 = bad pixel) or None.  near_field: the Fresnel
+    parameter f or (f_y, f_x) of a near-field scan (iobs and mask then in
+    natural pixel order), None for the far field.  The arrays must not change
+    until the future is done.  A request whose offsets leave the object, or
+    that needs more memory than the budget, is refused in `submit`.
     """
 
     def __init__(self, device="cuda:0", hbm_budget: Optional[int] = None, max_active: int = 8,
@@ -618,7 +632,7 @@ class ReconstructionService:
         self._thread.start()
         self._started.wait()
 
-    def submit(self, iobs, offsets, obj0, probe0, mask=None, schedule=SCHEDULE):
+    def submit(self, iobs, offsets, obj0, probe0, mask=None, schedule=SCHEDULE, near_field=None):
         import ctypes
         from concurrent.futures import Future
         import torch
@@ -640,7 +654,9 @@ class ReconstructionService:
         for kind, cycles in schedule:
             if kind not in ("ap", "dm", "ml") or int(cycles) <= 0:
                 raise ValueError(f"bad schedule entry {(kind, cycles)}")
-        scan = Scan(n, int(probe0.shape[0]), jj, (int(obj0.shape[0]), int(obj0.shape[1])))
+        if near_field is not None and not np.all(np.isfinite(np.asarray(near_field, dtype=np.float64))):
+            raise ValueError("near_field must be finite")
+        scan = Scan(n, int(probe0.shape[0]), jj, (int(obj0.shape[0]), int(obj0.shape[1])), near_field)
         # sizes and window bounds checked by the library, without GPU work
         d = Desc(n, scan.n_modes, jj, scan.obj_shape[0], scan.obj_shape[1], 0, 1e-2, 1e-2, 1e-20, 0)
         tb = ctypes.c_size_t()
