@@ -1,12 +1,16 @@
 #!/usr/bin/env python3
-"""Benchmark of the far-field ptychography hot path on one MI355X.
+"""Benchmark of the ptychography hot path on one MI355X.
 
 A step is one difference-map cycle (views x probe, far-field FFT, modulus
 projection with the gap mask, inverse FFT, DM combination, object update,
 probe update) over all 1000 frames of the DM workload: 256x256 frames, 3
 probe modes, object 1024x1024, 1e8 photons per frame, 2% gap mask.  The
-throughput is frames*cycles/s; a second leg times conjugate-gradient ML
-cycles (gradient + line search + step) on the ML workload (500 frames).
+throughput is frames*cycles/s.  Further legs (reported beside the headline,
+each skippable): conjugate-gradient ML cycles (gradient + line search +
+step) on the ML workload (500 frames); AP and DM cycles on 4000 frames of
+512x512 with 4 modes; DM and ML cycles in the near-field geometry on 17
+frames of 2048x2048 with one probe; the served mixed workload; the FP64
+oracle on the host.
 
 Inputs are synthetic and built on the GPU: the seeded truth, probe modes,
 spiral positions and mask come from `synth`; the integer offsets and the
