@@ -511,7 +511,9 @@ struct ColSeqBufs {
 
 // Waves per SIMD a column kernel is compiled for: the DM form with up to 3
 // modes fits 128 registers without spilling, which gives 4 waves instead of
-// 3 (measured faster); the others keep the compiler's choice.
+// 3 (measured faster); the near-field pass at 2048 points with one mode gets
+// 4 waves too, so that two of its 512-thread blocks share a CU (a 32-byte
+// spill; measured faster); the others keep the compiler's choice.
 template <int N, int K, int OP, bool NF>
 struct ColMinWaves {
     static constexpr int value = ((!NF && ColJoint<N, K>::SEQ && N <= 256 && K <= 3 && OP == OP_CORR) ||
@@ -660,7 +662,6 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     const int gg = active ? g : a.S * N - 1;
     const int s = gg / N, c = gg % N;
     const int j = a.order[a.s0 + s];
-    ColLds<N, CB> L(lds_dyn, cl);
     constexpr float nrm = NF ? 1.0f : 1.0f / ((float)N * (float)N);
     constexpr int SETS = ColSeqBufs<N, OP>::SETS;
     constexpr bool ONE_BUF = ColSeqBufs<N, OP>::value == 1 && SETS > 1;
@@ -672,7 +673,6 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     ColLds<N, CB> Ls[SETS];
 #pragma unroll
     for (int set = 0; set < SETS; ++set) Ls[set] = ColLds<N, CB>(lds_dyn + (ONE_BUF ? 0 : set) * G::LDS_F2, cl);
-    (void)L;
     for (int k = 0; k < a.K; ++k) {
         if constexpr (ONE_BUF) {
             // one transform at a time (large N): keep A, fold B and C into
