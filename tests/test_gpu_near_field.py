@@ -283,3 +283,42 @@ def test_near_field_background_matches_oracle(dev):
                                  bg=pb.bg0, nf=pb.nf)
     assert rel_l2(host(bg), rb) < 1e-4
     assert rel_l2(host(o), ro) < 1e-4 and rel_l2(host(p), rp) < 1e-4
+
+
+def test_near_field_position_refinement_follows_oracle(dev):
+    """AP cycles with position updates in the near field: the rebuilt plans
+    keep the geometry, and positions follow the oracle."""
+    from paper_2008_11511_amd import Plan
+    from paper_2008_11511_amd.plan import refine_positions
+    n, side = 64, 64 + 64 + 32
+    f = synth.fresnel_parameter(n, 0.02)
+    wl = small("nf1024", n=n, k=1, j=20, obj=(side, side), step=64.0, mask_frac=0.0, photons=1e4 * n * n,
+               fresnel=f)
+    pb = make_problem(wl, start="truth")
+    pos_true = synth.random_positions(wl.n_frames, wl.step, wl.seed)
+    rng = np.random.default_rng(1)
+    err = np.zeros_like(pos_true)
+    sel = rng.random(len(pos_true)) < 0.5
+    err[sel] = rng.choice([-0.4, 0.4], size=(sel.sum(), 2))
+    pos0 = pos_true + err
+    say("near field position refinement: 2 AP cycles with position updates")
+    pos, o, p = pos0.copy(), pb.obj0, pb.probe0
+    for _ in range(2):
+        offs = oracle.offsets_from_positions(pos, n, wl.obj_shape)
+        psi = oracle.fourier_project(oracle.exit_waves(o, p, offs), pb.iobs, None, nf=f)
+        o, p = oracle.overlap_update(o, p, psi, offs, UPD)
+        sh, e = oracle.position_shifts(o, p, psi, offs)
+        pos = oracle.update_positions(pos, pos0, sh, e)
+    gpos = pos0.copy()
+    plan = Plan(oracle.offsets_from_positions(gpos, n, wl.obj_shape), to_dev(pb.iobs, dev, torch.float32), None, 1,
+                wl.obj_shape, near_field=f)
+    go, gp = state(pb, dev)
+    psi_d = torch.empty((wl.n_frames, 1, n, n), dtype=torch.complex64, device=dev)
+    start_off = plan.offsets.copy()
+    for _ in range(2):
+        plan.ap_cycle(go, gp, 1, UPD, psi=psi_d)
+        plan, gpos, goffs = refine_positions(plan, go, gp, psi_d, gpos, pos0)
+        assert plan.near_field == (f, f)
+    assert not np.array_equal(start_off, goffs)
+    assert np.abs(gpos - pos).max() < 1e-3
+    np.testing.assert_array_equal(goffs, oracle.offsets_from_positions(pos, n, wl.obj_shape))
