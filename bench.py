@@ -376,8 +376,13 @@ def main():
                     k4[name] = {"avg_us": round(1e3 * ms / n, 2), "launches": n}
                     if name in algo4:
                         k4[name]["alg_GBs"] = round(algo4[name] * n_ndm / n / (ms / n * 1e-3) / 1e9, 1)
+            cyc4 = sum(algo4.values())
             near.update({"dm_cycles": n_ndm, "dm_ms_per_cycle": round(dt4 / n_ndm * 1e3, 3),
-                         "dm_frames_cycles_per_s": round(wl4.n_frames * n_ndm / dt4, 1), "dm_kernels": k4})
+                         "dm_frames_cycles_per_s": round(wl4.n_frames * n_ndm / dt4, 1), "dm_kernels": k4,
+                         "cycle_alg_bytes": cyc4, "cycle_alg_GBs": round(cyc4 * n_ndm / dt4 / 1e9, 1),
+                         "cycle_hbm_frac": round(cyc4 * n_ndm / dt4 / 1e9 / HBM_PEAK_GBS, 4),
+                         "note": "the column pass runs four 2048-point transforms per column and is bound by "
+                                 "the vector ALU, not HBM"})
             del psi4
         if n_nml:
             o4, p4 = build_workload(wl4, torch, dev, "ml")[3:5]
