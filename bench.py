@@ -214,6 +214,16 @@ def main():
         plan.dm_cycle(o, p, psi, 50, 3)
         plan.llk(o, p).cpu()
         extra["dm_ms_per_cycle_with_llk_fetch_every_50"] = round((time.perf_counter() - t0) / 50 * 1e3, 4)
+        # five repeats of 10 DM cycles each (the spread of the headline figure)
+        reps = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.dm_cycle(o, p, psi, 10, 3)
+            torch.cuda.synchronize()
+            reps.append(round((time.perf_counter() - t0) / 10 * 1e3, 4))
+        extra["dm_ms_per_cycle_5_repeats"] = reps
+        extra["dm_ms_per_cycle_median_of_5"] = float(np.median(reps))
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         llk_ms = {}
         for model in ("poisson", "gaussian", "euclidean"):
