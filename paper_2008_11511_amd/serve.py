@@ -294,11 +294,17 @@ class GpuExecutor:
         import synth
         from .plan import offsets_from_positions
         wl = req.wl
+        near = near_field_of(wl) is not None
         obj = synth.object_truth(wl.obj_shape, wl.seed)
-        probe = synth.probe_modes(wl.n, wl.n_modes, wl.seed)
-        offs = offsets_from_positions(synth.spiral_positions(wl.n_frames, wl.step), wl.n, wl.obj_shape)
+        if near:
+            probe = synth.near_field_probe(wl.n, wl.n_modes, wl.seed)
+            pos = synth.random_positions(wl.n_frames, wl.step, wl.seed)
+        else:
+            probe = synth.probe_modes(wl.n, wl.n_modes, wl.seed)
+            pos = synth.spiral_positions(wl.n_frames, wl.step)
+        offs = offsets_from_positions(pos, wl.n, wl.obj_shape)
         probe = probe * synth.probe_photon_scale(obj, probe, offs, wl.photons)
-        mask = synth.gap_mask(wl.n, wl.mask_frac, wl.seed)
+        mask = synth.gap_mask(wl.n, wl.mask_frac, wl.seed, fft_order=not near)
         self.host[req.rid] = dict(
             obj=np.ascontiguousarray(obj.astype(np.complex64)),
             probe=np.ascontiguousarray(probe.astype(np.complex64)),

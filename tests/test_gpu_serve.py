@@ -186,3 +186,43 @@ def test_service_serves_near_field_and_far_field_scans_together():
     with ReconstructionService() as svc2:
         with pytest.raises(ValueError, match="finite"):
             svc2.submit(schedule=SCHED, near_field=float("nan"), **near)
+
+
+def test_synthetic_near_field_request_in_a_trace():
+    """A synthetic near-field request (data drawn on the device from the
+    near-field forward model) beside far-field ones: the same result in the
+    continuous and the sequential schedule."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import dataclasses
+    import synth
+    from paper_2008_11511_amd import lib
+    from paper_2008_11511_amd.serve import GpuExecutor, Request, Scheduler, make_trace
+    lib()
+    nf = dataclasses.replace(synth.workload("nf1024"), name="nf64", n=64, n_frames=20, obj_shape=(160, 160),
+                             step=64.0, photons=1e4 * 64 * 64, fresnel=synth.fresnel_parameter(64, 0.02))
+
+    def run(sequential):
+        reqs = make_trace(3, 40.0, 5, sizes=(64,), min_frames=60, max_frames=100, schedule=SCHED, min_side=256)
+        reqs.append(Request(3, 0.02, nf, SCHED))
+        ex = GpuExecutor("cuda:0")
+        for r in reqs:
+            ex.prepare(r)
+        free, _ = torch.cuda.mem_get_info(torch.device("cuda:0"))
+        budget = int(0.5 * free)
+        ex.attach_arena(int(budget * 0.85))
+        Scheduler(ex, budget, max_active=6, sequential=sequential).run(reqs)
+        ex.close()
+        return reqs
+
+    say("serve: synthetic near-field request, continuous")
+    con = run(False)
+    say("serve: synthetic near-field request, sequential")
+    seq = run(True)
+    for a, b in zip(con, seq):
+        assert a.error is None and b.error is None
+        assert np.array_equal(a.result["obj"], b.result["obj"])
+        assert a.result["llk"] == b.result["llk"] and np.isfinite(a.result["llk"])
+    # the near-field request fits its own data: the final LLK per pixel is a
+    # few units (Poisson noise), not the far-field model's mismatch
+    assert con[3].result["llk"] < 50.0
