@@ -284,15 +284,18 @@ int ptycho_icalc(ptycho_plan_t plan, const float *obj_dev,
 int ptycho_fft2(int32_t n, int32_t count, float *data_dev, int32_t direction,
                 void *stream);
 
-/* Per-kernel timing for diagnostics and benchmarks: with enable != 0 the
- * plan records a HIP event pair on its stream around every later launch of
- * each kernel class (0 forward row FFTs, 1 column FFT + Fourier-space step,
- * 2 inverse row FFTs, 3 object gather, 4 per-stack probe gather, 5 all-frame
- * probe gather, 6 normalisation, 7 other); enable = 0 stops recording.
+/* Per-kernel timing for diagnostics and benchmarks: `classes` is a bit mask
+ * of kernel classes (bit c for class c: 0 forward row FFTs, 1 column FFT +
+ * Fourier-space step, 2 inverse row FFTs, 3 object gather, 4 per-stack probe
+ * gather, 5 all-frame probe gather, 6 normalisation, 7 other; 255 = all).
+ * With classes != 0 the plan records a HIP event pair on its stream around
+ * every later launch of the selected classes (each pair adds a few
+ * microseconds to the stream, so time a whole run with few classes);
+ * 0 stops recording.  PTYCHO_E_INVALID for bits beyond class 7.
  * ptycho_plan_timing_read waits for the last recorded event and returns the
  * summed milliseconds and the launch count of one class since timing was
  * last enabled. */
-int ptycho_plan_timing(ptycho_plan_t plan, int32_t enable);
+int ptycho_plan_timing(ptycho_plan_t plan, int32_t classes);
 int ptycho_plan_timing_read(ptycho_plan_t plan, int32_t cls, double *ms_total,
                             int64_t *launches);
 

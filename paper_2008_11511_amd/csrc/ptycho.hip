@@ -200,6 +200,7 @@ enum { TC_ROWS_FWD = 0, TC_COLS = 1, TC_ROWS_INV = 2, TC_GATHER_OBJ = 3, TC_GATH
 
 struct TimingLog {
     bool on = false;
+    unsigned mask = 0;      // classes recorded (bit c: class c)
     std::vector<hipEvent_t> pool;
     std::vector<int> cls;   // class of event pair i (events 2i, 2i+1)
     size_t used = 0;        // pairs recorded
@@ -248,9 +249,10 @@ struct Timed {
     ptycho_plan_s *p;
     int c;
     size_t pair;
+    bool rec = false;
     Timed(ptycho_plan_s *p_, int c_) : p(p_), c(c_), pair(0) {
         TimingLog &t = p->timing;
-        if (!t.on) return;
+        if (!t.on || !((t.mask >> c) & 1u)) return;
         pair = t.used++;
         while (t.pool.size() < 2 * t.used) {
             hipEvent_t e;
@@ -260,10 +262,11 @@ struct Timed {
         if (t.cls.size() < t.used) t.cls.resize(t.used);
         t.cls[pair] = c;
         (void)hipEventRecord(t.pool[2 * pair], p->stream);
+        rec = true;
     }
     ~Timed() {
         TimingLog &t = p->timing;
-        if (t.on) (void)hipEventRecord(t.pool[2 * pair + 1], p->stream);
+        if (rec && t.on) (void)hipEventRecord(t.pool[2 * pair + 1], p->stream);
     }
 };
 
@@ -649,10 +652,12 @@ extern "C" int ptycho_plan_destroy(ptycho_plan_t p) {
     return PTYCHO_OK;
 }
 
-extern "C" int ptycho_plan_timing(ptycho_plan_t p, int32_t enable) {
+extern "C" int ptycho_plan_timing(ptycho_plan_t p, int32_t classes) {
     if (!p) return fail(PTYCHO_E_INVALID, "null plan");
-    p->timing.on = enable != 0;
-    if (enable) p->timing.used = 0;
+    if (classes < 0 || classes >= (1 << TC_N)) return fail(PTYCHO_E_INVALID, "bad timing class mask");
+    p->timing.on = classes != 0;
+    p->timing.mask = (unsigned)classes;
+    if (classes) p->timing.used = 0;
     return PTYCHO_OK;
 }
 

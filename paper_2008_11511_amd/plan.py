@@ -260,9 +260,13 @@ class Plan:
     TIMING_CLASSES = ("rows_fwd", "cols", "rows_inv", "gather_obj", "gather_probe", "probe_all",
                       "normalize", "other")
 
-    def timing(self, enable: bool):
-        """Start (and reset) or stop per-kernel-class event timing."""
-        check(lib().ptycho_plan_timing(self._h, 1 if enable else 0))
+    def timing(self, enable: bool, classes=None):
+        """Start (and reset) or stop per-kernel-class event timing; `classes`
+        names the timed classes (TIMING_CLASSES), None = all."""
+        mask = 0
+        if enable:
+            mask = 255 if classes is None else sum(1 << self.TIMING_CLASSES.index(c) for c in classes)
+        check(lib().ptycho_plan_timing(self._h, mask))
 
     def timing_read(self):
         """{class: (total ms, launches)} since timing was last enabled."""

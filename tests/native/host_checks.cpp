@@ -75,6 +75,7 @@ int main() {
     EXPECT(ptycho_plan_dry_run(&d, nullptr, &ws) == PTYCHO_E_INVALID);
     EXPECT(ptycho_plan_set_background(nullptr, nullptr) == PTYCHO_E_INVALID);
     EXPECT(ptycho_plan_set_near_field(nullptr, 0.1, 0.1) == PTYCHO_E_INVALID);
+    EXPECT(ptycho_plan_timing(nullptr, 255) == PTYCHO_E_INVALID);
     std::printf("host checks: %d failures\n", failures);
     return failures == 0 ? 0 : 1;
 }

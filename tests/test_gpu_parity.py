@@ -514,3 +514,27 @@ def test_position_refinement_follows_oracle(dev):
     wrong0 = int((start_off != off_true).any(axis=1).sum())
     wrong = int((goffs != off_true).any(axis=1).sum())
     assert wrong < wrong0
+
+
+def test_timing_records_only_the_selected_kernel_classes(dev):
+    from paper_2008_11511_amd import PtychoError
+    from paper_2008_11511_amd._lib import lib
+    wl = small("dm256", n=64, k=2, j=20, obj=(160, 160), step=4.0, mask_frac=0.0)
+    pb = make_problem(wl, start="ml")
+    say("timing class mask")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    psi = plan.psi_init(o, p)
+    plan.timing(True, ("rows_inv",))
+    plan.dm_cycle(o, p, psi, 3, UPD)
+    per = plan.timing_read()
+    assert per["rows_inv"][1] == 3 and per["rows_inv"][0] > 0
+    assert all(n == 0 for name, (_, n) in per.items() if name != "rows_inv")
+    plan.timing(True)
+    plan.dm_cycle(o, p, psi, 2, UPD)
+    per = plan.timing_read()
+    assert per["rows_fwd"][1] == 2 and per["cols"][1] == 2 and per["rows_inv"][1] == 2
+    plan.timing(False)
+    with pytest.raises(PtychoError):
+        from paper_2008_11511_amd._lib import check
+        check(lib().ptycho_plan_timing(plan._h, 256))
