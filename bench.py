@@ -317,14 +317,16 @@ def main():
         hist = torch.zeros(args.ml_steps, dtype=torch.float64, device=dev)
         plan2.ml_cycle(o2, p2, st, 2, 3, reset=True, hist=hist[:2].contiguous())
         torch.cuda.synchronize()
-        plan2.timing(True)
         t0 = time.perf_counter()
         plan2.ml_cycle(o2, p2, st, args.ml_steps, 3, reset=False, hist=hist)
         torch.cuda.synchronize()
         dt2 = time.perf_counter() - t0
+        h = hist.cpu().numpy()
+        # per-class breakdown from a separate run with every class timed
+        plan2.timing(True)
+        plan2.ml_cycle(o2, p2, st, args.ml_steps, 3, reset=False)
         per2 = plan2.timing_read()
         plan2.timing(False)
-        h = hist.cpu().numpy()
         ml = {"workload": "ml256", "frames": wl2.n_frames, "cycles": args.ml_steps,
               "ms_per_cycle": round(dt2 / args.ml_steps * 1e3, 3),
               "frames_cycles_per_s": round(wl2.n_frames * args.ml_steps / dt2, 1),
@@ -345,7 +347,6 @@ def main():
         psi3 = torch.empty((wl3.n_frames, wl3.n_modes, wl3.n, wl3.n), dtype=torch.complex64, device=dev)
         plan3.ap_cycle(o3, p3, 1, 3, psi=psi3)                       # warm-up
         torch.cuda.synchronize()
-        plan3.timing(True)
         t0 = time.perf_counter()
         plan3.ap_cycle(o3, p3, n_ap, 3, psi=psi3)
         torch.cuda.synchronize()
@@ -356,6 +357,10 @@ def main():
         plan3.dm_cycle(o3, p3, psi3, n_dm, 3)
         torch.cuda.synchronize()
         t_dm = time.perf_counter() - t0
+        # per-class breakdown: one AP and one DM cycle with every class timed
+        plan3.timing(True)
+        plan3.ap_cycle(o3, p3, 1, 3, psi=psi3)
+        plan3.dm_cycle(o3, p3, psi3, 1, 3)
         per3 = plan3.timing_read()
         plan3.timing(False)
         algo3 = algorithmic_bytes(wl3, 0, "dm")
@@ -365,7 +370,7 @@ def main():
                 k3[name] = {"avg_us": round(1e3 * ms / n, 2), "launches": n}
                 if name in ("cols", "gather_obj", "probe_all"):
                     # these classes run with the same bytes in AP and DM cycles
-                    bpl = algo3[name] * (n_ap + n_dm) / n
+                    bpl = algo3[name] * 2 / n
                     k3[name]["alg_GBs"] = round(bpl / (ms / n * 1e-3) / 1e9, 1)
         large = {"workload": "apdm512: 4000 frames 512x512, 4 modes, object 4096x4096, 1e9 photons/frame, 3% mask",
                  "ap_cycles": n_ap, "dm_cycles": n_dm,
@@ -391,7 +396,8 @@ def main():
                 "frames": wl4.n_frames, "frame": wl4.n, "modes": wl4.n_modes, "stack": plan4.stack}
         if n_ndm:
             psi4 = plan4.psi_init(o4, p4)
-            dt4, per4 = timed_dm(plan4, o4, p4, psi4, n_ndm, 2, torch)
+            dt4, _ = timed_dm(plan4, o4, p4, psi4, n_ndm, 2, torch, classes=("rows_inv",))
+            _, per4 = timed_dm(plan4, o4, p4, psi4, n_ndm, 0, torch)
             algo4 = algorithmic_bytes(wl4, 0, "dm")
             k4 = {}
             for name, (ms, n) in per4.items():
