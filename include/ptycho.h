@@ -149,7 +149,7 @@ int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
 int ptycho_plan_set_near_field(ptycho_plan_t plan, double fy, double fx);
 
 /* Incoherent background (Section 4: the Ptycho object carries one beside the
- * object and probe estimates): bg_dev float[N][N] in FFT order, shared by
+ * object and probe estimates): bg_dev float[N][N] in the detector layout of iobs, shared by
  * all frames, caller-owned, NULL = none.  Every operator then models the
  * intensity as I = sum_k |FT(O_j P_k)|^2 + bg: the modulus projection (the
  * background is scaled like one more incoherent mode), LLK, icalc, the ML

@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for far-field ptychography (test infrastructure only).
+"""FP64 CPU oracle for far- and near-field ptychography (test infrastructure only).
 
 This package is the slow, plain reference that the GPU library is checked
 against.  Only the tests, the smoke check and the CPU-baseline leg of the

@@ -174,7 +174,7 @@ def calc_intensity(psi_hat: np.ndarray) -> np.ndarray:
 
 def model_intensity(psi_hat: np.ndarray, bg=None) -> np.ndarray:
     """Model intensity: the modes' sum plus the incoherent background bg
-    [N][N] (shared by all frames, FFT order), which the Ptycho object of
+    [N][N] (shared by all frames, in the detector layout of iobs), which the Ptycho object of
     Section 4 carries beside object and probe; bg None means zero."""
     inten = calc_intensity(psi_hat)
     return inten if bg is None else inten + np.asarray(bg, dtype=np.float64)[None]

@@ -1,4 +1,4 @@
-"""MI355X (gfx950) far-field ptychography hot path.
+"""MI355X (gfx950) ptychography hot path (far and near field).
 
 The computation lives in the HIP library `libptycho.so` (C ABI in
 include/ptycho.h).  This package only marshals torch tensors (device memory

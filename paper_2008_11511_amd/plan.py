@@ -154,7 +154,7 @@ class Plan:
         self.near_field = (fy, fx)
 
     def set_background(self, bg: Optional[torch.Tensor]) -> None:
-        """Incoherent background float32 [N][N] (FFT order) used by every later
+        """Incoherent background float32 [N][N] (the detector layout of iobs) used by every later
         call, or None.  The plan keeps a reference; AP cycles with
         UPDATE_BACKGROUND refine it in place."""
         if bg is not None:

@@ -602,7 +602,7 @@ class ReconstructionService:
             res = fut.result()     # obj, probe, llk, llk_history, timings
 
     Inputs (numpy arrays or torch tensors, host or device): iobs float32
-    [J][N][N] in FFT order, offsets int32 [J][2] window corners, obj0
+    [J][N][N] (FFT order in the far field), offsets int32 [J][2] window corners, obj0
     complex64 [Ny][Nx] and probe0 complex64 [K][N][N] starting guesses, mask
     uint8 [N][N] (1 = bad pixel) or None.  near_field: the Fresnel
     parameter f or (f_y, f_x) of a near-field scan (iobs and mask then in

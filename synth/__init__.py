@@ -55,7 +55,8 @@ BASE_SEED = 20081151
 
 @dataclasses.dataclass(frozen=True)
 class Workload:
-    """One synthetic far-field ptychography workload (sizes in pixels)."""
+    """One synthetic ptychography workload (sizes in pixels; far field unless
+    geometry is "near")."""
 
     name: str
     n: int                 # frame (= probe window) side, power of two
