@@ -205,3 +205,24 @@ def test_near_field_dm_reduces_the_likelihood():
     for _ in range(15):
         o, p, psi = oracle.dm_cycle(o, p, psi, pb.offsets, pb.iobs, pb.mask, nf=pb.nf)
     assert oracle.llk(o, p, pb.offsets, pb.iobs, pb.mask, nf=pb.nf)[0] < 0.2 * l0
+
+
+@pytest.mark.parametrize("n", [4, 6, 8])
+def test_propagation_is_a_circular_convolution_with_the_fresnel_kernel(n):
+    """Brute force on tiny frames: D x equals the circular convolution of x
+    with h = inverse DFT of Q, every sum written out (no FFT)."""
+    fy, fx = 0.37, -0.21
+    rng = np.random.default_rng(n)
+    x = crandn(rng, n, n)
+    us = [u if u < n / 2 else u - n for u in range(n)]
+    q = [[np.exp(-1j * (fy * us[u] ** 2 + fx * us[v] ** 2)) for v in range(n)] for u in range(n)]
+    h = np.zeros((n, n), dtype=np.complex128)
+    for y in range(n):
+        for xx in range(n):
+            h[y, xx] = sum(q[u][v] * np.exp(2j * np.pi * (u * y + v * xx) / n)
+                           for u in range(n) for v in range(n)) / (n * n)
+    want = np.zeros((n, n), dtype=np.complex128)
+    for y in range(n):
+        for xx in range(n):
+            want[y, xx] = sum(h[(y - a) % n, (xx - b) % n] * x[a, b] for a in range(n) for b in range(n))
+    np.testing.assert_allclose(oracle.propagate_near_field(x, (fy, fx)), want, atol=1e-12)
