@@ -248,3 +248,17 @@ def test_loop_reports_each_request_once_and_isolates_a_failing_start():
     assert [r.rid for r in bad] == [3] and isinstance(bad[0].error, ValueError)
     assert all(r.result is not None for r in done if r.rid != 3)
     assert not ex.left                                    # every started request was released
+
+
+def test_near_field_requests_reserve_the_transfer_function_table():
+    """The footprint of a near-field scan includes the plan's 2N-entry
+    transfer-function table (workspace sizes come from the library, no GPU)."""
+    from paper_2008_11511_amd.serve import GpuExecutor, Request, Scan, near_field_of
+    import synth
+    far = Request(0, 0.0, Scan(64, 2, 50, (160, 160)), (("dm", 2),), data={})
+    near = Request(1, 0.0, Scan(64, 2, 50, (160, 160), near_field=0.05), (("dm", 2),), data={})
+    ws = {r.rid: dict(GpuExecutor._layout(r))["ws"] for r in (far, near)}
+    assert ws[1] >= ws[0] + 2 * 64 * 8
+    assert near_field_of(near.wl) == 0.05 and near_field_of(far.wl) is None
+    assert near_field_of(synth.workload("nf1024")) == synth.workload("nf1024").fresnel
+    assert near_field_of(synth.workload("dm256")) is None
