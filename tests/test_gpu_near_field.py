@@ -322,3 +322,24 @@ def test_near_field_position_refinement_follows_oracle(dev):
     assert not np.array_equal(start_off, goffs)
     assert np.abs(gpos - pos).max() < 1e-3
     np.testing.assert_array_equal(goffs, oracle.offsets_from_positions(pos, n, wl.obj_shape))
+
+
+def test_near_field_autograd_matches_oracle_gradient(dev):
+    """torch.autograd over the near-field adjoint: loss and gradients against
+    the oracle, and a torch optimiser step lowers the likelihood."""
+    import paper_2008_11511_amd as P
+    pb = near(64, 1, 12, mask_frac=0.03, start="ml")
+    say("near field autograd PoissonLLK")
+    plan = make_plan(pb, dev)
+    o, p = state(pb, dev)
+    o.requires_grad_(True)
+    p.requires_grad_(True)
+    loss = P.poisson_llk(o, p, plan)
+    loss.backward()
+    ro, rp, rl = oracle.ml_grad(pb.obj0, pb.probe0, pb.offsets, pb.iobs, pb.mask, nf=pb.nf)
+    assert abs(float(loss.detach().cpu()) - rl) < 1e-4 * abs(rl)
+    assert rel_l2(host(o.grad), ro) < 1e-4 and rel_l2(host(p.grad), rp) < 1e-4
+    # a small gradient step on the object lowers the LLK
+    with torch.no_grad():
+        o2 = o - 1e-3 * float(np.abs(pb.obj0).max()) / float(o.grad.abs().max()) * o.grad
+    assert float(P.poisson_llk(o2, p.detach(), plan).cpu()) < float(loss.detach().cpu())
