@@ -226,3 +226,19 @@ def test_propagation_is_a_circular_convolution_with_the_fresnel_kernel(n):
         for xx in range(n):
             want[y, xx] = sum(h[(y - a) % n, (xx - b) % n] * x[a, b] for a in range(n) for b in range(n))
     np.testing.assert_allclose(oracle.propagate_near_field(x, (fy, fx)), want, atol=1e-12)
+
+
+def test_golden_scalar_dm_cases_hold_in_the_near_field():
+    """With 1x1 frames the only frequency is 0, where the transfer function
+    is 1: the hand-worked DM cases of the far field hold unchanged."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "scalar_cases.json")) as f:
+        cases = json.load(f)
+    for c in cases["dm"]:
+        o = np.array([[complex(*c["obj"])]])
+        p = np.array([[[complex(*c["probe"])]]])
+        psi = np.array([[[[complex(*c["psi"])]]]])
+        offs = np.zeros((1, 2), np.int32)
+        _, _, psi1 = oracle.dm_cycle(o, p, psi, offs, np.array([[[c["iobs"]]]]), None, nf=(0.7, -1.3))
+        assert abs(psi1[0, 0, 0, 0] - complex(*c["psi_new"])) < 1e-12, c
