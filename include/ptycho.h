@@ -53,6 +53,14 @@
 #include <stddef.h>
 #include <stdint.h>
 
+/* Every entry point is exported with default visibility; the library's
+ * internal symbols are hidden. */
+#if defined(__GNUC__) || defined(__clang__)
+#define PTYCHO_API __attribute__((visibility("default")))
+#else
+#define PTYCHO_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -104,32 +112,42 @@ typedef struct ptycho_plan_s *ptycho_plan_t;
  * PTYCHO_E_BOUNDS, writing nothing, if any window leaves the object.
  * (Section 4: PtychoData holds the probe translation positions; the exit
  * wave of the ptychography-operator table shifts the probe by r_j.) */
-int ptycho_offsets_from_positions(const double *pos_yx_host, int32_t n_frames,
+PTYCHO_API int ptycho_offsets_from_positions(const double *pos_yx_host, int32_t n_frames,
                                   int32_t n, int32_t obj_ny, int32_t obj_nx,
                                   int32_t *offsets_out_host);
 
-/* Device workspace needed by a plan for `desc`, in bytes (host only). */
-int ptycho_workspace_bytes(const ptycho_desc_t *desc, size_t *bytes_out);
+/* Device workspace needed by a plan for `desc`, in bytes (host only).
+ * Section 4: operators compute a stack of frames of the Psi array at once
+ * and loop over the stacks to cover every frame (the paper's stacks hold 16
+ * to 128 frames, larger ones being faster); the workspace holds that stack
+ * (desc->stack frames, 0 = the largest whose scratch fits about 2 GiB), the
+ * plan's index tables, the overlap-update sums and the reduction partials.
+ * PTYCHO_E_INVALID / PTYCHO_E_UNSUPPORTED for a bad descriptor. */
+PTYCHO_API int ptycho_workspace_bytes(const ptycho_desc_t *desc, size_t *bytes_out);
 
-/* Create a plan.  offsets_host: int32[J][2] window offsets (checked against
- * the object bounds).  iobs_dev / mask_dev: observed data and bad-pixel mask
- * (mask may be NULL); the plan keeps these pointers, which must stay valid
- * for the plan's life.  workspace_dev: at least ptycho_workspace_bytes()
+/* Create a plan: the scan's data object of Section 4 (PtychoData: observed
+ * intensity, probe positions, bad-pixel mask, near or far field) with the
+ * stack of exit waves (the Psi array of the Ptycho object) placed in the
+ * caller's workspace.  offsets_host: int32[J][2] window offsets (checked
+ * against the object bounds, PTYCHO_E_BOUNDS otherwise).  iobs_dev /
+ * mask_dev: observed data and bad-pixel mask (mask may be NULL); the plan
+ * keeps these pointers, which must stay valid for the plan's life.  workspace_dev: at least ptycho_workspace_bytes()
  * bytes, 256-byte aligned, owned by the caller, used exclusively by this
  * plan.  stream: a hipStream_t (NULL = default stream).  The call enqueues
  * the upload of the index tables (the plan keeps their host copies) and the
  * count of unmasked pixels on `stream`, returns the handle in *out, and does
  * not wait for the stream; later calls on the plan's stream see the tables. */
-int ptycho_plan_create(const ptycho_desc_t *desc, const int32_t *offsets_host,
-                       const float *iobs_dev, const uint8_t *mask_dev,
-                       void *workspace_dev, size_t workspace_bytes,
-                       void *stream, ptycho_plan_t *out);
+PTYCHO_API int ptycho_plan(const ptycho_desc_t *desc, const int32_t *offsets_host,
+                const float *iobs_dev, const uint8_t *mask_dev,
+                void *workspace_dev, size_t workspace_bytes,
+                void *stream, ptycho_plan_t *out);
 
 /* Build and check a plan's host-side index tables (frame order, object-gather
  * lists) for `desc` and offsets_host without any GPU work; *table_bytes_out
- * receives their size.  Same checks and status codes as ptycho_plan_create
- * (without the device pointers); for capacity planning and tests. */
-int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
+ * receives their size.  Same checks and status codes as ptycho_plan
+ * (without the device pointers); for capacity planning and tests (the
+ * index tables of the stacks of Section 4 that ptycho_plan builds). */
+PTYCHO_API int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
                         size_t *table_bytes_out);
 
 /* Near-field geometry (Section 4: near and far-field geometries; operator
@@ -146,7 +164,7 @@ int ptycho_plan_dry_run(const ptycho_desc_t *desc, const int32_t *offsets_host,
  * otherwise, and for non-finite parameters).  The table Q/N is computed on
  * the host in double precision and uploaded on the plan's stream without
  * waiting; calls may change it between cycles (e.g. another distance). */
-int ptycho_plan_set_near_field(ptycho_plan_t plan, double fy, double fx);
+PTYCHO_API int ptycho_plan_set_near_field(ptycho_plan_t plan, double fy, double fx);
 
 /* Incoherent background (Section 4: the Ptycho object carries one beside the
  * object and probe estimates): bg_dev float[N][N] in the detector layout of iobs, shared by
@@ -157,7 +175,7 @@ int ptycho_plan_set_near_field(ptycho_plan_t plan, double fy, double fx);
  * refines it in place: bg <- bg * (1/J) sum_j s_j^2, s_j^2 = Iobs / I at
  * frame j (1 at bad pixels), from the projection of that cycle (the
  * augmented projections the paper cites for AP background optimisation). */
-int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
+PTYCHO_API int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
 
 /* Position refinement (operator Psi2PosShift, Section 4, after Odstrcil et
  * al. 2018): for every frame j, the shift d of its illumination position
@@ -171,23 +189,27 @@ int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
  * S_yy + S_xx) in pixels, frames in scan order.  The caller moves the
  * positions (the paper's filter leaves frames of low gradient energy in
  * place) and builds a plan from the new offsets. */
-int ptycho_position_shifts(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
+PTYCHO_API int ptycho_position_shifts(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                            const float *psi_dev, double *out_dev);
 
 /* Failure detection: flag_dev (int32[1], device) is set to 1 if any value
  * of the object or probe is NaN or infinite, else 0 (enqueued, so a caller
  * can copy the flag back and read it at its next poll without waiting). */
-int ptycho_check_finite(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
+PTYCHO_API int ptycho_check_finite(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                         int32_t *flag_dev);
 
-/* Change the stream later calls enqueue on (hipStream_t). */
-int ptycho_plan_set_stream(ptycho_plan_t plan, void *stream);
+/* Change the stream later calls enqueue on (hipStream_t); the paper's
+ * asynchronous execution (Section 2) queues every operator on one stream. */
+PTYCHO_API int ptycho_plan_set_stream(ptycho_plan_t plan, void *stream);
 
-/* Frames per launch actually used by the plan. */
-int ptycho_plan_stack(ptycho_plan_t plan, int32_t *stack_out);
+/* Frames per launch actually used by the plan (the stack size of Section 4). */
+PTYCHO_API int ptycho_plan_stack(ptycho_plan_t plan, int32_t *stack_out);
 
-/* Free the host-side plan.  Device buffers are untouched. */
-int ptycho_plan_destroy(ptycho_plan_t plan);
+/* Free the host-side plan (the data object of Section 4 whose device arrays
+ * belong to the caller).  Device buffers, including the workspace, are
+ * untouched; work already enqueued must complete before the caller frees
+ * them.  A null plan is accepted. */
+PTYCHO_API int ptycho_plan_destroy(ptycho_plan_t plan);
 
 /* n_cycles alternating-projection cycles (operator AP): for every frame and
  * mode Psi = IFT * ApplyAmplitude * FT (O_j P_k); then the overlap update
@@ -204,7 +226,7 @@ int ptycho_plan_destroy(ptycho_plan_t plan);
  * (PTYCHO_E_INVALID otherwise) when the probe is updated, since the probe
  * update runs after the object update over all frames; may be NULL for an
  * object-only update.  On return it holds the last cycle's exit waves. */
-int ptycho_ap_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
+PTYCHO_API int ptycho_ap_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
                     float *psi_dev, int32_t n_cycles, uint32_t update);
 
 /* n_cycles difference-map cycles (operator DM, beta = 1) on the persistent
@@ -212,18 +234,20 @@ int ptycho_ap_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
  *   Psi <- Psi + IFT ApplyAmplitude FT (2 Phi - Psi) - Phi,  Phi = O_j P_k
  * followed by the overlap update of obj / probe as in ptycho_ap_cycle
  * (object, then probe from the new object). */
-int ptycho_dm_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
+PTYCHO_API int ptycho_dm_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
                     float *psi_dev, int32_t n_cycles, uint32_t update);
 
-/* psi <- O_j P_k for every frame and mode (DM starting point). */
-int ptycho_psi_init(ptycho_plan_t plan, const float *obj_dev,
+/* psi <- O_j P_k for every frame and mode: operator ObjProbe2Psi of the
+ * ptychography-operator table (the views of Section 4's Psi array), the
+ * DM starting point.  psi_dev: complex[J][K][N][N], caller-owned. */
+PTYCHO_API int ptycho_psi_init(ptycho_plan_t plan, const float *obj_dev,
                     const float *probe_dev, float *psi_dev);
 
 /* Poisson log-likelihood (operator LLK): llk_dev (double[2], device)
  * receives { sum over unmasked pixels of all frames of
  * I - Iobs + Iobs ln(Iobs / I), number of those pixels }, with
  * I = sum_k |FT(O_j P_k)|^2 floored at icalc_floor, 0 ln 0 = 0. */
-int ptycho_llk(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
+PTYCHO_API int ptycho_llk(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                double *llk_dev);
 
 /* Noise models for reporting the likelihood (Section 4 lists Poisson,
@@ -237,7 +261,7 @@ typedef enum {
 
 /* As ptycho_llk with the terms of `model` (a ptycho_llk_model_t); an unknown
  * model is PTYCHO_E_INVALID.  llk_dev: double[2] device, as ptycho_llk. */
-int ptycho_llk_model(ptycho_plan_t plan, const float *obj_dev,
+PTYCHO_API int ptycho_llk_model(ptycho_plan_t plan, const float *obj_dev,
                      const float *probe_dev, int32_t model, double *llk_dev);
 
 /* Gradient of that LLK (maximum-likelihood operator ML):
@@ -246,21 +270,24 @@ int ptycho_llk_model(ptycho_plan_t plan, const float *obj_dev,
  *   g_obj   = 2 sum_jk S_j^T (conj(P_k) psi_jk)       complex[obj_ny][obj_nx]
  *   g_probe = 2 sum_j conj(O_j) psi_jk                 complex[K][N][N]
  * llk_dev (nullable, double[2]) receives the LLK as ptycho_llk. */
-int ptycho_ml_grad(ptycho_plan_t plan, const float *obj_dev,
+PTYCHO_API int ptycho_ml_grad(ptycho_plan_t plan, const float *obj_dev,
                    const float *probe_dev, float *g_obj_dev,
                    float *g_probe_dev, double *llk_dev);
 
 /* Line-search coefficients along (d_obj, d_probe): coef_dev (double[2],
  * device) receives { L'(0), L''(0) } of L(g) = LLK(O + g dO, P + g dP), with
- * L'' from the quadratic expansion of the intensity in g (Poisson ML
- * conjugate gradient, the method the paper cites for ML). */
-int ptycho_ml_linesearch(ptycho_plan_t plan, const float *obj_dev,
+ * L'' from the quadratic expansion of the intensity in g.  This is the step
+ * of operator ML (Section 4 algorithm list and the ptychography-operator
+ * table: conjugate gradient on the Poisson likelihood, after Thibault and
+ * Guizar-Sicairos 2012), whose quadratic line search it follows. */
+PTYCHO_API int ptycho_ml_linesearch(ptycho_plan_t plan, const float *obj_dev,
                          const float *probe_dev, const float *d_obj_dev,
                          const float *d_probe_dev, double *coef_dev);
 
-/* Device state of the conjugate-gradient ML iteration, in bytes, for
+/* Device state of the conjugate-gradient ML iteration (operator ML, Section
+ * 4: search direction, previous gradient and scalars), in bytes, for
  * ptycho_ml_cycle (host only). */
-int ptycho_ml_state_bytes(ptycho_plan_t plan, size_t *bytes_out);
+PTYCHO_API int ptycho_ml_state_bytes(ptycho_plan_t plan, size_t *bytes_out);
 
 /* n_cycles Polak-Ribiere conjugate-gradient ML cycles on the Poisson LLK,
  * entirely on the device (no host synchronisation): gradient, preconditioned
@@ -268,20 +295,20 @@ int ptycho_ml_state_bytes(ptycho_plan_t plan, size_t *bytes_out);
  * search, step.  state_dev: ptycho_ml_state_bytes() bytes, 256-byte aligned;
  * reset != 0 starts a new conjugate sequence (beta = 0).  llk_hist_dev
  * (nullable, double[n_cycles]) receives the LLK at the start of each cycle. */
-int ptycho_ml_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
+PTYCHO_API int ptycho_ml_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
                     void *state_dev, int32_t n_cycles, uint32_t update,
                     int32_t reset, double *llk_hist_dev);
 
 /* Calculated intensity sum_k |FT(O_j P_k)|^2 of every frame into
  * icalc_dev (float[J][N][N], FFT order); the forward model used to simulate
  * data. */
-int ptycho_icalc(ptycho_plan_t plan, const float *obj_dev,
+PTYCHO_API int ptycho_icalc(ptycho_plan_t plan, const float *obj_dev,
                  const float *probe_dev, float *icalc_dev);
 
 /* Batched unitary 2D FFT of `count` complex N x N frames in place
  * (direction -1 forward, +1 inverse), exposed for tests and the FFT
  * bandwidth benchmark of the paper's appendix (FFT performance). */
-int ptycho_fft2(int32_t n, int32_t count, float *data_dev, int32_t direction,
+PTYCHO_API int ptycho_fft2(int32_t n, int32_t count, float *data_dev, int32_t direction,
                 void *stream);
 
 /* Per-kernel timing for diagnostics and benchmarks: `classes` is a bit mask
@@ -295,12 +322,12 @@ int ptycho_fft2(int32_t n, int32_t count, float *data_dev, int32_t direction,
  * ptycho_plan_timing_read waits for the last recorded event and returns the
  * summed milliseconds and the launch count of one class since timing was
  * last enabled. */
-int ptycho_plan_timing(ptycho_plan_t plan, int32_t classes);
-int ptycho_plan_timing_read(ptycho_plan_t plan, int32_t cls, double *ms_total,
+PTYCHO_API int ptycho_plan_timing(ptycho_plan_t plan, int32_t classes);
+PTYCHO_API int ptycho_plan_timing_read(ptycho_plan_t plan, int32_t cls, double *ms_total,
                             int64_t *launches);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
-const char *ptycho_last_error(void);
+PTYCHO_API const char *ptycho_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -41,7 +41,7 @@ _P = ctypes.c_void_p
 _SIGS = {
     "ptycho_offsets_from_positions": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
     "ptycho_workspace_bytes": [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)],
-    "ptycho_plan_create": [ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "ptycho_plan": [ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
     "ptycho_plan_dry_run": [ctypes.POINTER(Desc), _P, ctypes.POINTER(ctypes.c_size_t)],
     "ptycho_plan_set_stream": [_P, _P],
     "ptycho_plan_set_background": [_P, _P],

@@ -1,29 +1,60 @@
 """Build the gfx950 HIP library libptycho.so in-tree with hipcc.
 
+The host code (ptycho.hip) and the stack kernels of each frame size
+(inst_N.hip) are separate translation units, compiled in parallel and linked
+into one shared library.
+
 Usage: python -m paper_2008_11511_amd.build  (or build() from Python).
 """
+import concurrent.futures
+import glob
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ptycho.hip")
+CSRC = os.path.join(HERE, "csrc")
+OBJDIR = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libptycho.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # keep hand-written float code off the packed-fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
+    # only the C ABI (PTYCHO_API) is exported
+    "-fvisibility=hidden",
 ]
 
 
-def build(verbose: bool = False) -> str:
+def sources():
+    """The library's translation units, largest frame sizes first (they take longest)."""
+    inst = sorted(glob.glob(os.path.join(CSRC, "inst_*.hip")),
+                  key=lambda f: -int(os.path.basename(f)[5:-4]))
+    return inst + [os.path.join(CSRC, "ptycho.hip")]
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src)[:-4] + ".o")
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile the library (always) and return its path."""
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           SRC, "-o", OUT + ".tmp"]
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, min(os.cpu_count() or 1, 16)))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -175,9 +175,13 @@ template <int N, int E, int DIR>
 __device__ __forceinline__ int out_index(int t, int e) { return elem_index<N, E, LastRadix<N, E, DIR>::value>(t, e); }
 
 // Twiddle table exp(-2 pi i m / 2048), m = 0..2047, filled once per device
-// (read-only for kernels, so loads can be shared between probe modes).
+// (read-only for kernels, so loads can be shared between probe modes).  Each
+// translation unit that runs transforms holds its own copy (internal
+// linkage) and fills it through its set_twiddles entry.
 constexpr int TW_MAX = 2048;
-extern __constant__ float2 g_twiddle[TW_MAX];
+namespace {
+__constant__ float2 g_twiddle[TW_MAX];
+}
 
 template <int DIR>
 __device__ __forceinline__ float2 twiddle(int m_of_table) {

@@ -18,33 +18,61 @@
 #include <vector>
 
 #include "ptycho.h"
+#include "plan.hpp"
 #include "kernels.hpp"
 #include "mlcg.hpp"
-
-namespace ptycho {
-__constant__ float2 g_twiddle[TW_MAX];
-}
 
 using namespace ptycho;
 
 // ------------------------------------------------------------------ errors --
 static thread_local std::string g_err;
-static int fail(int code, const std::string &msg) {
+int ptycho::fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
-#define HIPCHK(x)                                                                              \
-    do {                                                                                       \
-        hipError_t e_ = (x);                                                                   \
-        if (e_ != hipSuccess) return fail(PTYCHO_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-#define LAUNCHCHK()                                                                            \
-    do {                                                                                       \
-        hipError_t e_ = hipGetLastError();                                                     \
-        if (e_ != hipSuccess) return fail(PTYCHO_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
-    } while (0)
 
 extern "C" const char *ptycho_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------ frame-size table --
+// The stack kernels of each frame size live in a translation unit of their
+// own (inst_N.hip).  PTYCHO_KERNEL_N_MAX (a build option of the host-only
+// sanitizer test, whose program launches nothing) limits the sizes linked
+// in; the library is built with all of them.
+#ifndef PTYCHO_KERNEL_N_MAX
+#define PTYCHO_KERNEL_N_MAX 2048
+#endif
+namespace ptycho {
+const NPass *passes_8();
+#if PTYCHO_KERNEL_N_MAX >= 16
+const NPass *passes_16();
+const NPass *passes_32();
+const NPass *passes_64();
+const NPass *passes_128();
+const NPass *passes_256();
+const NPass *passes_512();
+const NPass *passes_1024();
+const NPass *passes_2048();
+#endif
+}  // namespace ptycho
+
+static const NPass *(*const g_passes[])() = {
+    passes_8,
+#if PTYCHO_KERNEL_N_MAX >= 16
+    passes_16, passes_32, passes_64, passes_128, passes_256, passes_512, passes_1024, passes_2048,
+#endif
+};
+
+static bool supported_n(int n) {
+    return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048;
+}
+
+// The passes of frame size n, or null (with the error recorded).
+static const NPass *passes_for(int n) {
+    for (auto get : g_passes)
+        if (get()->n == n) return get();
+    fail(PTYCHO_E_UNSUPPORTED, supported_n(n) ? "frame size not compiled into this build" : "unsupported frame size");
+    return nullptr;
+}
 
 // --------------------------------------------------------------- twiddles --
 static std::mutex g_tw_mu;
@@ -61,65 +89,15 @@ static int ensure_twiddles() {
         const double a = -2.0 * M_PI * (double)m / (double)TW_MAX;
         h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), h.data(), sizeof(float2) * TW_MAX));
+    for (auto get : g_passes) HIPCHK(get()->set_twiddles(h.data()));
     HIPCHK(hipDeviceSynchronize());
     g_tw_done[dev] = 1;
     return PTYCHO_OK;
 }
 
-// ------------------------------------------------------------- sizes -------
-static bool supported_n(int n) {
-    return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048;
-}
-
-// Kernel dispatch by frame size.  PTYCHO_KERNEL_N_MAX (a build option of
-// the host-only sanitizer test, whose program launches nothing) limits the
-// sizes whose kernels are compiled; the library is built with all of them.
-#ifndef PTYCHO_KERNEL_N_MAX
-#define PTYCHO_KERNEL_N_MAX 2048
-#endif
-template <class F>
-static int with_n(int n, F &&f) {
-    if (n > PTYCHO_KERNEL_N_MAX) return fail(PTYCHO_E_UNSUPPORTED, "frame size not compiled into this build");
-    switch (n) {
-        case 8: return f(std::integral_constant<int, 8>());
-        case 16: if constexpr (16 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 16>()); break;
-        case 32: if constexpr (32 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 32>()); break;
-        case 64: if constexpr (64 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 64>()); break;
-        case 128: if constexpr (128 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 128>()); break;
-        case 256: if constexpr (256 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 256>()); break;
-        case 512: if constexpr (512 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 512>()); break;
-        case 1024: if constexpr (1024 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 1024>()); break;
-        case 2048: if constexpr (2048 <= PTYCHO_KERNEL_N_MAX) return f(std::integral_constant<int, 2048>()); break;
-        default: break;
-    }
-    return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
-}
-template <class F>
-static int with_k(int k, F &&f) {
-    switch (k) {
-        case 1: return f(std::integral_constant<int, 1>());
-        case 2: return f(std::integral_constant<int, 2>());
-        case 3: return f(std::integral_constant<int, 3>());
-        case 4: return f(std::integral_constant<int, 4>());
-        default: return fail(PTYCHO_E_UNSUPPORTED, "unsupported number of probe modes");
-    }
-}
-
-
-static constexpr size_t ALIGN = 256;
-static size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 static constexpr int NPART = 512;       // blocks of the max-reduction
 static constexpr int NSCAL = 64;        // device scalars
 static constexpr int SC_NOBS = 0;       //   unmasked pixels of all frames (double)
-
-struct Layout {
-    int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
-    size_t nlist_ints, npslots;   // object-gather block/reduce lists, partial slots
-    size_t nent_max, nfr_max, nred;
-    size_t off_offs, off_order, off_lists, off_ent_fr, off_opart, off_scr, off_q, off_pint, off_numO, off_denO,
-        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, off_s2, off_bsum, off_prop, total;
-};
 
 // Frame chunks of the all-frame probe gather: enough blocks to fill the
 // chip (about 4096), never more chunks than frames.
@@ -194,82 +172,6 @@ static Layout layout_for(const ptycho_desc_t &d) {
     return L;
 }
 
-// Per-kernel-class timing with HIP events on the plan's stream.
-enum { TC_ROWS_FWD = 0, TC_COLS = 1, TC_ROWS_INV = 2, TC_GATHER_OBJ = 3, TC_GATHER_PROBE = 4,
-       TC_PROBE_ALL = 5, TC_NORMALIZE = 6, TC_OTHER = 7, TC_N = 8 };
-
-struct TimingLog {
-    bool on = false;
-    unsigned mask = 0;      // classes recorded (bit c: class c)
-    std::vector<hipEvent_t> pool;
-    std::vector<int> cls;   // class of event pair i (events 2i, 2i+1)
-    size_t used = 0;        // pairs recorded
-};
-
-struct ptycho_plan_s {
-    ptycho_desc_t d;
-    TimingLog timing;
-    Layout L;
-    hipStream_t stream;
-    const float *iobs;
-    const uint8_t *mask;
-    char *ws;
-    int2 *offs;
-    int *order;
-    int4 *ent_fr;
-    int *lists;          // device copy of h_lists
-    float2 *opnum;       // object-gather chunk partials
-    float *opden;
-    float2 *scr, *q, *numO, *numP, *pnum;
-    float *bg = nullptr;     // caller's background [N][N] (set_background), or null
-    float *s2 = nullptr;     // [S][N][N] with PTYCHO_FLAG_BACKGROUND
-    double *bsum = nullptr;  // [N][N]
-    float2 *prop = nullptr;  // [2][N] with PTYCHO_FLAG_NEAR_FIELD
-    bool nf_ready = false;   // Fresnel parameters set
-    std::vector<float2> h_prop;
-    float *pint, *denO, *denP, *pden, *part;
-    double *red, *scal;
-    int ntx, nty;
-    // Object-gather lists.  A list is a run of blocks (tile, entry range,
-    // partial slot or -1) followed by a run of reductions (split tile, first
-    // slot, count), stored in h_lists; GatherList gives the offsets.
-    struct GatherList {
-        int nb, blk_tile, blk_ptr, blk_slot, nr, red_tile, red_first, red_count;
-    };
-    std::vector<GatherList> stack_lists;
-    std::vector<int> h_lists;
-    // host copies kept alive for the asynchronous uploads
-    std::vector<int2> h_offs;
-    std::vector<int> h_order;
-    std::vector<int4> h_fr;
-};
-
-// Records an event pair around the launches made while it is alive.
-struct Timed {
-    ptycho_plan_s *p;
-    int c;
-    size_t pair;
-    bool rec = false;
-    Timed(ptycho_plan_s *p_, int c_) : p(p_), c(c_), pair(0) {
-        TimingLog &t = p->timing;
-        if (!t.on || !((t.mask >> c) & 1u)) return;
-        pair = t.used++;
-        while (t.pool.size() < 2 * t.used) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) { t.on = false; return; }
-            t.pool.push_back(e);
-        }
-        if (t.cls.size() < t.used) t.cls.resize(t.used);
-        t.cls[pair] = c;
-        (void)hipEventRecord(t.pool[2 * pair], p->stream);
-        rec = true;
-    }
-    ~Timed() {
-        TimingLog &t = p->timing;
-        if (rec && t.on) (void)hipEventRecord(t.pool[2 * pair + 1], p->stream);
-    }
-};
-
 // ---------------------------------------------------------------- validate --
 static int check_desc(const ptycho_desc_t *d) {
     if (!d) return fail(PTYCHO_E_INVALID, "null descriptor");
@@ -324,7 +226,7 @@ static uint32_t spread_bits(uint32_t v) {
 }
 
 // Host-side index tables of a plan: frame order, object-gather lists.  No
-// GPU work; shared by ptycho_plan_create and ptycho_plan_dry_run.
+// GPU work; shared by ptycho_plan and ptycho_plan_dry_run.
 static int build_host_tables(ptycho_plan_s *p, const Layout &L, const int32_t *offsets) {
     const ptycho_desc_t *d = &p->d;
     const int J = d->n_frames, N = d->n;
@@ -492,7 +394,7 @@ static hipError_t upload_tables(const std::vector<HostPart> &parts, hipStream_t 
     return hipSuccess;
 }
 
-extern "C" int ptycho_plan_create(const ptycho_desc_t *d, const int32_t *offsets, const float *iobs,
+extern "C" int ptycho_plan(const ptycho_desc_t *d, const int32_t *offsets, const float *iobs,
                                   const uint8_t *mask, void *ws, size_t ws_bytes, void *stream,
                                   ptycho_plan_t *out) {
     int st = check_desc(d);
@@ -626,13 +528,6 @@ static int check_geometry(const ptycho_plan_s *p) {
     return PTYCHO_OK;
 }
 
-// Calls f(std::true_type) on a near-field plan, f(std::false_type) otherwise.
-template <class F>
-static int with_nf(const ptycho_plan_s *p, F &&f) {
-    if (p->prop) return f(std::true_type{});
-    return f(std::false_type{});
-}
-
 extern "C" int ptycho_plan_set_stream(ptycho_plan_t p, void *stream) {
     if (!p) return fail(PTYCHO_E_INVALID, "null plan");
     p->stream = (hipStream_t)stream;
@@ -681,8 +576,6 @@ extern "C" int ptycho_plan_timing_read(ptycho_plan_t p, int32_t cls, double *ms_
 }
 
 // ----------------------------------------------------------------- passes --
-static int grid_for(long n) { return (int)std::max(1L, std::min((n + 255) / 256, 4096L)); }
-
 static int zero_async(void *ptr, size_t bytes, hipStream_t s) {
     // plain fill kernel (no memset nodes, so the work can be graph-captured)
     if (bytes % 16) return fail(PTYCHO_E_INVALID, "internal: zero size");
@@ -692,7 +585,7 @@ static int zero_async(void *ptr, size_t bytes, hipStream_t s) {
     return PTYCHO_OK;
 }
 
-static StackArgs stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, const float *probe) {
+StackArgs ptycho::stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, const float *probe) {
     StackArgs a{};
     a.Ny = p->d.obj_ny;
     a.Nx = p->d.obj_nx;
@@ -713,38 +606,6 @@ static StackArgs stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj, 
     return a;
 }
 
-// Kernels whose dynamic LDS exceeds 64 KiB must opt in once per process.
-template <class KernelT>
-static hipError_t set_dyn_lds(KernelT kern, size_t bytes) {
-    if (bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-template <int N>
-static int rows_blocks(int sn) {
-    return (int)(((long)sn * N + RowGeom<N>::RB - 1) / RowGeom<N>::RB);
-}
-template <int N>
-static int cols_blocks(int sn) {
-    return (int)(((long)sn * N + ColGeom<N>::CB - 1) / ColGeom<N>::CB);
-}
-
-template <int N, int K, int OP, bool NF>
-static void launch_cols_joint(const StackArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * ColJoint<N, K>::BUFS;
-    static const hipError_t attr = set_dyn_lds(k_cols_joint<N, K, OP, NF>, lds);
-    (void)attr;
-    hipLaunchKernelGGL((k_cols_joint<N, K, OP, NF>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s,
-                       a);
-}
-template <int N, int OP, bool NF>
-static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2 * ColSeqBufs<N, OP>::value;
-    static const hipError_t attr = set_dyn_lds(k_cols_seq<N, OP, NF>, lds);
-    (void)attr;
-    hipLaunchKernelGGL((k_cols_seq<N, OP, NF>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
-}
-
 // log2 of the tile width of exit waves at psi: the stack scratch is stored in
 // column tiles, caller-stored exit waves are row-major.
 static int psi_tile_log2(const ptycho_plan_s *p, const float2 *psi) {
@@ -756,7 +617,7 @@ static int psi_tile_log2(const ptycho_plan_s *p, const float2 *psi) {
 // Object sums of one stack, added to the running sums, from the stack's
 // per-frame numerator terms q (written by the inverse row pass) and the
 // probe intensity image.
-static int object_sums(ptycho_plan_s *p, int sidx) {
+int ptycho::object_sums(ptycho_plan_s *p, int sidx) {
     const ptycho_plan_s::GatherList &gl = p->stack_lists[sidx];
     if (gl.nb <= 0) return PTYCHO_OK;
     ObjTileArgs a{};
@@ -789,7 +650,7 @@ static int object_sums(ptycho_plan_s *p, int sidx) {
 // Probe sums over frames order[q0 .. q0+nq) with the given object, from the
 // stack scratch (slots) or stored exit waves (frames); deterministic chunked
 // reduction, written or added to the running sums.
-static int probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, int q0, int nq, bool from_scr,
+int ptycho::probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, int q0, int nq, bool from_scr,
                       bool accumulate) {
     ProbeAllArgs a{};
     a.N = p->d.n;
@@ -820,9 +681,6 @@ static int probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, int
     return PTYCHO_OK;
 }
 
-// Which sums a projection pass accumulates.
-enum { ACC_OBJ = 1, ACC_PROBE = 2 };
-
 static int zero_sums(ptycho_plan_s *p, unsigned acc) {
     const size_t no = (size_t)p->d.obj_ny * p->d.obj_nx, n2 = (size_t)p->d.n * p->d.n;
     int st = PTYCHO_OK;
@@ -837,72 +695,20 @@ static int zero_sums(ptycho_plan_s *p, unsigned acc) {
     return st;
 }
 
-template <int N, int K, int MODE, bool NF>
-static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
-    const dim3 grid((unsigned)(((long)a.S * N + InvRowGeom<N>::RQ - 1) / InvRowGeom<N>::RQ));
-    const dim3 block(InvRowGeom<N>::TPM * K);
-    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true, NF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false, NF>), grid, block, 0, s, a);
+// Probe intensity image sum_k |P_k|^2 (the object denominator's term).
+int ptycho::launch_probe_intensity(ptycho_plan_s *p, const float *probe) {
+    const long n2 = (long)p->d.n * p->d.n;
+    hipLaunchKernelGGL(k_probe_intensity, dim3(grid_for(n2)), dim3(256), 0, p->stream, (const float2 *)probe,
+                       p->d.n_modes, n2, p->pint);
+    LAUNCHCHK();
+    return PTYCHO_OK;
 }
 
-// One pass over all stacks: forward rows, column op, inverse rows and the
-// per-stack gathers.  kind: 0 = AP projection, 1 = DM, 2 = ML gradient.
-// Exit waves go to `psi` (all frames) when it is given, else stay in the
-// stack scratch.  acc selects the sums taken per stack: the object sums
-// (from the inverse row pass's per-frame terms), the probe sums (only for
-// the gradient, whose two sums are taken at the same point; they read the
-// exit waves from the scratch).
-template <int N, int K, bool NF>
-static int project_pass(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind,
-                        unsigned acc, bool upd_bg = false) {
-    const int J = p->d.n_frames, S = p->L.S;
-    hipStream_t s = p->stream;
-    const bool store = (psi != nullptr);
-    const bool wq = (acc & ACC_OBJ) != 0;
-    if (wq) {
-        const long n2 = (long)N * N;
-        Timed tm(p, TC_OTHER);
-        hipLaunchKernelGGL(k_probe_intensity, dim3(grid_for(n2)), dim3(256), 0, s, (const float2 *)probe, K, n2,
-                           p->pint);
-    }
-    for (int sidx = 0; sidx < p->L.nstacks; ++sidx) {
-        const int s0 = sidx * S, sn = std::min(S, J - s0);
-        StackArgs a = stack_args(p, s0, sn, obj, probe);
-        a.psi = (const float2 *)psi;
-        a.psi_out = (float2 *)psi;
-        a.red = p->red + (size_t)sidx * p->L.maxb;
-        if (upd_bg) a.s2 = p->s2;
-        const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
-        {
-            Timed tm(p, TC_ROWS_FWD);
-            if (kind == 1) hipLaunchKernelGGL((k_rows_fwd<N, IN_DM, NF>), rg, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI, NF>), rg, dim3(256), 0, s, a);
-        }
-        {
-            Timed tm(p, TC_COLS);
-            if (kind == 2) launch_cols_joint<N, K, OP_GRAD, NF>(a, s);
-            else if (kind == 1) launch_cols_joint<N, K, OP_CORR, NF>(a, s);
-            else launch_cols_joint<N, K, OP_PROJECT, NF>(a, s);
-        }
-        if (upd_bg) {
-            const long n2 = (long)N * N;
-            Timed tm(p, TC_OTHER);
-            hipLaunchKernelGGL(k_bg_accum, dim3(grid_for(n2)), dim3(256), 0, s, p->s2, sn, n2, p->bsum,
-                               sidx == 0 ? 1 : 0);
-        }
-        {
-            Timed tm(p, TC_ROWS_INV);
-            if (kind == 1) launch_rows_inv<N, K, OUT_DM, NF>(a, wq, s);
-            else if (store) launch_rows_inv<N, K, OUT_STORE, NF>(a, wq, s);
-            else if (acc & ACC_PROBE) launch_rows_inv<N, K, OUT_SCR, NF>(a, wq, s);
-            else launch_rows_inv<N, K, OUT_NONE, NF>(a, wq, s);
-        }
-        LAUNCHCHK();
-        int st = PTYCHO_OK;
-        if (acc & ACC_OBJ) st = object_sums(p, sidx);
-        if (!st && (acc & ACC_PROBE)) st = probe_sums(p, obj, p->scr, s0, sn, true, true);
-        if (st) return st;
-    }
+// AP background refinement: the s^2 sums of one stack of sn frames.
+int ptycho::launch_bg_accum(ptycho_plan_s *p, int sn, int first) {
+    const long n2 = (long)p->d.n * p->d.n;
+    hipLaunchKernelGGL(k_bg_accum, dim3(grid_for(n2)), dim3(256), 0, p->stream, p->s2, sn, n2, p->bsum, first);
+    LAUNCHCHK();
     return PTYCHO_OK;
 }
 
@@ -946,34 +752,26 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
     if (kind == 1 && !psi) return fail(PTYCHO_E_INVALID, "null psi");
     if (kind == 0 && (upd & 2u) && !psi)
         return fail(PTYCHO_E_INVALID, "an AP probe update needs exit-wave storage (psi)");
-    return with_n(p->d.n, [&](auto nn) {
-        constexpr int N = decltype(nn)::value;
-        return with_k(p->d.n_modes, [&](auto kk) {
-            constexpr int K = decltype(kk)::value;
-            for (int c = 0; c < n_cycles; ++c) {
-                int s2 = PTYCHO_OK;
-                if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
-                if (!s2)
-                    s2 = with_nf(p, [&](auto nf) {
-                        return project_pass<N, K, decltype(nf)::value>(p, obj, probe, psi, kind,
-                                                                        (upd & 1u) ? ACC_OBJ : 0u, upd_bg);
-                    });
-                if (!s2 && upd_bg) {
-                    // every stack was projected with the old background
-                    const long n2 = (long)N * N;
-                    Timed tm(p, TC_OTHER);
-                    hipLaunchKernelGGL(k_bg_finish, dim3(grid_for(n2)), dim3(256), 0, p->stream, p->bg, p->bsum, n2,
-                                       (double)p->d.n_frames);
-                    s2 = hipGetLastError() == hipSuccess ? PTYCHO_OK : fail(PTYCHO_E_HIP, "background update launch");
-                }
-                if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
-                if (!s2 && (upd & 2u)) s2 = probe_sums(p, obj, (const float2 *)psi, 0, p->d.n_frames, false, false);
-                if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);
-                if (s2) return s2;
-            }
-            return (int)PTYCHO_OK;
-        });
-    });
+    const NPass *np = passes_for(p->d.n);
+    if (!np) return PTYCHO_E_UNSUPPORTED;
+    const long n2 = (long)p->d.n * p->d.n;
+    for (int c = 0; c < n_cycles; ++c) {
+        int s2 = PTYCHO_OK;
+        if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
+        if (!s2) s2 = np->project(p, obj, probe, psi, kind, (upd & 1u) ? ACC_OBJ : 0u, upd_bg);
+        if (!s2 && upd_bg) {
+            // every stack was projected with the old background
+            Timed tm(p, TC_OTHER);
+            hipLaunchKernelGGL(k_bg_finish, dim3(grid_for(n2)), dim3(256), 0, p->stream, p->bg, p->bsum, n2,
+                               (double)p->d.n_frames);
+            s2 = hipGetLastError() == hipSuccess ? PTYCHO_OK : fail(PTYCHO_E_HIP, "background update launch");
+        }
+        if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
+        if (!s2 && (upd & 2u)) s2 = probe_sums(p, obj, (const float2 *)psi, 0, p->d.n_frames, false, false);
+        if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);
+        if (s2) return s2;
+    }
+    return PTYCHO_OK;
 }
 
 extern "C" int ptycho_ap_cycle(ptycho_plan_t p, float *obj, float *probe, float *psi, int32_t n_cycles,
@@ -997,36 +795,12 @@ extern "C" int ptycho_psi_init(ptycho_plan_t p, const float *obj, const float *p
     return PTYCHO_OK;
 }
 
-// Read-only forward passes: LLK, icalc, line search.
-template <int N, int OP, bool NF>
-static int forward_pass(ptycho_plan_s *p, const float *obj, const float *probe, const float *dobj,
+// A read-only forward pass of column op `op` through the frame-size table.
+static int forward_pass(ptycho_plan_s *p, int op, const float *obj, const float *probe, const float *dobj,
                         const float *dprobe, float *icalc, int llk_model = LLK_POISSON) {
-    const bool ls = (OP == OP_LS);
-    const int J = p->d.n_frames, S = ls ? p->L.S_ls : p->L.S;
-    const int nst = ls ? p->L.nstacks_ls : p->L.nstacks;
-    const int maxb = ls ? p->L.maxb_ls : p->L.maxb;
-    hipStream_t s = p->stream;
-    for (int sidx = 0; sidx < nst; ++sidx) {
-        const int s0 = sidx * S, sn = std::min(S, J - s0);
-        StackArgs a = stack_args(p, s0, sn, obj, probe);
-        a.dobj = (const float2 *)dobj;
-        a.dprobe = (const float2 *)dprobe;
-        a.icalc = icalc;
-        a.llk_model = llk_model;
-        a.red = p->red + (size_t)sidx * maxb * (ls ? 2 : 1);
-        const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
-        {
-            Timed tm(p, TC_ROWS_FWD);
-            if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS, NF>), rg, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI, NF>), rg, dim3(256), 0, s, a);
-        }
-        {
-            Timed tm(p, TC_COLS);
-            launch_cols_seq<N, OP, NF>(a, s);
-        }
-        LAUNCHCHK();
-    }
-    return PTYCHO_OK;
+    const NPass *np = passes_for(p->d.n);
+    if (!np) return PTYCHO_E_UNSUPPORTED;
+    return np->forward(p, op, obj, probe, dobj, dprobe, icalc, llk_model);
 }
 
 static int zero_red(ptycho_plan_s *p) { return zero_async(p->red, up(sizeof(double) * p->L.nred), p->stream); }
@@ -1037,12 +811,7 @@ __global__ void k_copy_scalar(double *dst, const double *src) { dst[0] = src[0];
 static int llk_into(ptycho_plan_t p, const float *obj, const float *probe, double *llk, int model) {
     int st = zero_red(p);
     if (st) return st;
-    st = with_n(p->d.n, [&](auto nn) {
-        return with_nf(p, [&](auto nf) {
-            return forward_pass<decltype(nn)::value, OP_LLK, decltype(nf)::value>(p, obj, probe, nullptr, nullptr,
-                                                                                  nullptr, model);
-        });
-    });
+    st = forward_pass(p, OP_LLK, obj, probe, nullptr, nullptr, nullptr, model);
     if (st) return st;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
     hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, p->stream, llk + 1, p->scal + SC_NOBS);
@@ -1105,12 +874,7 @@ extern "C" int ptycho_icalc(ptycho_plan_t p, const float *obj, const float *prob
     int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (!icalc) return fail(PTYCHO_E_INVALID, "null icalc output");
-    return with_n(p->d.n, [&](auto nn) {
-        return with_nf(p, [&](auto nf) {
-            return forward_pass<decltype(nn)::value, OP_ICALC, decltype(nf)::value>(p, obj, probe, nullptr, nullptr,
-                                                                                    icalc);
-        });
-    });
+    return forward_pass(p, OP_ICALC, obj, probe, nullptr, nullptr, icalc);
 }
 
 // Gradient pass: sums in numO/numP (and denominators), LLK partials in red.
@@ -1118,15 +882,9 @@ static int grad_pass(ptycho_plan_s *p, const float *obj, const float *probe) {
     int st = zero_sums(p, ACC_OBJ | ACC_PROBE);
     if (!st) st = zero_red(p);
     if (st) return st;
-    return with_n(p->d.n, [&](auto nn) {
-        constexpr int N = decltype(nn)::value;
-        return with_k(p->d.n_modes, [&](auto kk) {
-            return with_nf(p, [&](auto nf) {
-                return project_pass<N, decltype(kk)::value, decltype(nf)::value>(p, obj, probe, nullptr, 2,
-                                                                                 ACC_OBJ | ACC_PROBE);
-            });
-        });
-    });
+    const NPass *np = passes_for(p->d.n);
+    if (!np) return PTYCHO_E_UNSUPPORTED;
+    return np->project(p, obj, probe, nullptr, 2, ACC_OBJ | ACC_PROBE, false);
 }
 
 extern "C" int ptycho_ml_grad(ptycho_plan_t p, const float *obj, const float *probe, float *g_obj, float *g_probe,
@@ -1151,12 +909,7 @@ static int ls_pass(ptycho_plan_s *p, const float *obj, const float *probe, const
                    double *coef) {
     int st = zero_red(p);
     if (st) return st;
-    st = with_n(p->d.n, [&](auto nn) {
-        return with_nf(p, [&](auto nf) {
-            return forward_pass<decltype(nn)::value, OP_LS, decltype(nf)::value>(p, obj, probe, dobj, dprobe,
-                                                                                 nullptr);
-        });
-    });
+    st = forward_pass(p, OP_LS, obj, probe, dobj, dprobe, nullptr);
     if (st) return st;
     const long n = (long)p->L.nred / 2;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, n, 2, coef, 0);
@@ -1246,28 +999,7 @@ extern "C" int ptycho_fft2(int32_t n, int32_t count, float *data, int32_t dir, v
     if (!data) return fail(PTYCHO_E_INVALID, "null data");
     int st = ensure_twiddles();
     if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
-    return with_n(n, [&](auto nn) {
-        constexpr int N = decltype(nn)::value;
-        const long rows = (long)count * N;
-        const int rb = (int)((rows + RowGeom<N>::RB - 1) / RowGeom<N>::RB);
-        const int cbk = (int)((rows + ColGeom<N>::CB - 1) / ColGeom<N>::CB);
-        const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2;
-        const float scale = 1.0f / (float)N;
-        if (dir < 0) {
-            static const hipError_t attr = set_dyn_lds(k_fft_cols<N, -1>, lds);
-            (void)attr;
-            hipLaunchKernelGGL((k_fft_rows<N, -1>), dim3(rb), dim3(256), 0, s, (float2 *)data, rows);
-            hipLaunchKernelGGL((k_fft_cols<N, -1>), dim3(cbk), dim3(ColGeom<N>::THREADS), lds, s, (float2 *)data,
-                               (long)count, scale);
-        } else {
-            static const hipError_t attr = set_dyn_lds(k_fft_cols<N, 1>, lds);
-            (void)attr;
-            hipLaunchKernelGGL((k_fft_rows<N, 1>), dim3(rb), dim3(256), 0, s, (float2 *)data, rows);
-            hipLaunchKernelGGL((k_fft_cols<N, 1>), dim3(cbk), dim3(ColGeom<N>::THREADS), lds, s, (float2 *)data,
-                               (long)count, scale);
-        }
-        LAUNCHCHK();
-        return (int)PTYCHO_OK;
-    });
+    const NPass *np = passes_for(n);
+    if (!np) return PTYCHO_E_UNSUPPORTED;
+    return np->fft2(count, data, dir, (hipStream_t)stream);
 }

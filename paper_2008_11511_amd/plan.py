@@ -129,7 +129,7 @@ class Plan:
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            check(lib().ptycho_plan_create(ctypes.byref(self.desc), offs.ctypes.data, _ptr(iobs),
+            check(lib().ptycho_plan(ctypes.byref(self.desc), offs.ctypes.data, _ptr(iobs),
                                            _ptr(mask) if mask is not None else None,
                                            _ptr(self.workspace), self.workspace_bytes, stream,
                                            ctypes.byref(h)))

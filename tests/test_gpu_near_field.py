@@ -235,7 +235,7 @@ def test_near_field_arguments_are_checked(dev):
     h = ctypes.c_void_p()
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     offs = np.ascontiguousarray(pb.offsets, dtype=np.int32)
-    check(lib().ptycho_plan_create(ctypes.byref(d2), offs.ctypes.data, iobs.data_ptr(), None, ws.data_ptr(),
+    check(lib().ptycho_plan(ctypes.byref(d2), offs.ctypes.data, iobs.data_ptr(), None, ws.data_ptr(),
                                    plan.workspace_bytes, torch.cuda.current_stream(dev).cuda_stream,
                                    ctypes.byref(h)))
     try:

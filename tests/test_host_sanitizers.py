@@ -22,6 +22,7 @@ def test_host_code_is_clean_under_asan_and_ubsan(tmp_path):
            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Wno-unused-result",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2008_11511_amd", "csrc"),
            os.path.join(ROOT, "paper_2008_11511_amd", "csrc", "ptycho.hip"),
+           os.path.join(ROOT, "paper_2008_11511_amd", "csrc", "inst_8.hip"),
            os.path.join(ROOT, "tests", "native", "host_checks.cpp"), "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")

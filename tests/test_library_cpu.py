@@ -28,6 +28,25 @@ def test_library_exports_every_declared_symbol():
     assert sorted(_lib.exported_symbols()) == names
 
 
+def test_boundary_exports_the_operator_entry_points_and_nothing_else():
+    """The plan and the four operator calls carry their C names, and the
+    shared library exports only the C ABI (no internal C++ symbols)."""
+    h = _lib.lib()
+    for name in ("ptycho_plan", "ptycho_ap_cycle", "ptycho_dm_cycle", "ptycho_ml_grad", "ptycho_llk"):
+        assert hasattr(h, name), name
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("no nm")
+    out = subprocess.run([nm, "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    text_syms = [ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] == "T"]
+    assert text_syms and all(s.startswith("ptycho_") for s in text_syms), [s for s in text_syms
+                                                                            if not s.startswith("ptycho_")]
+    assert set(declared_functions()) <= set(text_syms)
+
+
 def test_offsets_match_oracle_bitwise_on_a_million_positions():
     rng = np.random.default_rng(0)
     n, shape = 64, (4096, 3000)
@@ -97,18 +116,18 @@ def test_plan_create_rejects_bad_arguments_before_gpu_work():
     offs = np.zeros((10, 2), np.int32)
     fake = ctypes.c_void_p(256)     # never dereferenced: validation fails first
     # null workspace
-    assert h.ptycho_plan_create(ctypes.byref(_desc()), offs.ctypes.data, fake, None, None, 0, None,
+    assert h.ptycho_plan(ctypes.byref(_desc()), offs.ctypes.data, fake, None, None, 0, None,
                                 ctypes.byref(out)) == -5
     # misaligned workspace
-    assert h.ptycho_plan_create(ctypes.byref(_desc()), offs.ctypes.data, fake, None, ctypes.c_void_p(257),
+    assert h.ptycho_plan(ctypes.byref(_desc()), offs.ctypes.data, fake, None, ctypes.c_void_p(257),
                                 1 << 30, None, ctypes.byref(out)) == -5
     # too small
-    assert h.ptycho_plan_create(ctypes.byref(_desc()), offs.ctypes.data, fake, None, ctypes.c_void_p(256),
+    assert h.ptycho_plan(ctypes.byref(_desc()), offs.ctypes.data, fake, None, ctypes.c_void_p(256),
                                 16, None, ctypes.byref(out)) == -5
     # window outside the object
     bad = offs.copy()
     bad[3] = [100, 0]
-    assert h.ptycho_plan_create(ctypes.byref(_desc()), bad.ctypes.data, fake, None, ctypes.c_void_p(256),
+    assert h.ptycho_plan(ctypes.byref(_desc()), bad.ctypes.data, fake, None, ctypes.c_void_p(256),
                                 1 << 40, None, ctypes.byref(out)) == -2
     # null plan handles
     assert h.ptycho_ap_cycle(None, fake, fake, fake, 1, 3) == -1
@@ -149,7 +168,7 @@ def test_plan_tables_for_awkward_shapes_and_dense_scans():
     # all windows at one spot: the heaviest possible tile lists
     offs = np.zeros((3000, 2), np.int32)
     assert _dry(64, 1, 3000, (64, 64), 0, offs)[0] == 0
-    # out-of-bounds offsets are reported, as by ptycho_plan_create
+    # out-of-bounds offsets are reported, as by ptycho_plan
     assert _dry(64, 1, 1, (64, 64), 0, np.array([[1, 0]]))[0] == -2
 
 
