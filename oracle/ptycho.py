@@ -47,7 +47,7 @@ __all__ = [
     "calc_intensity", "project_modulus", "fourier_project", "overlap_sums",
     "overlap_denominators", "overlap_update", "ap_cycle", "dm_cycle",
     "psi_init", "llk", "llk_terms", "llk_model_terms", "LLK_MODELS", "ml_grad", "linesearch_coefs",
-    "CGState", "ml_cycle", "simulate_intensity", "UPDATE_OBJECT",
+    "CGState", "cg_direction", "ml_cycle", "simulate_intensity", "UPDATE_OBJECT",
     "UPDATE_PROBE", "UPDATE_BACKGROUND", "DEFAULT_EPS", "DEFAULT_INERTIA",
     "model_intensity", "projection_scale", "background_update",
     "object_gradient", "position_shifts", "update_positions",
@@ -472,14 +472,41 @@ class CGState:
     history: list = field(default_factory=list)
 
 
+def cg_direction(state: CGState, g_o, g_p, s: float):
+    """Search direction of one preconditioned Polak-Ribiere (PR+) step.
+
+    Operator ML's conjugate gradient (Section 4, after Thibault and
+    Guizar-Sicairos 2012).  The preconditioner scales the probe block by s:
+    z = (g_O, s g_P).  With the previous gradient and direction in `state`,
+      beta = max(0, <z_n, g_n - g_{n-1}> / <z_{n-1}, g_{n-1}>)
+    (Polak-Ribiere, restarted at 0 whenever it is negative), beta = 0 when no
+    previous direction exists, and d = -z + beta d_prev, where
+    <a, b> = Re sum conj(a) b over the object and probe blocks.  Updates
+    `state` (direction, gradient, <z, g>) and returns (d_O, d_P, beta).
+    """
+    zg = _dot(g_o, g_o) + s * _dot(g_p, g_p)
+    if state.d_obj is None or state.zg <= 0.0:
+        beta = 0.0
+        d_o = -g_o
+        d_p = -s * g_p
+    else:
+        num = _dot(g_o, g_o - state.g_obj) + s * _dot(g_p, g_p - state.g_probe)
+        beta = max(0.0, num / state.zg)
+        d_o = -g_o + beta * state.d_obj
+        d_p = -s * g_p + beta * state.d_probe
+    state.d_obj, state.d_probe = d_o, d_p
+    state.g_obj, state.g_probe = g_o, g_p
+    state.zg = zg
+    return d_o, d_p, beta
+
+
 def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
              update=UPDATE_OBJECT, eps=DEFAULT_EPS, bg=None, nf=None):
     """One Polak-Ribiere (PR+) conjugate-gradient step on the Poisson LLK.
 
     The probe block of the gradient is scaled by s = max(denO) / max(denP)
-    (a diagonal preconditioner that balances object and probe steps);
-    z = (g_O, s g_P); beta = max(0, <z_n, g_n - g_{n-1}> / <z_{n-1}, g_{n-1}>)
-    (0 on the first cycle); d = -z + beta d_prev; the step gamma = -L'(0)/L''(0)
+    (a diagonal preconditioner that balances object and probe steps) and the
+    direction comes from `cg_direction`; the step gamma = -L'(0)/L''(0)
     from `linesearch_coefs` (0 when L''(0) <= 0).  Blocks not being updated
     have zero gradient.  Returns (obj, probe) and updates `state` in place;
     `state.history` receives the LLK at the start of the cycle.
@@ -493,21 +520,9 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
         g_p = np.zeros_like(g_p)
     den_o, den_p = overlap_denominators(obj, probe, offsets)
     s = den_o.max() / den_p.max() if den_p.max() > 0 else 1.0
-    zg = _dot(g_o, g_o) + s * _dot(g_p, g_p)
-    if state.d_obj is None or state.zg <= 0.0:
-        beta = 0.0
-        d_o = -g_o
-        d_p = -s * g_p
-    else:
-        num = _dot(g_o, g_o - state.g_obj) + s * _dot(g_p, g_p - state.g_probe)
-        beta = max(0.0, num / state.zg)
-        d_o = -g_o + beta * state.d_obj
-        d_p = -s * g_p + beta * state.d_probe
+    d_o, d_p, _ = cg_direction(state, g_o, g_p, s)
     l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps, bg, nf)
     gamma = -l1 / l2 if (l2 > 0.0 and math.isfinite(l1) and math.isfinite(l2)) else 0.0
-    state.d_obj, state.d_probe = d_o, d_p
-    state.g_obj, state.g_probe = g_o, g_p
-    state.zg = zg
     state.history.append(lsum)
     return obj + gamma * d_o, probe + gamma * d_p
 
