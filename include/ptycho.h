@@ -192,6 +192,26 @@ PTYCHO_API int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
 PTYCHO_API int ptycho_position_shifts(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                            const float *psi_dev, double *out_dev);
 
+/* Position update of the refinement (Section 4: position optimisation
+ * during AP and ML after Odstrcil et al. 2018, with a filter that keeps
+ * frames of too little object contrast in place).  For every frame j and
+ * axis, with e_j the gradient energy and d_j the shift from
+ * ptycho_position_shifts (shifts_dev, double[J][3] device):
+ *   keep_j = e_j >= min_grad * median_j(e_j)
+ *   p'_j   = pos_j + mult * (keep_j ? d_j : 0)
+ *   out_j  = pos0_j + clamp(p'_j - pos0_j, -max_shift, max_shift)
+ * (the paper's update_pos_mult and update_pos_max_shift; the median of an
+ * even count is the mean of the two middle values; gradient energies must
+ * be finite).  pos_dev, pos0_dev (starting positions), pos_out_dev:
+ * double[J][2] device, in pixels; pos_out_dev may equal pos_dev.  Enqueued
+ * on `stream` (hipStream_t), no plan and no workspace; the caller turns the
+ * new positions into offsets (ptycho_offsets_from_positions) and a plan.
+ * PTYCHO_E_INVALID for n_frames < 1, null pointers, non-finite parameters or
+ * negative max_shift / min_grad. */
+PTYCHO_API int ptycho_update_positions(int32_t n_frames, const double *pos_dev, const double *pos0_dev,
+                                       const double *shifts_dev, double mult, double max_shift,
+                                       double min_grad, double *pos_out_dev, void *stream);
+
 /* Failure detection: flag_dev (int32[1], device) is set to 1 if any value
  * of the object or probe is NaN or infinite, else 0 (enqueued, so a caller
  * can copy the flag back and read it at its next poll without waiting). */

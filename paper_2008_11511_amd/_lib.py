@@ -47,6 +47,8 @@ _SIGS = {
     "ptycho_plan_set_background": [_P, _P],
     "ptycho_plan_set_near_field": [_P, ctypes.c_double, ctypes.c_double],
     "ptycho_position_shifts": [_P, _P, _P, _P, _P],
+    "ptycho_update_positions": [ctypes.c_int32, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
+                                _P],
     "ptycho_check_finite": [_P, _P, _P, _P],
     "ptycho_plan_stack": [_P, ctypes.POINTER(ctypes.c_int32)],
     "ptycho_plan_destroy": [_P],

@@ -89,6 +89,77 @@ __global__ __launch_bounds__(256) void k_pos_shift(PosShiftArgs a) {
     }
 }
 
+// Position update of the refinement (Section 4: frames move by the shift
+// estimated from the exit waves, except frames whose object gradient is too
+// weak to tell a shift, and the total move from the starting positions is
+// bounded).  One block: the median of the frames' gradient energies by an
+// exact radix selection over their bit patterns (non-negative doubles order
+// as unsigned integers), then, for every frame j and axis a,
+//   keep_j = e_j >= min_grad * median(e)
+//   p'     = p + mult * (keep_j ? d : 0)
+//   out    = p0 + clamp(p' - p0, -max_shift, max_shift)
+// with the median of an even count the mean of the two middle values.  The
+// arithmetic is not contracted into fused multiply-adds, so every step
+// rounds as written.  out may alias pos.
+constexpr int POSUPD_THREADS = 1024;
+
+// The k-th smallest (0-based) of the non-negative doubles v[stride * i],
+// i < n, as its bit pattern; every thread of the block returns it.
+__device__ unsigned long long select_kth_nonneg(const double *v, int n, int stride, int k, unsigned *hist,
+                                                unsigned long long *s_prefix, int *s_rank) {
+    unsigned long long prefix = 0ull;
+    int rank = k;
+    for (int sh = 56; sh >= 0; sh -= 8) {
+        const unsigned long long decided = (sh == 56) ? 0ull : (~0ull << (sh + 8));
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const unsigned long long key = (unsigned long long)__double_as_longlong(v[(size_t)stride * i]);
+            if ((key & decided) == prefix) atomicAdd(&hist[(key >> sh) & 255ull], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int below = 0, b = 0;
+            for (; b < 255; ++b) {
+                if (below + (int)hist[b] > rank) break;
+                below += (int)hist[b];
+            }
+            *s_prefix = prefix | ((unsigned long long)b << sh);
+            *s_rank = rank - below;
+        }
+        __syncthreads();
+        prefix = *s_prefix;
+        rank = *s_rank;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+__global__ __launch_bounds__(POSUPD_THREADS) void k_update_positions(int J, const double *pos, const double *pos0,
+                                                                     const double *shifts, double mult,
+                                                                     double max_shift, double min_grad,
+                                                                     double *out) {
+#pragma clang fp contract(off)
+    __shared__ unsigned hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_rank;
+    const unsigned long long lo = select_kth_nonneg(shifts + 2, J, 3, (J - 1) / 2, hist, &s_prefix, &s_rank);
+    const unsigned long long hi = select_kth_nonneg(shifts + 2, J, 3, J / 2, hist, &s_prefix, &s_rank);
+    const double median = (__longlong_as_double((long long)lo) + __longlong_as_double((long long)hi)) / 2.0;
+    const double threshold = min_grad * median;
+    for (int j = threadIdx.x; j < J; j += blockDim.x) {
+        const bool keep = shifts[3 * (size_t)j + 2] >= threshold;
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            const double step = keep ? shifts[3 * (size_t)j + ax] : 0.0;
+            const double moved = pos[2 * (size_t)j + ax] + mult * step;
+            const double p0 = pos0[2 * (size_t)j + ax];
+            const double d = fmin(fmax(moved - p0, -max_shift), max_shift);
+            out[2 * (size_t)j + ax] = p0 + d;
+        }
+    }
+}
+
 // flag[0] = 1 if any of a[0 .. n) is not finite (flag cleared beforehand;
 // every writer stores the same value).
 __global__ __launch_bounds__(256) void k_check_finite(const float *a, long n, int *flag) {

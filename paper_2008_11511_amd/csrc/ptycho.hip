@@ -857,6 +857,20 @@ extern "C" int ptycho_position_shifts(ptycho_plan_t p, const float *obj, const f
     return PTYCHO_OK;
 }
 
+extern "C" int ptycho_update_positions(int32_t n_frames, const double *pos, const double *pos0, const double *shifts,
+                                       double mult, double max_shift, double min_grad, double *pos_out,
+                                       void *stream) {
+    if (n_frames < 1) return fail(PTYCHO_E_INVALID, "n_frames must be >= 1");
+    if (!pos || !pos0 || !shifts || !pos_out) return fail(PTYCHO_E_INVALID, "null pointer");
+    if (!std::isfinite(mult) || !std::isfinite(max_shift) || !(max_shift >= 0.0) || !std::isfinite(min_grad) ||
+        !(min_grad >= 0.0))
+        return fail(PTYCHO_E_INVALID, "mult, max_shift and min_grad must be finite, the last two >= 0");
+    hipLaunchKernelGGL(k_update_positions, dim3(1), dim3(POSUPD_THREADS), 0, (hipStream_t)stream, (int)n_frames, pos,
+                       pos0, shifts, mult, max_shift, min_grad, pos_out);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
 extern "C" int ptycho_check_finite(ptycho_plan_t p, const float *obj, const float *probe, int32_t *flag) {
     int st = check_plan_ptrs(p, obj, probe);
     if (st) return st;

@@ -39,28 +39,33 @@ def offsets_from_positions(pos_yx, n: int, obj_shape) -> np.ndarray:
     return out
 
 
-def update_positions(pos, pos0, shifts, energy, mult: float = 1.0, max_shift: float = 2.0,
-                     min_grad: float = 0.1) -> np.ndarray:
-    """Move scan positions (float [J][2], pixels) by mult * shift, except the
-    frames whose gradient energy is below min_grad times the median energy
-    (too little object contrast to tell a shift); the total move from the
-    starting positions pos0 is clipped to +-max_shift per axis."""
-    pos = np.asarray(pos, dtype=np.float64)
-    pos0 = np.asarray(pos0, dtype=np.float64)
-    energy = np.asarray(energy, dtype=np.float64)
-    keep = energy >= min_grad * np.median(energy)
-    new = pos + mult * np.where(keep[:, None], np.asarray(shifts, dtype=np.float64), 0.0)
-    return pos0 + np.clip(new - pos0, -max_shift, max_shift)
+def update_positions(pos: torch.Tensor, pos0: torch.Tensor, shifts: torch.Tensor, mult: float = 1.0,
+                     max_shift: float = 2.0, min_grad: float = 0.1, out: Optional[torch.Tensor] = None):
+    """New scan positions (float64 [J][2] device tensor, pixels) from the
+    shifts of `Plan.position_shifts` (float64 [J][3]), computed by the
+    library on the current stream: the low-contrast filter, the step and
+    the bound on the total move from pos0 (see ptycho_update_positions)."""
+    j = pos.shape[0]
+    for name, t, shape in (("pos", pos, (j, 2)), ("pos0", pos0, (j, 2)), ("shifts", shifts, (j, 3))):
+        _need(t, name, torch.float64, shape, pos.device)
+    out = torch.empty_like(pos) if out is None else out
+    _need(out, "out", torch.float64, (j, 2), pos.device)
+    check(lib().ptycho_update_positions(j, _ptr(pos), _ptr(pos0), _ptr(shifts), float(mult), float(max_shift),
+                                        float(min_grad), _ptr(out),
+                                        torch.cuda.current_stream(pos.device).cuda_stream))
+    return out
 
 
 def refine_positions(plan: "Plan", obj, probe, psi, pos, pos0, mult: float = 1.0, max_shift: float = 2.0,
                      min_grad: float = 0.1):
     """One position-refinement step after a cycle that left exit waves in psi:
-    shifts on the GPU, the position update on the host, and a plan rebuilt
+    the shifts and the position update in the library, then a plan rebuilt
     on the new offsets when any frame moved to another pixel.
     Returns (plan, new positions, new offsets)."""
-    res = plan.position_shifts(obj, probe, psi).cpu().numpy()
-    new = update_positions(pos, pos0, res[:, :2], res[:, 2], mult, max_shift, min_grad)
+    sh = plan.position_shifts(obj, probe, psi)
+    pos_d = torch.as_tensor(np.ascontiguousarray(pos, dtype=np.float64)).to(plan.device)
+    pos0_d = torch.as_tensor(np.ascontiguousarray(pos0, dtype=np.float64)).to(plan.device)
+    new = update_positions(pos_d, pos0_d, sh, mult, max_shift, min_grad).cpu().numpy()
     offs = offsets_from_positions(new, plan.n, plan.obj_shape)
     if not np.array_equal(offs, plan.offsets):
         plan = plan.rebuild(offs)

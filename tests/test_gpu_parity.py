@@ -477,6 +477,28 @@ def test_position_shifts_match_oracle(dev):
     np.testing.assert_allclose(got[:, 2], e_ref, rtol=1e-5)
 
 
+def test_position_update_matches_oracle_bitwise(dev):
+    """ptycho_update_positions against the oracle's update rule: odd and even
+    frame counts, tied energies, filtered frames, clipping on both sides."""
+    from paper_2008_11511_amd.plan import update_positions
+    rng = np.random.default_rng(8)
+    for j, mult, mx, mg in ((201, 1.0, 2.0, 0.1), (200, 0.5, 1.0, 0.5), (7, 2.0, 3.0, 0.0), (1, 1.0, 2.0, 0.1),
+                            (4096, 1.3, 0.75, 0.8)):
+        say(f"position update: {j} frames, mult {mult}, max_shift {mx}, min_grad {mg}")
+        pos0 = rng.uniform(-50, 50, (j, 2))
+        pos = pos0 + rng.uniform(-2.5, 2.5, (j, 2))
+        shifts = np.concatenate([rng.normal(0, 0.7, (j, 2)), rng.lognormal(0, 1.5, (j, 1))], axis=1)
+        shifts[: j // 4, 2] = shifts[0, 2]             # ties in the energies
+        want = oracle.update_positions(pos, pos0, shifts[:, :2], shifts[:, 2], mult, mx, mg)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        got = update_positions(t(pos), t(pos0), t(shifts), mult, mx, mg).cpu().numpy()
+        np.testing.assert_array_equal(got, want)
+        # in place
+        pos_d = t(pos)
+        update_positions(pos_d, t(pos0), t(shifts), mult, mx, mg, out=pos_d)
+        np.testing.assert_array_equal(pos_d.cpu().numpy(), want)
+
+
 def test_position_refinement_follows_oracle(dev):
     from paper_2008_11511_amd import Plan
     from paper_2008_11511_amd.plan import refine_positions
