@@ -319,6 +319,28 @@ PTYCHO_API int ptycho_ml_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_
                     void *state_dev, int32_t n_cycles, uint32_t update,
                     int32_t reset, double *llk_hist_dev);
 
+/* Allocation-free Poisson LLK, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * allocation): ptycho_llk of one far-field scan without a plan or a
+ * workspace.  Its scratch (frame tables, the stack of transformed frames,
+ * reduction partials) lives in a static device array of
+ * PTYCHO_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends; the call allocates nothing.  desc: as for ptycho_plan,
+ * flags must be 0 (PTYCHO_E_INVALID otherwise); desc->stack is ignored, the
+ * stack is as many frames as fit the scratch; a problem whose frame
+ * (K*N*N complex) or tables do not fit is PTYCHO_E_WORKSPACE.
+ * offsets_dev: int32[J][2] device, top-left window corners; a window
+ * outside the object is clamped to it and llk_dev[0] receives NaN.
+ * iobs_dev, mask_dev (NULL = none), obj_dev, probe_dev: as for ptycho_plan
+ * and ptycho_llk.  llk_dev: double[2] device, { LLK sum, unmasked pixels }.
+ * Enqueued on `stream` (hipStream_t).  Every call on one GPU shares that
+ * GPU's scratch: calls that overlap on one GPU (different streams, or
+ * threads) race and must be serialised by the caller. */
+#define PTYCHO_NOALLOC_SCRATCH_BYTES (64u << 20)
+PTYCHO_API int ptycho_llk_noalloc(const ptycho_desc_t *desc, const int32_t *offsets_dev, const float *iobs_dev,
+                                  const uint8_t *mask_dev, const float *obj_dev, const float *probe_dev,
+                                  double *llk_dev, void *stream);
+
 /* Calculated intensity sum_k |FT(O_j P_k)|^2 of every frame into
  * icalc_dev (float[J][N][N], FFT order); the forward model used to simulate
  * data. */

@@ -61,6 +61,7 @@ _SIGS = {
     "ptycho_ml_linesearch": [_P, _P, _P, _P, _P, _P],
     "ptycho_ml_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "ptycho_ml_cycle": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, _P],
+    "ptycho_llk_noalloc": [ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, _P],
     "ptycho_icalc": [_P, _P, _P, _P],
     "ptycho_fft2": [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32, _P],
     "ptycho_plan_timing": [_P, ctypes.c_int32],

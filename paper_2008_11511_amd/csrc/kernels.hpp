@@ -160,6 +160,26 @@ __global__ __launch_bounds__(POSUPD_THREADS) void k_update_positions(int J, cons
     }
 }
 
+// Frame tables of a plan-free call: offs[j] = the caller's offsets clamped
+// to the object (flag[0] = 1 if any window was outside it), order[j] = j.
+__global__ __launch_bounds__(256) void k_frame_tables(const int *offsets, int J, int n, int ny, int nx, int2 *offs,
+                                                      int *order, int *flag) {
+    bool bad = false;
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < J; j += gridDim.x * 256) {
+        const int oy = offsets[2 * j], ox = offsets[2 * j + 1];
+        const int cy = min(max(oy, 0), ny - n), cx = min(max(ox, 0), nx - n);
+        bad |= (cy != oy) || (cx != ox);
+        offs[j] = make_int2(cy, cx);
+        order[j] = j;
+    }
+    if (bad) flag[0] = 1;
+}
+
+// dst[0] = NaN when flag[0] is set.
+__global__ void k_nan_if_flagged(double *dst, const int *flag) {
+    if (flag[0] != 0) dst[0] = __longlong_as_double(0x7ff8000000000000ll);
+}
+
 // flag[0] = 1 if any of a[0 .. n) is not finite (flag cleared beforehand;
 // every writer stores the same value).
 __global__ __launch_bounds__(256) void k_check_finite(const float *a, long n, int *flag) {

@@ -1005,6 +1005,121 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
     return PTYCHO_OK;
 }
 
+// ------------------------------------------------- allocation-free LLK ---
+// Scratch of ptycho_llk_noalloc: one static device array per GPU (held until
+// the process ends), reached from host code through the address that
+// hipGetSymbolAddress returns on that device, never through its name.
+namespace {
+__device__ __align__(256) unsigned char scratch[PTYCHO_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // per device, null until looked up
+}  // namespace
+
+static int scratch_for_current_device(char **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(PTYCHO_E_HIP, "no device address for the static scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (char *)g_scratch_ptr[dev];
+    return PTYCHO_OK;
+}
+
+// Layout of the static scratch for one call: flag and count, the frame
+// tables, the reduction partials, then as many frames of stack scratch as
+// fit.  S = 0 when not even one frame fits.
+struct NoAllocLayout {
+    int S, nstacks, maxb;
+    size_t nred, off_flag, off_count, off_offs, off_order, off_red, off_scr, total;
+};
+static NoAllocLayout noalloc_layout(const ptycho_desc_t &d) {
+    NoAllocLayout L{};
+    const size_t J = (size_t)d.n_frames, N = (size_t)d.n, K = (size_t)d.n_modes;
+    const size_t frame = sizeof(float2) * K * N * N;
+    const int cb = col_cb(d.n);
+    size_t o = 0;
+    L.off_flag = o; o = up(o + sizeof(int));
+    L.off_count = o; o = up(o + sizeof(double));
+    L.off_offs = o; o = up(o + sizeof(int2) * J);
+    L.off_order = o; o = up(o + sizeof(int) * J);
+    // partials: one per column block of every stack; bounded by the
+    // all-frames count, sized after S is known
+    const size_t fixed = o;
+    const size_t per_frame = frame + sizeof(double) * (N + cb - 1) / cb + sizeof(double);
+    int S = 0;
+    if (PTYCHO_NOALLOC_SCRATCH_BYTES > fixed + 2 * ALIGN)
+        S = (int)std::min<size_t>(J, (PTYCHO_NOALLOC_SCRATCH_BYTES - fixed - 2 * ALIGN) / per_frame);
+    L.S = S;
+    if (S < 1) { L.total = SIZE_MAX; return L; }
+    L.nstacks = (int)((J + S - 1) / S);
+    L.maxb = (int)(((long)S * d.n + cb - 1) / cb);
+    L.nred = (size_t)L.nstacks * L.maxb;
+    L.off_red = o; o = up(o + sizeof(double) * L.nred);
+    L.off_scr = o; o = up(o + frame * (size_t)S);
+    L.total = o;
+    return L;
+}
+
+extern "C" int ptycho_llk_noalloc(const ptycho_desc_t *d, const int32_t *offsets, const float *iobs,
+                                  const uint8_t *mask, const float *obj, const float *probe, double *llk,
+                                  void *stream) {
+    int st = check_desc(d);
+    if (st) return st;
+    if (!offsets || !iobs || !obj || !probe || !llk) return fail(PTYCHO_E_INVALID, "null pointer");
+    if (d->flags != 0) return fail(PTYCHO_E_INVALID, "the allocation-free LLK takes a far-field descriptor without flags");
+    const NoAllocLayout L = noalloc_layout(*d);
+    if (L.S < 1 || L.total > PTYCHO_NOALLOC_SCRATCH_BYTES)
+        return fail(PTYCHO_E_WORKSPACE, "problem exceeds the allocation-free scratch (" +
+                                             std::to_string(PTYCHO_NOALLOC_SCRATCH_BYTES >> 20) + " MiB)");
+    const NPass *np = passes_for(d->n);
+    if (!np) return PTYCHO_E_UNSUPPORTED;
+    st = ensure_twiddles();
+    if (st) return st;
+    char *base = nullptr;
+    st = scratch_for_current_device(&base);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // a plan on the stack whose tables and scratch are carved from the
+    // static array; the forward pass is the plan path's own
+    ptycho_plan_s p{};
+    p.d = *d;
+    p.L.S = L.S;
+    p.L.nstacks = L.nstacks;
+    p.L.maxb = L.maxb;
+    p.L.nred = L.nred;
+    p.stream = s;
+    p.iobs = iobs;
+    p.mask = mask;
+    p.offs = (int2 *)(base + L.off_offs);
+    p.order = (int *)(base + L.off_order);
+    p.scr = (float2 *)(base + L.off_scr);
+    p.red = (double *)(base + L.off_red);
+    int *flag = (int *)(base + L.off_flag);
+    double *count = (double *)(base + L.off_count);
+    const int J = d->n_frames;
+    // every word the call reads is written first: the flag and partials are
+    // cleared by fill kernels, the tables and count are written whole
+    st = zero_async(flag, ALIGN, s);
+    if (!st) st = zero_async(p.red, up(sizeof(double) * L.nred), s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_frame_tables, dim3(grid_for(J)), dim3(256), 0, s, (const int *)offsets, J, d->n, d->obj_ny,
+                       d->obj_nx, p.offs, p.order, flag);
+    hipLaunchKernelGGL(k_count_good, dim3(1), dim3(256), 0, s, mask, d->n * d->n, (double)J, count);
+    LAUNCHCHK();
+    st = np->forward(&p, OP_LLK, obj, probe, nullptr, nullptr, nullptr, LLK_POISSON);
+    if (st) return st;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, p.red, (long)L.nred, 1, llk, 0);
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, llk + 1, count);
+    hipLaunchKernelGGL(k_nan_if_flagged, dim3(1), dim3(1), 0, s, llk, flag);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
 // ------------------------------------------------------------ plain FFT ---
 extern "C" int ptycho_fft2(int32_t n, int32_t count, float *data, int32_t dir, void *stream) {
     if (!supported_n(n)) return fail(PTYCHO_E_UNSUPPORTED, "unsupported frame size");
