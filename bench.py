@@ -105,6 +105,28 @@ def algorithmic_bytes(wl, nstacks, kind):
     return out
 
 
+def design_bytes(wl, alg):
+    """Bytes per cycle of the reference two-pass design that every cycle is
+    priced against (each kernel reads its inputs and writes its outputs once,
+    the probe cache-resident): per frame, with U = 8 N^2 and W = 4 N^2,
+    N >= 256: AP 8KU + 2U + W, DM 10KU + 3U + W, ML (gradient and line
+    search) 13KU + 4U + 2W; N <= 128: AP 3KU + 2U + W, DM 4KU + 2U + W,
+    ML 3KU + 4U + 2W."""
+    K, N = wl.n_modes, wl.n
+    U, W = 8 * N * N, 4 * N * N
+    if N >= 256:
+        per = {"ap": 8 * K * U + 2 * U + W, "dm": 10 * K * U + 3 * U + W, "ml": 13 * K * U + 4 * U + 2 * W}[alg]
+    else:
+        per = {"ap": 3 * K * U + 2 * U + W, "dm": 4 * K * U + 2 * U + W, "ml": 3 * K * U + 4 * U + 2 * W}[alg]
+    return wl.n_frames * per
+
+
+def design_roofline(wl, alg, ms_per_cycle):
+    b = design_bytes(wl, alg)
+    gbs = b / (ms_per_cycle * 1e-3) / 1e9
+    return {"design_bytes_per_cycle": b, "design_GBs": round(gbs, 1), "design_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def timed_dm(plan, o, p, psi, steps, warmup, torch, classes=None):
     """Time `steps` DM cycles after `warmup` ones, with HIP events around the
     launches of the given kernel classes (None = all)."""
@@ -139,9 +161,243 @@ def cpu_baseline(wl, truth, sample, cycles):
     return sample * cycles / dt, dt
 
 
-def traffic_for(kernel, launches_per_cycle):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def _cpu_worker(args):
+    """One host process of the all-cores baseline: the oracle's DM cycles on
+    its share of the scan, timed after every worker has finished its set-up."""
+    wl_name, obj_t, probe_t, pos_s, m, cycles, barrier = args
+    import oracle
+    import synth
+    wl = synth.workload(wl_name)
+    offs = oracle.offsets_from_positions(pos_s, wl.n, wl.obj_shape)
+    iobs = synth.poisson_counts(oracle.simulate_intensity(obj_t, probe_t, offs), wl.seed)
+    o0 = synth.start_object(wl.obj_shape)
+    p0 = synth.start_probe(probe_t)
+    psi = oracle.psi_init(o0, p0, offs)
+    barrier.wait()
+    t0 = time.monotonic()
+    for _ in range(cycles):
+        o0, p0, psi = oracle.dm_cycle(o0, p0, psi, offs, iobs, m)
+    return t0, time.monotonic()
+
+
+def cpu_baseline_all_cores(wl, truth, sample, cycles, workers):
+    """The FP64 oracle on `workers` host processes at once, each running
+    `cycles` DM cycles on its own share of the first `sample` frames (the
+    oracle is not parallel itself; independent pieces of the scan are).
+    Returns (aggregate frames*cycles/s, wall seconds of the timed region)."""
+    import multiprocessing as mp
+    obj_t, probe_t, pos, m = truth
+    per = max(1, sample // workers)
+    ctx = mp.get_context("spawn")
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        with ctx.Manager() as mgr:
+            barrier = mgr.Barrier(workers)
+            jobs = [(wl.name, obj_t, probe_t, pos[w * per:(w + 1) * per], m, cycles, barrier) for w in range(workers)]
+            with ctx.Pool(workers) as pool:
+                res = pool.map(_cpu_worker, jobs)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    t0 = min(r[0] for r in res)
+    t1 = max(r[1] for r in res)
+    return workers * per * cycles / (t1 - t0), t1 - t0
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (python bench.py --summarize-rocprof TRACE FETCH WRITE)
+# ---------------------------------------------------------------------------
+# Kernel classes of each profiled cycle.  A cycle's dispatch window runs from
+# the first to the last launch of its anchors (template instances only that
+# cycle uses); every class takes the launches of its kernel inside the window
+# at their most frequent grid (the cycle's full-size launches).
+PROFILE_SPECS = {
+    "dm256_dm_cycle": {
+        "title": "DM cycle, 1000 frames 256x256, 3 modes (dm256)",
+        "anchors": ["void ptycho::k_cols_joint<256, 3, 5, false>", "void ptycho::k_rows_inv<256, 3, 1, true, false>"],
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<256, 1, false>",
+                    "cols": "void ptycho::k_cols_joint<256, 3, 5, false>",
+                    "rows_inv": "void ptycho::k_rows_inv<256, 3, 1, true, false>",
+                    "gather_obj": "ptycho::k_gather_obj(",
+                    "probe_all": "void ptycho::k_gather_probe<3, false>"}},
+    "ml256_ml_cycle": {
+        "title": "conjugate-gradient ML cycle, 500 frames 256x256, 3 modes (ml256)",
+        "anchors": ["void ptycho::k_cols_joint<256, 3, 1, false>", "void ptycho::k_cols_seq<256, 6, false>"],
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<256, 0, false>",
+                    "cols": "void ptycho::k_cols_joint<256, 3, 1, false>",
+                    "rows_inv": "void ptycho::k_rows_inv<256, 3, 0, true, false>",
+                    "gather_obj": "ptycho::k_gather_obj(",
+                    "gather_probe": "void ptycho::k_gather_probe<3, true>",
+                    "ls_rows": "void ptycho::k_rows_fwd<256, 4, false>",
+                    "ls_cols": "void ptycho::k_cols_seq<256, 6, false>"}},
+    "apdm512_dm_cycle": {
+        "title": "AP and DM cycles, 4000 frames 512x512, 4 modes, object 4096x4096 (apdm512)",
+        "anchors": ["void ptycho::k_cols_joint<512, 4, 5, false>", "void ptycho::k_cols_joint<512, 4, 0, false>"],
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<512, 1, false>",
+                    "cols": "void ptycho::k_cols_joint<512, 4, 5, false>",
+                    "rows_inv": "void ptycho::k_rows_inv<512, 4, 1, true, false>",
+                    "ap_cols": "void ptycho::k_cols_joint<512, 4, 0, false>",
+                    "ap_rows_inv": "void ptycho::k_rows_inv<512, 4, 2, true, false>",
+                    "gather_obj": "ptycho::k_gather_obj(",
+                    "probe_all": "void ptycho::k_gather_probe<4, false>"}},
+    "nf2048_dm_cycle": {
+        "title": "near-field DM cycle, 17 frames 2048x2048, 1 mode (nf2048)",
+        "anchors": ["void ptycho::k_cols_joint<2048, 1, 5, true>", "void ptycho::k_rows_inv<2048, 1, 1, true, true>"],
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<2048, 1, true>",
+                    "cols": "void ptycho::k_cols_joint<2048, 1, 5, true>",
+                    "rows_inv": "void ptycho::k_rows_inv<2048, 1, 1, true, true>",
+                    "gather_obj": "ptycho::k_gather_obj(",
+                    "probe_all": "void ptycho::k_gather_probe<1, false>"}},
+}
+
+
+def _read_csv(directory, suffix):
+    import csv
+    files = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {directory}")
+    with open(files[0], newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name):
+    """Kernel name without its return type and argument list."""
+    n = name[5:] if name.startswith("void ") else name
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and not n.startswith("(anonymous", i):
+            return n[:i]
+    return n
+
+
+def _dispatches(rows, counter=None):
+    """[(dispatch id, kernel name, grid threads, value)] in dispatch order; value
+    is the duration in ns (trace) or the counter's value (counter runs)."""
+    out = []
+    for r in rows:
+        if counter is None:
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], grid,
+                        float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))))
+        elif r["Counter_Name"] == counter:
+            out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def _select(disp, spec):
+    """Values of each class's full-size launches inside the cycle's window."""
+    def named(d, k):
+        return d[1].startswith(k + "(") if k.startswith("void ") else d[1].startswith(k)
+    ids = [d[0] for d in disp if any(named(d, k) for k in spec["anchors"])]
+    if not ids:
+        return {}
+    lo, hi = min(ids), max(ids)
+    out = {}
+    for c, k in spec["classes"].items():
+        win = [d for d in disp if named(d, k) and lo <= d[0] <= hi]
+        if not win:
+            continue
+        grids = {}
+        for d in win:
+            grids[d[2]] = grids.get(d[2], 0) + 1
+        g = max(grids, key=lambda x: (grids[x], x))
+        sel = [d for d in win if d[2] == g]
+        out[c] = (g, [d[3] for d in sel], sel[0][1])
+    return out
+
+
+def summarize_rocprof(trace_dir, fetch_dir, write_dir, command, out_dir=None):
+    """Per-kernel-class summaries of one profiled bench run: average launch
+    duration from the kernel trace, HBM bytes per launch from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for
+    the run's 1 GiB device copy.  Writes profiles/<name>.md for every cycle of
+    PROFILE_SPECS found in the run, and profiles/traffic.json."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    trace = _dispatches(_read_csv(trace_dir, "_kernel_trace.csv"))
+    fetch = _dispatches(_read_csv(fetch_dir, "_counter_collection.csv"), "FETCH_SIZE")
+    write = _dispatches(_read_csv(write_dir, "_counter_collection.csv"), "WRITE_SIZE")
+    stats = _read_csv(trace_dir, "_kernel_stats.csv")
+    # calibration: the copy dispatch that wrote the most bytes (the 1 GiB copy)
+    gib = float(1 << 30)
+    copies_w = [d for d in write if "copyBuffer" in d[1]]
+    copies_f = [d for d in fetch if "copyBuffer" in d[1]]
+    if not copies_w or not copies_f:
+        raise ValueError("the run holds no device copy to calibrate the counters (bench.py --calib-copy)")
+    w_cal = max(d[3] for d in copies_w)
+    big_grid = max(copies_w, key=lambda d: d[3])[2]
+    f_cal = max(d[3] for d in copies_f if d[2] == big_grid)
+    write_scale = gib / (w_cal * 1024.0)
+    fetch_scale = gib / (f_cal * 1024.0)
+    sha = source_sha()
+    traffic = {"source_sha": sha, "fetch_scale": fetch_scale, "write_scale": write_scale, "command": command,
+               "cycles": {}}
+    written = []
+    for name, spec in PROFILE_SPECS.items():
+        t_sel = _select(trace, spec)
+        if not t_sel:
+            continue
+        f_sel = _select(fetch, spec)
+        w_sel = _select(write, spec)
+        rows = {}
+        for c, (grid, durs, kname) in t_sel.items():
+            e = {"kernel": _short(kname), "grid": grid, "launches": len(durs),
+                 "avg_us": sum(durs) / len(durs) / 1e3}
+            if c in f_sel and c in w_sel and f_sel[c][0] == grid and w_sel[c][0] == grid:
+                rd = sum(f_sel[c][1]) / len(f_sel[c][1]) * 1024.0 * fetch_scale
+                wr = sum(w_sel[c][1]) / len(w_sel[c][1]) * 1024.0 * write_scale
+                e.update({"read_bytes": rd, "write_bytes": wr, "bytes_per_launch": rd + wr,
+                          "GBs": (rd + wr) / (e["avg_us"] * 1e-6) / 1e9})
+            rows[c] = e
+        traffic["cycles"][name] = rows
+        lines = [f"# {name}: rocprofv3 summary", "", spec["title"] + ".", "",
+                 "Command (run from /tmp with TMPDIR=/tmp on one MI355X; $R is the repository root; the same "
+                 "program once with `--kernel-trace --stats`, once with `--pmc FETCH_SIZE`, once with "
+                 "`--pmc WRITE_SIZE`), summarised by `python bench.py --summarize-rocprof TRACE FETCH WRITE`:", "",
+                 "    " + command, "",
+                 f"Counter calibration: the run's 1 GiB device-to-device copy reads FETCH_SIZE = {f_cal:.0f} KiB "
+                 f"and WRITE_SIZE = {w_cal:.0f} KiB, so HBM read bytes = FETCH_SIZE x 1024 x {fetch_scale:.3f} and "
+                 f"write bytes = WRITE_SIZE x 1024 x {write_scale:.3f}.", "",
+                 f"Kernel sources sha256[:16] = {sha}", "",
+                 "## Full-size launches of the cycle: measured traffic per launch", "",
+                 "| class | kernel | grid (threads) | launches | avg us | read MB | write MB | GB/s (counted) |",
+                 "|---|---|---|---|---|---|---|---|"]
+        for c, e in rows.items():
+            if "read_bytes" in e:
+                lines.append(f"| {c} | `{e['kernel']}` | {e['grid']} | {e['launches']} | {e['avg_us']:.2f} | "
+                             f"{e['read_bytes'] / 1e6:.1f} | {e['write_bytes'] / 1e6:.1f} | {e['GBs']:.0f} |")
+            else:
+                lines.append(f"| {c} | `{e['kernel']}` | {e['grid']} | {e['launches']} | {e['avg_us']:.2f} | "
+                             f"- | - | - |")
+        lines += ["", "## Kernel stats of the whole run (top 12 by total time)", "",
+                  "| kernel | calls | avg us | total % |", "|---|---|---|---|"]
+        for r in sorted(stats, key=lambda r: -float(r["Percentage"]))[:12]:
+            kn = _short(r["Name"])
+            if len(kn) > 70:
+                kn = kn[:67] + "..."
+            lines.append(f"| `{kn}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                         f"{float(r['Percentage']):.2f} |")
+        with open(os.path.join(out_dir, f"{name}.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        written.append(name)
+    with open(os.path.join(out_dir, "traffic.json"), "w") as f:
+        json.dump(traffic, f, indent=1)
+    return written
+
+
+def traffic_for(cls, cycle="dm256_dm_cycle"):
+    """HBM bytes per launch of kernel class `cls` of a profiled cycle from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -150,8 +406,8 @@ def traffic_for(kernel, launches_per_cycle):
             t = json.load(f)
         if t.get("source_sha") != source_sha():
             return None
-        e = t["kernels"].get(kernel)
-        return None if e is None else e["bytes_per_launch"]
+        e = t["cycles"].get(cycle, {}).get(cls)
+        return None if e is None or "bytes_per_launch" not in e else e["bytes_per_launch"]
     except Exception:
         return None
 
@@ -165,6 +421,8 @@ def main():
     ap.add_argument("--stack", type=int, default=0, help="frames per launch (0 = the library's choice)")
     ap.add_argument("--cpu-sample", type=int, default=1000, help="frames of the oracle CPU baseline sample")
     ap.add_argument("--cpu-cycles", type=int, default=2, help="DM cycles of the oracle CPU baseline sample")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="host processes of the all-cores oracle baseline (at most the CPUs available; 1 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ml", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
@@ -181,7 +439,16 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/*.md and profiles/traffic.json from the rocprofv3 output of one bench run "
+                         "(kernel trace, FETCH_SIZE, WRITE_SIZE) and exit; no GPU needed")
+    ap.add_argument("--profile-command", default="(not given)",
+                    help="the profiled command, recorded in the summaries")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        done = summarize_rocprof(*args.summarize_rocprof, command=args.profile_command)
+        print(json.dumps({"profiles": done}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part of "
               f"this build", file=sys.stderr)
@@ -299,11 +566,12 @@ def main():
     achieved = dk["alg_GBs"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(dom, nstacks),
+                "traffic": traffic_for(dom),
                 "alg_bytes_per_launch": dk["alg_bytes_per_launch"], "avg_launch_us": round(dk["avg_us"], 2)}
     cycle_alg = sum(algo.values())
     whole = {"alg_bytes_per_cycle": cycle_alg, "alg_GBs": cycle_alg / (dt / args.steps) / 1e9}
     whole["frac"] = whole["alg_GBs"] / HBM_PEAK_GBS
+    whole.update(design_roofline(wl, "dm", dt / args.steps * 1e3))
 
     ml = None
     if not args.no_ml:
@@ -332,6 +600,7 @@ def main():
               "frames_cycles_per_s": round(wl2.n_frames * args.ml_steps / dt2, 1),
               "llk_first": float(h[0]), "llk_last": float(h[-1]),
               "kernels_ms_per_cycle": {k: round(ms / args.ml_steps, 4) for k, (ms, n) in per2.items() if n}}
+        ml.update(design_roofline(wl2, "ml", dt2 / args.ml_steps * 1e3))
         log(f"ML: {ml['ms_per_cycle']} ms/cycle, {ml['frames_cycles_per_s']} frames*cycles/s")
         del plan2, st
 
@@ -378,6 +647,10 @@ def main():
                  "dm_ms_per_cycle": round(t_dm / max(n_dm, 1) * 1e3, 2) if n_dm else None,
                  "dm_frames_cycles_per_s": round(wl3.n_frames * n_dm / t_dm, 1) if n_dm else None,
                  "stack": plan3.stack, "kernels": k3}
+        if n_ap:
+            large["ap_design"] = design_roofline(wl3, "ap", t_ap / n_ap * 1e3)
+        if n_dm:
+            large["dm_design"] = design_roofline(wl3, "dm", t_dm / n_dm * 1e3)
         log(f"large: AP {large['ap_ms_per_cycle']} ms/cycle, DM {large['dm_ms_per_cycle']} ms/cycle")
         del plan3, psi3, iobs3, o3, p3
         torch.cuda.empty_cache()
@@ -474,12 +747,20 @@ def main():
     if not args.no_cpu_baseline:
         log(f"CPU baseline: FP64 oracle, {args.cpu_cycles} DM cycles over {args.cpu_sample} frames")
         fcs, t = cpu_baseline(wl, truth, args.cpu_sample, args.cpu_cycles)
-        cores = 1
-        cpu = {"value": round(fcs, 3), "unit": "frames*cycles/s", "cores": cores, "kind": "oracle",
+        cpu = {"value": round(fcs, 3), "unit": "frames*cycles/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_cycles} DM cycles over the first {args.cpu_sample} of {wl.n_frames} frames "
                          f"of the same scan (256x256, 3 modes), {t:.1f} s timed; numpy FFT single-threaded",
                "host_cpus": len(os.sched_getaffinity(0))}
         log(f"CPU oracle: {fcs:.2f} frames*cycles/s ({t:.1f} s)")
+        workers = min(args.cpu_workers, len(os.sched_getaffinity(0)))
+        if workers > 1:
+            log(f"CPU baseline, all cores: {workers} oracle processes, {args.cpu_cycles} DM cycles each")
+            fcs_all, t_all = cpu_baseline_all_cores(wl, truth, args.cpu_sample, args.cpu_cycles, workers)
+            cpu["all_cores"] = {"value": round(fcs_all, 3), "unit": "frames*cycles/s", "cores": workers,
+                                "sample": f"{workers} processes, each {args.cpu_cycles} DM cycles on its own "
+                                          f"{args.cpu_sample // workers} of the first {args.cpu_sample} frames, "
+                                          f"{t_all:.1f} s timed"}
+            log(f"CPU oracle, {workers} cores: {fcs_all:.2f} frames*cycles/s ({t_all:.1f} s)")
 
     out = {
         "metric": "frames*cycles/s (256^2 frames, 3 modes) & %HBM roofline",

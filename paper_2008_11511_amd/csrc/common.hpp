@@ -151,6 +151,9 @@ struct StackArgs {
     const float2 *psi;           // DM state read  [J][K][N][N]
     float2 *psi_out;             // DM state write [J][K][N][N]
     float2 *scr;                 // stack scratch [S][sets*K][N][N] (column tiles)
+    float2 *fwd;                 // where the forward row pass writes (the scratch, or
+                                 // the kept row transforms of the ML cycle), [S][K][N][N]
+    const float2 *colin;         // where the column pass reads its first set, [S][K][N][N]
     float2 *qbuf;                // per slot sum_k conj(P_k) Psi_k, [S][N][N] row-major
     const float *iobs;           // [J][N][N]
     const float *bg;             // incoherent background [N][N] or null
@@ -233,8 +236,8 @@ __device__ __forceinline__ float llk_model_term(int model, float inten, float io
 }
 
 // Operation selectors of the stack kernels (also used by the host).
-enum RowIn { IN_PHI = 0, IN_DM = 1, IN_LS = 2, IN_DATA = 3 };
+enum RowIn { IN_PHI = 0, IN_DM = 1, IN_LS = 2, IN_DATA = 3, IN_LS2 = 4 };
 enum RowOut { OUT_SCR = 0, OUT_DM = 1, OUT_STORE = 2, OUT_NONE = 3 };
-enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4, OP_CORR = 5 };
+enum ColOp { OP_PROJECT = 0, OP_GRAD = 1, OP_LLK = 2, OP_ICALC = 3, OP_LS = 4, OP_CORR = 5, OP_LS2 = 6 };
 
 }  // namespace ptycho

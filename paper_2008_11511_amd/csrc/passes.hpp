@@ -58,7 +58,7 @@ static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
 // exit waves from the scratch).
 template <int N, int K, bool NF>
 static int project_pass_nk(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind,
-                           unsigned acc, bool upd_bg) {
+                           unsigned acc, bool upd_bg, float2 *keep) {
     const int J = p->d.n_frames, S = p->L.S;
     hipStream_t s = p->stream;
     const bool store = (psi != nullptr);
@@ -75,6 +75,8 @@ static int project_pass_nk(ptycho_plan_s *p, const float *obj, const float *prob
         a.psi_out = (float2 *)psi;
         a.red = p->red + (size_t)sidx * p->L.maxb;
         if (upd_bg) a.s2 = p->s2;
+        if (keep) a.fwd = keep + (size_t)s0 * K * N * N;
+        a.colin = a.fwd;
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
@@ -110,11 +112,11 @@ static int project_pass_nk(ptycho_plan_s *p, const float *obj, const float *prob
 
 template <int N>
 static int project_pass_n(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind,
-                          unsigned acc, bool upd_bg) {
+                          unsigned acc, bool upd_bg, float2 *keep) {
     return with_k(p->d.n_modes, [&](auto kk) {
         return with_nf(p, [&](auto nf) {
             return project_pass_nk<N, decltype(kk)::value, decltype(nf)::value>(p, obj, probe, psi, kind, acc,
-                                                                                  upd_bg);
+                                                                                  upd_bg, keep);
         });
     });
 }
@@ -122,11 +124,13 @@ static int project_pass_n(ptycho_plan_s *p, const float *obj, const float *probe
 // Read-only forward passes: LLK, icalc, line search.
 template <int N, int OP, bool NF>
 static int forward_pass_op(ptycho_plan_s *p, const float *obj, const float *probe, const float *dobj,
-                           const float *dprobe, float *icalc, int llk_model) {
-    const bool ls = (OP == OP_LS);
-    const int J = p->d.n_frames, S = ls ? p->L.S_ls : p->L.S;
-    const int nst = ls ? p->L.nstacks_ls : p->L.nstacks;
-    const int maxb = ls ? p->L.maxb_ls : p->L.maxb;
+                           const float *dprobe, float *icalc, int llk_model, const float2 *keep) {
+    const bool ls = (OP == OP_LS || OP == OP_LS2);
+    const Layout &Lp = p->L;
+    const int J = p->d.n_frames;
+    const int S = (OP == OP_LS2) ? Lp.S_ls2 : ls ? Lp.S_ls : Lp.S;
+    const int nst = (OP == OP_LS2) ? Lp.nstacks_ls2 : ls ? Lp.nstacks_ls : Lp.nstacks;
+    const int maxb = (OP == OP_LS2) ? Lp.maxb_ls2 : ls ? Lp.maxb_ls : Lp.maxb;
     hipStream_t s = p->stream;
     for (int sidx = 0; sidx < nst; ++sidx) {
         const int s0 = sidx * S, sn = std::min(S, J - s0);
@@ -136,10 +140,12 @@ static int forward_pass_op(ptycho_plan_s *p, const float *obj, const float *prob
         a.icalc = icalc;
         a.llk_model = llk_model;
         a.red = p->red + (size_t)sidx * maxb * (ls ? 2 : 1);
+        if (OP == OP_LS2) a.colin = keep + (size_t)s0 * p->d.n_modes * N * N;
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
-            if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS, NF>), rg, dim3(256), 0, s, a);
+            if (OP == OP_LS2) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS2, NF>), rg, dim3(256), 0, s, a);
+            else if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS, NF>), rg, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI, NF>), rg, dim3(256), 0, s, a);
         }
         {
@@ -153,13 +159,14 @@ static int forward_pass_op(ptycho_plan_s *p, const float *obj, const float *prob
 
 template <int N>
 static int forward_pass_n(ptycho_plan_s *p, int op, const float *obj, const float *probe, const float *dobj,
-                          const float *dprobe, float *icalc, int llk_model) {
+                          const float *dprobe, float *icalc, int llk_model, const float2 *keep) {
     return with_nf(p, [&](auto nf) {
         constexpr bool NF = decltype(nf)::value;
         switch (op) {
-            case OP_LLK: return forward_pass_op<N, OP_LLK, NF>(p, obj, probe, dobj, dprobe, icalc, llk_model);
-            case OP_ICALC: return forward_pass_op<N, OP_ICALC, NF>(p, obj, probe, dobj, dprobe, icalc, llk_model);
-            case OP_LS: return forward_pass_op<N, OP_LS, NF>(p, obj, probe, dobj, dprobe, icalc, llk_model);
+            case OP_LLK: return forward_pass_op<N, OP_LLK, NF>(p, obj, probe, dobj, dprobe, icalc, llk_model, keep);
+            case OP_ICALC: return forward_pass_op<N, OP_ICALC, NF>(p, obj, probe, dobj, dprobe, icalc, llk_model, keep);
+            case OP_LS: return forward_pass_op<N, OP_LS, NF>(p, obj, probe, dobj, dprobe, icalc, llk_model, keep);
+            case OP_LS2: return forward_pass_op<N, OP_LS2, NF>(p, obj, probe, dobj, dprobe, icalc, llk_model, keep);
             default: return fail(PTYCHO_E_INVALID, "internal: unknown forward op");
         }
     });

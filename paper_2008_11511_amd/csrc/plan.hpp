@@ -49,6 +49,7 @@ inline int grid_for(long n) { return (int)std::max(1L, std::min((n + 255) / 256,
 
 struct Layout {
     int S, nstacks, S_ls, nstacks_ls, maxb, maxb_ls, pchunks;
+    int S_ls2, nstacks_ls2, maxb_ls2;   // line search with kept A (two sets per slot)
     size_t nlist_ints, npslots;   // object-gather block/reduce lists, partial slots
     size_t nent_max, nfr_max, nred;
     size_t off_offs, off_order, off_lists, off_ent_fr, off_opart, off_scr, off_q, off_pint, off_numO, off_denO,
@@ -158,11 +159,15 @@ struct NPass {
     int n;
     // One pass over all stacks (kind: 0 AP projection, 1 DM, 2 ML gradient)
     // with the per-stack sums selected by acc.
+    // keep (nullable): [J][K][N][N] column-tiled buffer that receives the
+    // forward row transforms of every frame (slot order), read by the column
+    // pass from there; the ML cycle's line search reuses them.
     int (*project)(ptycho_plan_s *p, const float *obj, const float *probe, float *psi, int kind, unsigned acc,
-                   bool upd_bg);
-    // Read-only forward pass of column op `op` (OP_LLK, OP_ICALC, OP_LS).
+                   bool upd_bg, float2 *keep);
+    // Read-only forward pass of column op `op` (OP_LLK, OP_ICALC, OP_LS, and
+    // OP_LS2: the line search with A read from `keep`).
     int (*forward)(ptycho_plan_s *p, int op, const float *obj, const float *probe, const float *dobj,
-                   const float *dprobe, float *icalc, int llk_model);
+                   const float *dprobe, float *icalc, int llk_model, const float2 *keep);
     // Plain batched unitary 2D FFT.
     int (*fft2)(int32_t count, float *data, int32_t dir, hipStream_t s);
     // Copies the twiddle table into this translation unit's constant memory

@@ -126,9 +126,13 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.nstacks = (J + L.S - 1) / L.S;
     L.S_ls = std::max(1, L.S / 3);
     L.nstacks_ls = (J + L.S_ls - 1) / L.S_ls;
+    // the scratch holds max(S, 3 S_ls) frame-modes per mode; two sets per slot
+    L.S_ls2 = std::max(1, std::min(J, std::max(L.S, 3 * L.S_ls) / 2));
+    L.nstacks_ls2 = (J + L.S_ls2 - 1) / L.S_ls2;
     const int cb = col_cb(N);
     L.maxb = (int)(((long)L.S * N + cb - 1) / cb);
     L.maxb_ls = (int)(((long)L.S_ls * N + cb - 1) / cb);
+    L.maxb_ls2 = (int)(((long)L.S_ls2 * N + cb - 1) / cb);
     const long ty = (N + OTILE_Y - 1) / OTILE_Y + 1, tx = (N + OTILE_X - 1) / OTILE_X + 1;
     L.nfr_max = (size_t)J * ty * tx;
     const long ntx = (d.obj_nx + OTILE_X - 1) / OTILE_X, nty = (d.obj_ny + OTILE_Y - 1) / OTILE_Y;
@@ -140,7 +144,8 @@ static Layout layout_for(const ptycho_desc_t &d) {
     const size_t nb_st = L.nent_max + L.nfr_max / 16 + L.nstacks;
     L.nlist_ints = 3 * nb_st + 3 * L.nent_max + 2;
     L.npslots = std::min<size_t>(8192, L.nfr_max / 8 + 1);
-    L.nred = std::max((size_t)L.nstacks * L.maxb, (size_t)L.nstacks_ls * L.maxb_ls * 2);
+    L.nred = std::max({(size_t)L.nstacks * L.maxb, (size_t)L.nstacks_ls * L.maxb_ls * 2,
+                       (size_t)L.nstacks_ls2 * L.maxb_ls2 * 2});
     L.pchunks = probe_chunks(d);
     const size_t n2 = (size_t)N * N, no = (size_t)d.obj_ny * d.obj_nx;
     size_t o = 0;
@@ -597,6 +602,8 @@ StackArgs ptycho::stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj,
     a.obj = (const float2 *)obj;
     a.probe = (const float2 *)probe;
     a.scr = p->scr;
+    a.fwd = p->scr;
+    a.colin = p->scr;
     a.qbuf = p->q;
     a.iobs = p->iobs;
     a.bg = p->bg;
@@ -758,7 +765,7 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
     for (int c = 0; c < n_cycles; ++c) {
         int s2 = PTYCHO_OK;
         if (upd & 1u) s2 = zero_sums(p, ACC_OBJ);
-        if (!s2) s2 = np->project(p, obj, probe, psi, kind, (upd & 1u) ? ACC_OBJ : 0u, upd_bg);
+        if (!s2) s2 = np->project(p, obj, probe, psi, kind, (upd & 1u) ? ACC_OBJ : 0u, upd_bg, nullptr);
         if (!s2 && upd_bg) {
             // every stack was projected with the old background
             Timed tm(p, TC_OTHER);
@@ -797,10 +804,11 @@ extern "C" int ptycho_psi_init(ptycho_plan_t p, const float *obj, const float *p
 
 // A read-only forward pass of column op `op` through the frame-size table.
 static int forward_pass(ptycho_plan_s *p, int op, const float *obj, const float *probe, const float *dobj,
-                        const float *dprobe, float *icalc, int llk_model = LLK_POISSON) {
+                        const float *dprobe, float *icalc, int llk_model = LLK_POISSON,
+                        const float2 *keep = nullptr) {
     const NPass *np = passes_for(p->d.n);
     if (!np) return PTYCHO_E_UNSUPPORTED;
-    return np->forward(p, op, obj, probe, dobj, dprobe, icalc, llk_model);
+    return np->forward(p, op, obj, probe, dobj, dprobe, icalc, llk_model, keep);
 }
 
 static int zero_red(ptycho_plan_s *p) { return zero_async(p->red, up(sizeof(double) * p->L.nred), p->stream); }
@@ -892,13 +900,14 @@ extern "C" int ptycho_icalc(ptycho_plan_t p, const float *obj, const float *prob
 }
 
 // Gradient pass: sums in numO/numP (and denominators), LLK partials in red.
-static int grad_pass(ptycho_plan_s *p, const float *obj, const float *probe) {
+// keep (nullable) receives the forward row transforms of every frame.
+static int grad_pass(ptycho_plan_s *p, const float *obj, const float *probe, float2 *keep = nullptr) {
     int st = zero_sums(p, ACC_OBJ | ACC_PROBE);
     if (!st) st = zero_red(p);
     if (st) return st;
     const NPass *np = passes_for(p->d.n);
     if (!np) return PTYCHO_E_UNSUPPORTED;
-    return np->project(p, obj, probe, nullptr, 2, ACC_OBJ | ACC_PROBE, false);
+    return np->project(p, obj, probe, nullptr, 2, ACC_OBJ | ACC_PROBE, false, keep);
 }
 
 extern "C" int ptycho_ml_grad(ptycho_plan_t p, const float *obj, const float *probe, float *g_obj, float *g_probe,
@@ -919,11 +928,14 @@ extern "C" int ptycho_ml_grad(ptycho_plan_t p, const float *obj, const float *pr
     return PTYCHO_OK;
 }
 
+// Line-search coefficients; with keep (the gradient pass's row transforms at
+// the same point) the pass forms and row-transforms only B and C.
 static int ls_pass(ptycho_plan_s *p, const float *obj, const float *probe, const float *dobj, const float *dprobe,
-                   double *coef) {
+                   double *coef, const float2 *keep = nullptr) {
     int st = zero_red(p);
     if (st) return st;
-    st = forward_pass(p, OP_LS, obj, probe, dobj, dprobe, nullptr);
+    st = keep ? forward_pass(p, OP_LS2, obj, probe, dobj, dprobe, nullptr, LLK_POISSON, keep)
+              : forward_pass(p, OP_LS, obj, probe, dobj, dprobe, nullptr);
     if (st) return st;
     const long n = (long)p->L.nred / 2;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, n, 2, coef, 0);
@@ -941,10 +953,14 @@ extern "C" int ptycho_ml_linesearch(ptycho_plan_t p, const float *obj, const flo
 }
 
 // ------------------------------------------------------------ CG ML cycle --
+// State of the CG iteration: scalars, direction and previous gradient of the
+// object and probe, inner-product partials, and the forward row transforms
+// of every frame at the current point (kept by the gradient pass for the
+// line search, which then forms only its two other transforms).
 static size_t ml_state_bytes(const ptycho_desc_t &d) {
     const size_t no = (size_t)d.obj_ny * d.obj_nx, np = (size_t)d.n_modes * d.n * d.n;
     return up(sizeof(double) * CG_NSCAL) + 2 * up(sizeof(float2) * no) + 2 * up(sizeof(float2) * np) +
-           up(sizeof(double) * 4 * CG_NPART);
+           up(sizeof(double) * 4 * CG_NPART) + up(sizeof(float2) * np * d.n_frames);
 }
 
 extern "C" int ptycho_ml_state_bytes(ptycho_plan_t p, size_t *bytes) {
@@ -974,6 +990,8 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
     float2 *g_p = (float2 *)b;
     b += up(sizeof(float2) * np);
     double *cpart = (double *)b;
+    b += up(sizeof(double) * 4 * CG_NPART);
+    float2 *keep = (float2 *)b;
     hipStream_t s = p->stream;
     if (reset) {
         hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, s, scal);
@@ -982,7 +1000,7 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
     const long n2 = (long)p->d.n * p->d.n;
     for (int c = 0; c < n_cycles; ++c) {
         // 1. gradient (sums in numO/numP), LLK, denominators
-        st = grad_pass(p, obj, probe);
+        st = grad_pass(p, obj, probe, keep);
         if (st) return st;
         {
         Timed tm(p, TC_OTHER);
@@ -996,7 +1014,7 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
                            (long)no, p->numP, g_p, d_p, (long)np, upd, scal);
         }
         // 3. line search along d, then the step
-        st = ls_pass(p, obj, probe, (const float *)d_o, (const float *)d_p, scal + CG_L1);
+        st = ls_pass(p, obj, probe, (const float *)d_o, (const float *)d_p, scal + CG_L1, keep);
         if (st) return st;
         hipLaunchKernelGGL(k_cg_step, dim3(grid_for((long)std::max(no, np))), dim3(256), 0, s, (float2 *)obj, d_o,
                            (long)no, (float2 *)probe, d_p, (long)np, upd, scal);
@@ -1111,7 +1129,7 @@ extern "C" int ptycho_llk_noalloc(const ptycho_desc_t *d, const int32_t *offsets
                        d->obj_nx, p.offs, p.order, flag);
     hipLaunchKernelGGL(k_count_good, dim3(1), dim3(256), 0, s, mask, d->n * d->n, (double)J, count);
     LAUNCHCHK();
-    st = np->forward(&p, OP_LLK, obj, probe, nullptr, nullptr, nullptr, LLK_POISSON);
+    st = np->forward(&p, OP_LLK, obj, probe, nullptr, nullptr, nullptr, LLK_POISSON, nullptr);
     if (st) return st;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, p.red, (long)L.nred, 1, llk, 0);
     hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, llk + 1, count);

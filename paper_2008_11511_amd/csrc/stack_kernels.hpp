@@ -27,13 +27,16 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     const int2 o = a.offs[j];
     const size_t orow = (size_t)(o.x + y) * a.Nx + o.y;
     RowLds<N> L(lds, rr);
-    constexpr int SETS = (MODE == IN_LS) ? 3 : 1;
+    // line search: A = P O, B = P dO + dP O, C = dP dO; IN_LS2 forms B and C
+    // only (A is the gradient pass's kept row transform)
+    constexpr bool LSM = (MODE == IN_LS) || (MODE == IN_LS2);
+    constexpr int SETS = (MODE == IN_LS) ? 3 : (MODE == IN_LS2) ? 2 : 1;
     const float2 *prow = a.probe + ((size_t)k * N + y) * N;
-    const float2 *drow = (MODE == IN_LS) ? a.dprobe + ((size_t)k * N + y) * N : nullptr;
+    const float2 *drow = LSM ? a.dprobe + ((size_t)k * N + y) * N : nullptr;
     // The three line-search rows held together need 3E complex registers;
     // at 2048 points each set is formed and transformed on its own instead
     // (the object and probe rows are read again, from the caches).
-    constexpr bool SPLIT = (MODE == IN_LS) && N >= 2048;
+    constexpr bool SPLIT = LSM && N >= 2048;
     float2 u[SPLIT ? 1 : SETS][E];
 #pragma unroll
     for (int set = 0; set < SETS; ++set) {
@@ -46,7 +49,13 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
                 const float2 p = prow[x];
                 if constexpr (SPLIT) {
                     const float2 dv = a.dobj[orow + x], dp = drow[x];
-                    u[0][e] = set == 0 ? cmul(ov, p) : set == 1 ? cadd(cmul(dv, p), cmul(ov, dp)) : cmul(dv, dp);
+                    const int q = (MODE == IN_LS2) ? set + 1 : set;
+                    u[0][e] = q == 0 ? cmul(ov, p) : q == 1 ? cadd(cmul(dv, p), cmul(ov, dp)) : cmul(dv, dp);
+                } else if constexpr (MODE == IN_LS2) {
+                    const float2 dv = a.dobj[orow + x];
+                    const float2 dp = drow[x];
+                    u[0][e] = cadd(cmul(dv, p), cmul(ov, dp));
+                    u[1][e] = cmul(dv, dp);
                 } else if constexpr (MODE == IN_LS) {
                     const float2 dv = a.dobj[orow + x];
                     const float2 dp = drow[x];
@@ -72,7 +81,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
             for (int e = 0; e < E; ++e) u[sl][e] = cmul(u[sl][e], qx[out_index<N, E, -1>(t1, e)]);
             fft1d<N, E, +1>(u[sl], t1, L);
         }
-        float2 *dst = a.scr + ((size_t)s * SETS * a.K + set * a.K + k) * N * N;
+        float2 *dst = (MODE == IN_PHI ? a.fwd : a.scr) + ((size_t)s * SETS * a.K + set * a.K + k) * N * N;
         if (active) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -171,7 +180,7 @@ __global__ __launch_bounds__(InvRowGeom<N>::TPM * K) void k_rows_inv(StackArgs a
 // 96 KiB of LDS, one after the other through one buffer beyond that.
 template <int N, int OP>
 struct ColSeqBufs {
-    static constexpr int SETS = (OP == OP_LS) ? 3 : 1;
+    static constexpr int SETS = (OP == OP_LS || OP == OP_LS2) ? 3 : 1;
     static constexpr int value = ((size_t)SETS * ColGeom<N>::LDS_F2 * 8 <= 96 * 1024) ? SETS : 1;
 };
 
@@ -243,7 +252,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP, NF>::va
     float2 u[K][E];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const float2 *src = a.scr + ((size_t)(s * K + k) * N) * N + scr_at<N>(0, c);
+        const float2 *src = a.colin + ((size_t)(s * K + k) * N) * N + scr_at<N>(0, c);
 #pragma unroll
         for (int e = 0; e < E; ++e) u[k][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
     }
@@ -339,13 +348,22 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     ColLds<N, CB> Ls[SETS];
 #pragma unroll
     for (int set = 0; set < SETS; ++set) Ls[set] = ColLds<N, CB>(lds_dyn + (ONE_BUF ? 0 : set) * G::LDS_F2, cl);
+    // set `set` of mode k: A from the kept row transforms (OP_LS2) or the
+    // scratch, B and C from the scratch
+    auto src_of = [&](int set, int k) -> const float2 * {
+        if constexpr (OP == OP_LS2) {
+            if (set == 0) return a.colin + ((size_t)(s * a.K + k) * N) * N + scr_at<N>(0, c);
+            return a.scr + ((size_t)(s * 2 * a.K + (set - 1) * a.K + k) * N) * N + scr_at<N>(0, c);
+        }
+        return a.colin + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + scr_at<N>(0, c);
+    };
     for (int k = 0; k < a.K; ++k) {
         if constexpr (ONE_BUF) {
             // one transform at a time (large N): keep A, fold B and C into
             // the sums as soon as each is transformed
             float2 A[1][E], V[1][E];
             auto load_transform = [&](float2 (&v)[1][E], int set) {
-                const float2 *src = a.scr + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + scr_at<N>(0, c);
+                const float2 *src = src_of(set, k);
 #pragma unroll
                 for (int e = 0; e < E; ++e) v[0][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
                 const int t0 = opaque(t);
@@ -372,7 +390,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
         float2 u[SETS][E];
 #pragma unroll
         for (int set = 0; set < SETS; ++set) {
-            const float2 *src = a.scr + ((size_t)(s * SETS * a.K + set * a.K + k) * N) * N + scr_at<N>(0, c);
+            const float2 *src = src_of(set, k);
 #pragma unroll
             for (int e = 0; e < E; ++e) u[set][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
         }
@@ -385,7 +403,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             i0[e] += cnorm(u[0][e]);
-            if constexpr (OP == OP_LS) {
+            if constexpr (OP == OP_LS || OP == OP_LS2) {
                 const float2 ab = cmulc(u[0][e], u[1][e]);
                 const float2 ac = cmulc(u[0][e], u[2][e]);
                 i1[e] += 2.0f * ab.x;
@@ -420,7 +438,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     if constexpr (OP == OP_LLK) {
         const double r = block_sum(acc0);
         if (threadIdx.x == 0) a.red[blk] = r;
-    } else if constexpr (OP == OP_LS) {
+    } else if constexpr (OP == OP_LS || OP == OP_LS2) {
         const double r0 = block_sum(acc0);
         const double r1 = block_sum(acc1);
         if (threadIdx.x == 0) {

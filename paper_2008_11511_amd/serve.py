@@ -351,7 +351,9 @@ class GpuExecutor:
         wl = req.wl
         no = wl.obj_shape[0] * wl.obj_shape[1]
         n2k = wl.n_modes * wl.n * wl.n
-        state = 8 * 16 + 2 * 8 * no + 2 * 8 * n2k + 8 * 4 * 256 + 8 * 256 * 6
+        # CG state: scalars, direction and gradient, partials, and the kept row
+        # transforms of every frame (ptycho_ml_state_bytes), with slack for alignment
+        state = 8 * 16 + 2 * 8 * no + 2 * 8 * n2k + 8 * 4 * 256 + 8 * 256 * 6 + 8 * n2k * wl.n_frames
         total = 0
         for name, nb in GpuExecutor._layout(req):
             total += (-(-(state if name == "state" else nb) // 4096)) * 4096
