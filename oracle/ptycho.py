@@ -50,7 +50,8 @@ __all__ = [
     "CGState", "cg_direction", "ml_cycle", "simulate_intensity", "UPDATE_OBJECT",
     "UPDATE_PROBE", "UPDATE_BACKGROUND", "DEFAULT_EPS", "DEFAULT_INERTIA",
     "model_intensity", "projection_scale", "background_update",
-    "object_gradient", "position_shifts", "update_positions",
+    "object_gradient", "position_shifts", "ml_position_shifts", "update_positions",
+    "windows_from_positions", "views_adjoint",
     "fresnel_pair", "near_field_transfer", "propagate_near_field", "to_detector", "from_detector",
 ]
 
@@ -145,22 +146,81 @@ def offsets_from_positions(pos_yx: np.ndarray, n: int, obj_shape) -> np.ndarray:
     return o.astype(np.int32)
 
 
-def views(obj: np.ndarray, offsets: np.ndarray, n: int) -> np.ndarray:
-    """Object patches under each frame window: [J][N][N]."""
-    return np.stack([np.asarray(obj)[oy:oy + n, ox:ox + n] for oy, ox in offsets])
+def windows_from_positions(pos_yx: np.ndarray, n: int, obj_shape):
+    """Sub-pixel windows: the real top-left corner t = centre + p - N/2 of each
+    frame split into its integer part o = floor(t) and fraction f = t - o in
+    [0, 1), per axis.  Reading: refined positions are real numbers (the
+    position optimisation of Section 4 moves them by fractions of a pixel), and
+    a window at a fractional corner views the object by bilinear
+    interpolation (`views`).  A corner outside [0, Ny - N] x [0, Nx - N] is an
+    error.  Returns (offsets int32 [J][2], frac float64 [J][2])."""
+    pos = np.asarray(pos_yx, dtype=np.float64)
+    ny, nx = obj_shape
+    t = np.array([ny / 2.0, nx / 2.0])[None, :] + pos - n / 2.0
+    if t.size and (t.min() < 0 or (t[:, 0] > ny - n).any() or (t[:, 1] > nx - n).any()):
+        raise ValueError("scan position window outside the object")
+    o = np.floor(t)
+    return o.astype(np.int32), t - o
 
 
-def exit_waves(obj: np.ndarray, probe: np.ndarray, offsets: np.ndarray) -> np.ndarray:
+def views(obj: np.ndarray, offsets: np.ndarray, n: int, frac=None) -> np.ndarray:
+    """Object patches under each frame window: [J][N][N].
+
+    With frac (sub-pixel windows, `windows_from_positions`) the patch is the
+    bilinear interpolation of the object at (o + f + y, o + f + x):
+      V[y, x] = sum over a, b in {0, 1} of w_a(f_y) w_b(f_x) O[o_y + y + a, o_x + x + b]
+    with w_0(f) = 1 - f, w_1(f) = f.  A neighbour beyond the object's last row
+    or column only ever has weight 0 (the corner is at most Ny - N) and is
+    read at the border instead."""
+    obj = np.asarray(obj)
+    if frac is None:
+        return np.stack([obj[oy:oy + n, ox:ox + n] for oy, ox in offsets])
+    ny, nx = obj.shape
+    out = []
+    for (oy, ox), (fy, fx) in zip(offsets, np.asarray(frac, dtype=np.float64)):
+        rows = np.minimum(np.arange(oy, oy + n + 1), ny - 1)
+        cols = np.minimum(np.arange(ox, ox + n + 1), nx - 1)
+        w = obj[np.ix_(rows, cols)]
+        out.append((1 - fy) * (1 - fx) * w[:n, :n] + (1 - fy) * fx * w[:n, 1:] +
+                   fy * (1 - fx) * w[1:, :n] + fy * fx * w[1:, 1:])
+    return np.stack(out)
+
+
+def views_adjoint(planes: np.ndarray, offsets: np.ndarray, obj_shape, frac=None) -> np.ndarray:
+    """Adjoint of `views`: sum over frames of each plane [N][N] put back on
+    the object grid, i.e. S_j^T applied to plane j and summed.  Integer
+    windows add plane j to the object window; sub-pixel windows spread
+    plane[y, x] over the four object pixels its bilinear view reads, with the
+    same weights (terms that would fall beyond the object have weight 0)."""
+    planes = np.asarray(planes)
+    n = planes.shape[-1]
+    out = np.zeros(obj_shape, dtype=planes.dtype)
+    if frac is None:
+        for (oy, ox), pl in zip(offsets, planes):
+            out[oy:oy + n, ox:ox + n] += pl
+        return out
+    ny, nx = obj_shape
+    for (oy, ox), (fy, fx), pl in zip(offsets, np.asarray(frac, dtype=np.float64), planes):
+        for a, wa in ((0, 1 - fy), (1, fy)):
+            for b, wb in ((0, 1 - fx), (1, fx)):
+                if wa * wb == 0.0:
+                    continue
+                out[oy + a:oy + a + n, ox + b:ox + b + n] += (wa * wb) * pl
+    return out
+
+
+def exit_waves(obj: np.ndarray, probe: np.ndarray, offsets: np.ndarray, frac=None) -> np.ndarray:
     """Exit waves Psi_jk(r) = O(r + o_j) P_k(r) (ptychography operator table,
-    ObjProbe2Psi: the object times the probe shifted to position j)."""
+    ObjProbe2Psi: the object times the probe shifted to position j), with
+    sub-pixel windows when frac is given."""
     probe = np.asarray(probe, dtype=np.complex128)
-    v = views(np.asarray(obj, dtype=np.complex128), offsets, probe.shape[-1])
+    v = views(np.asarray(obj, dtype=np.complex128), offsets, probe.shape[-1], frac)
     return v[:, None, :, :] * probe[None, :, :, :]
 
 
-def psi_init(obj, probe, offsets) -> np.ndarray:
+def psi_init(obj, probe, offsets, frac=None) -> np.ndarray:
     """DM starting exit waves: the current views (Psi^0 = Phi^0)."""
-    return exit_waves(obj, probe, offsets)
+    return exit_waves(obj, probe, offsets, frac)
 
 
 # --------------------------------------------------------------------------
@@ -224,51 +284,54 @@ def background_update(bg, scale) -> np.ndarray:
 # Object / probe update (operator Psi2ObjProbe; inertia, Section 4)
 # --------------------------------------------------------------------------
 
-def overlap_sums(psi, obj, probe, offsets):
+def overlap_sums(psi, obj, probe, offsets, frac=None):
     """Numerators and denominators of the overlap (least-squares) update.
 
     numO(r) = sum_jk conj(P_k(r - o_j)) Psi_jk(r - o_j)
     denO(r) = sum_jk |P_k(r - o_j)|^2
     numP_k(r) = sum_j conj(O(r + o_j)) Psi_jk(r)
     denP(r) = sum_j |O(r + o_j)|^2
-    numO and denO use the given probe, numP and denP the given object.
+    numO and denO use the given probe, numP and denP the given object.  With
+    sub-pixel windows (frac) the object terms go back through the adjoint of
+    the bilinear view, numO = sum_j S_j^T (sum_k conj(P_k) Psi_jk) and
+    denO = sum_j S_j^T (sum_k |P_k|^2): the row sums of the normal matrix
+    sum_j S_j^T diag(sum_k |P_k|^2) S_j, which is not diagonal once windows
+    interpolate (reading: the update keeps a diagonal denominator, exact for
+    integer windows); numP and denP use the interpolated views.
     """
     psi = np.asarray(psi, dtype=np.complex128)
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
     n = probe.shape[-1]
-    num_o = np.zeros(obj.shape, dtype=np.complex128)
-    den_o = np.zeros(obj.shape, dtype=np.float64)
-    num_p = np.zeros(probe.shape, dtype=np.complex128)
-    den_p = np.zeros(probe.shape[1:], dtype=np.float64)
     p_conj = np.conj(probe)
     p_int = (np.abs(probe) ** 2).sum(axis=0)
-    for j, (oy, ox) in enumerate(offsets):
-        win = (slice(oy, oy + n), slice(ox, ox + n))
-        num_o[win] += (p_conj * psi[j]).sum(axis=0)
-        den_o[win] += p_int
-        ov = obj[win]
-        num_p += np.conj(ov)[None] * psi[j]
-        den_p += np.abs(ov) ** 2
+    q = np.stack([(p_conj * psi[j]).sum(axis=0) for j in range(len(offsets))])
+    num_o = views_adjoint(q, offsets, obj.shape, frac)
+    den_o = views_adjoint(np.broadcast_to(p_int, (len(offsets), n, n)), offsets, obj.shape, frac)
+    v = views(obj, offsets, n, frac)
+    num_p = np.zeros(probe.shape, dtype=np.complex128)
+    den_p = np.zeros(probe.shape[1:], dtype=np.float64)
+    for j in range(len(offsets)):
+        num_p += np.conj(v[j])[None] * psi[j]
+        den_p += np.abs(v[j]) ** 2
     return num_o, den_o, num_p, den_p
 
 
-def overlap_denominators(obj, probe, offsets):
+def overlap_denominators(obj, probe, offsets, frac=None):
     """denO and denP alone (they do not depend on the exit waves)."""
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
     n = probe.shape[-1]
-    den_o = np.zeros(obj.shape, dtype=np.float64)
-    den_p = np.zeros(probe.shape[1:], dtype=np.float64)
     p_int = (np.abs(probe) ** 2).sum(axis=0)
-    for oy, ox in offsets:
-        den_o[oy:oy + n, ox:ox + n] += p_int
-        den_p += np.abs(obj[oy:oy + n, ox:ox + n]) ** 2
+    den_o = views_adjoint(np.broadcast_to(p_int, (len(offsets), n, n)), offsets, obj.shape, frac)
+    den_p = np.zeros(probe.shape[1:], dtype=np.float64)
+    for v in views(obj, offsets, n, frac):
+        den_p += np.abs(v) ** 2
     return den_o, den_p
 
 
 def overlap_update(obj, probe, psi, offsets, update=UPDATE_OBJECT | UPDATE_PROBE,
-                   inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA):
+                   inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA, frac=None):
     """New object and probe from the exit waves (Psi2ObjProbe).
 
     The object is updated first, from the current probe; the probe is then
@@ -285,12 +348,12 @@ def overlap_update(obj, probe, psi, offsets, update=UPDATE_OBJECT | UPDATE_PROBE
     probe = np.asarray(probe, dtype=np.complex128)
     new_obj, new_probe = obj.copy(), probe.copy()
     if update & UPDATE_OBJECT:
-        num_o, den_o, _, _ = overlap_sums(psi, obj, probe, offsets)
+        num_o, den_o, _, _ = overlap_sums(psi, obj, probe, offsets, frac)
         a = inertia_obj * den_o.max()
         d = den_o + a
         new_obj = np.where(d > 0, (num_o + a * obj) / np.where(d > 0, d, 1.0), obj)
     if update & UPDATE_PROBE:
-        _, _, num_p, den_p = overlap_sums(psi, new_obj, probe, offsets)
+        _, _, num_p, den_p = overlap_sums(psi, new_obj, probe, offsets, frac)
         a = inertia_probe * den_p.max()
         d = (den_p + a)[None]
         new_probe = np.where(d > 0, (num_p + a * probe) / np.where(d > 0, d, 1.0), probe)
@@ -303,7 +366,7 @@ def overlap_update(obj, probe, psi, offsets, update=UPDATE_OBJECT | UPDATE_PROBE
 
 def ap_cycle(obj, probe, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
              inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
-             eps=DEFAULT_EPS, bg=None, nf=None):
+             eps=DEFAULT_EPS, bg=None, nf=None, frac=None):
     """One alternating-projections cycle: views, Fourier projection of every
     frame, then one object/probe update from all projected exit waves.
     Returns (obj, probe); with a background bg, (obj, probe, bg), the
@@ -312,12 +375,12 @@ def ap_cycle(obj, probe, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROB
     field."""
     if (update & UPDATE_BACKGROUND) and bg is None:
         raise ValueError("a background update needs a background")
-    phi = exit_waves(obj, probe, offsets)
+    phi = exit_waves(obj, probe, offsets, frac)
     phi_hat = to_detector(phi, nf)
     scale = projection_scale(phi_hat, iobs, mask, eps, bg)
     psi = from_detector(phi_hat * scale[:, None, :, :], nf)
     o, p = overlap_update(obj, probe, psi, offsets, update & (UPDATE_OBJECT | UPDATE_PROBE),
-                          inertia_obj, inertia_probe)
+                          inertia_obj, inertia_probe, frac)
     if bg is None:
         return o, p
     b = background_update(bg, scale) if update & UPDATE_BACKGROUND else np.asarray(bg, dtype=np.float64)
@@ -326,17 +389,17 @@ def ap_cycle(obj, probe, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROB
 
 def dm_cycle(obj, probe, psi, offsets, iobs, mask, update=UPDATE_OBJECT | UPDATE_PROBE,
              inertia_obj=DEFAULT_INERTIA, inertia_probe=DEFAULT_INERTIA,
-             eps=DEFAULT_EPS, bg=None, nf=None):
+             eps=DEFAULT_EPS, bg=None, nf=None, frac=None):
     """One difference-map cycle (beta = 1) on persistent exit waves.
 
     Phi = views of the current object and probe (the overlap projection of
     the previous cycle's Psi); Psi <- Psi + P_F(2 Phi - Psi) - Phi; then the
     object and probe are updated from the new Psi.  Returns (obj, probe, psi).
     """
-    phi = exit_waves(obj, probe, offsets)
+    phi = exit_waves(obj, probe, offsets, frac)
     psi = np.asarray(psi, dtype=np.complex128)
     psi_new = psi + fourier_project(2.0 * phi - psi, iobs, mask, eps, bg, nf) - phi
-    o, p = overlap_update(obj, probe, psi_new, offsets, update, inertia_obj, inertia_probe)
+    o, p = overlap_update(obj, probe, psi_new, offsets, update, inertia_obj, inertia_probe, frac)
     return o, p, psi_new
 
 
@@ -378,10 +441,10 @@ def llk_model_terms(icalc, iobs, model, eps=DEFAULT_EPS):
     raise ValueError(f"unknown noise model {model!r}")
 
 
-def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson", bg=None, nf=None):
+def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson", bg=None, nf=None, frac=None):
     """(sum over unmasked pixels of all frames, number of those pixels) of
     the chosen noise model's terms."""
-    inten = model_intensity(to_detector(exit_waves(obj, probe, offsets), nf), bg)
+    inten = model_intensity(to_detector(exit_waves(obj, probe, offsets, frac), nf), bg)
     terms = llk_model_terms(inten, iobs, model, eps)
     if mask is not None:
         good = np.broadcast_to(np.asarray(mask)[None] == 0, terms.shape)
@@ -390,7 +453,7 @@ def llk(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, model="poisson", bg=No
     return float(terms[good].sum()), int(good.sum())
 
 
-def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None):
+def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None, frac=None):
     """Gradient of the Poisson LLK w.r.t. object and probe.
 
     Convention: g = dL/dRe(z) + i dL/dIm(z) (= 2 dL/dz*).  With
@@ -400,12 +463,14 @@ def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None):
       g_O = 2 sum_jk S_j^T (conj(P_k) psi_jk)
       g_P_k = 2 sum_j conj(O_j) psi_jk
     In the near field (nf given) F is the unitary propagation and F^-1 its
-    adjoint.  Returns (g_obj, g_probe, llk_sum).
+    adjoint.  With sub-pixel windows (frac) S_j is the bilinear view and
+    S_j^T its adjoint (`views_adjoint`), so the gradient stays exact.
+    Returns (g_obj, g_probe, llk_sum).
     """
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
     n = probe.shape[-1]
-    phi_hat = to_detector(exit_waves(obj, probe, offsets), nf)
+    phi_hat = to_detector(exit_waves(obj, probe, offsets, frac), nf)
     inten = np.maximum(model_intensity(phi_hat, bg), eps)
     io = np.asarray(iobs, dtype=np.float64)
     dl = 1.0 - io / inten
@@ -415,16 +480,17 @@ def ml_grad(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None):
         dl = np.where(bad, 0.0, dl)
         terms = np.where(bad, 0.0, terms)
     psi = from_detector(dl[:, None] * phi_hat, nf)
-    g_o = np.zeros(obj.shape, dtype=np.complex128)
+    p_conj = np.conj(probe)
+    q = np.stack([(p_conj * psi[j]).sum(axis=0) for j in range(len(offsets))])
+    g_o = 2.0 * views_adjoint(q, offsets, obj.shape, frac)
     g_p = np.zeros(probe.shape, dtype=np.complex128)
-    for j, (oy, ox) in enumerate(offsets):
-        win = (slice(oy, oy + n), slice(ox, ox + n))
-        g_o[win] += 2.0 * (np.conj(probe) * psi[j]).sum(axis=0)
-        g_p += 2.0 * np.conj(obj[win])[None] * psi[j]
+    for j, v in enumerate(views(obj, offsets, n, frac)):
+        g_p += 2.0 * np.conj(v)[None] * psi[j]
     return g_o, g_p, float(terms.sum())
 
 
-def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None):
+def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None,
+                     frac=None):
     """First and second derivative of L(gamma) = LLK(O + g dO, P + g dP) at 0.
 
     The exit wave along the line is A + gamma B + gamma^2 C with
@@ -436,9 +502,9 @@ def linesearch_coefs(obj, probe, dobj, dprobe, offsets, iobs, mask, eps=DEFAULT_
     quadratic line search of the Poisson ML conjugate gradient the paper
     cites, Thibault & Guizar-Sicairos 2012).
     """
-    a = to_detector(exit_waves(obj, probe, offsets), nf)
-    b = to_detector(exit_waves(obj, dprobe, offsets) + exit_waves(dobj, probe, offsets), nf)
-    c = to_detector(exit_waves(dobj, dprobe, offsets), nf)
+    a = to_detector(exit_waves(obj, probe, offsets, frac), nf)
+    b = to_detector(exit_waves(obj, dprobe, offsets, frac) + exit_waves(dobj, probe, offsets, frac), nf)
+    c = to_detector(exit_waves(dobj, dprobe, offsets, frac), nf)
     i0 = np.maximum(model_intensity(a, bg), eps)
     i1 = 2.0 * (np.conj(a) * b).real.sum(axis=1)
     i2 = (np.abs(b) ** 2).sum(axis=1) + 2.0 * (np.conj(a) * c).real.sum(axis=1)
@@ -501,7 +567,7 @@ def cg_direction(state: CGState, g_o, g_p, s: float):
 
 
 def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
-             update=UPDATE_OBJECT, eps=DEFAULT_EPS, bg=None, nf=None):
+             update=UPDATE_OBJECT, eps=DEFAULT_EPS, bg=None, nf=None, frac=None):
     """One Polak-Ribiere (PR+) conjugate-gradient step on the Poisson LLK.
 
     The probe block of the gradient is scaled by s = max(denO) / max(denP)
@@ -513,15 +579,15 @@ def ml_cycle(obj, probe, state: CGState, offsets, iobs, mask,
     """
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
-    g_o, g_p, lsum = ml_grad(obj, probe, offsets, iobs, mask, eps, bg, nf)
+    g_o, g_p, lsum = ml_grad(obj, probe, offsets, iobs, mask, eps, bg, nf, frac)
     if not update & UPDATE_OBJECT:
         g_o = np.zeros_like(g_o)
     if not update & UPDATE_PROBE:
         g_p = np.zeros_like(g_p)
-    den_o, den_p = overlap_denominators(obj, probe, offsets)
+    den_o, den_p = overlap_denominators(obj, probe, offsets, frac)
     s = den_o.max() / den_p.max() if den_p.max() > 0 else 1.0
     d_o, d_p, _ = cg_direction(state, g_o, g_p, s)
-    l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps, bg, nf)
+    l1, l2 = linesearch_coefs(obj, probe, d_o, d_p, offsets, iobs, mask, eps, bg, nf, frac)
     gamma = -l1 / l2 if (l2 > 0.0 and math.isfinite(l1) and math.isfinite(l2)) else 0.0
     state.history.append(lsum)
     return obj + gamma * d_o, probe + gamma * d_p
@@ -539,7 +605,7 @@ def object_gradient(obj):
     return np.gradient(o, axis=0), np.gradient(o, axis=1)
 
 
-def position_shifts(obj, probe, psi, offsets):
+def position_shifts(obj, probe, psi, offsets, frac=None):
     """Shift of every frame's illumination position from its exit waves.
 
     A frame whose true position is r_j + d has exit waves
@@ -551,21 +617,22 @@ def position_shifts(obj, probe, psi, offsets):
       [S_yy S_yx] [d_y]   [sum Re(conj(G_y) chi)]
       [S_xy S_xx] [d_x] = [sum Re(conj(G_x) chi)],  S_ab = sum Re(conj(G_a) G_b)
     with G_a = P_k dO/da over frame j's window and the sums over modes and
-    pixels (d = 0 when the system is singular).  Also returns the frame's
-    gradient energy e_j = S_yy + S_xx, by which frames with too little
-    object contrast are left in place.
+    pixels (d = 0 when the system is singular).  With sub-pixel windows
+    (frac) the view and the gradient are both interpolated bilinearly.  Also
+    returns the frame's gradient energy e_j = S_yy + S_xx, by which frames
+    with too little object contrast are left in place.
     Returns (shifts [J][2] as (dy, dx) in pixels, e [J])."""
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
     psi = np.asarray(psi, dtype=np.complex128)
     gy, gx = object_gradient(obj)
     n = probe.shape[-1]
+    vo, vy, vx = (views(a, offsets, n, frac) for a in (obj, gy, gx))
     shifts = np.zeros((len(offsets), 2))
     energy = np.zeros(len(offsets))
-    for j, (oy, ox) in enumerate(offsets):
-        win = (slice(oy, oy + n), slice(ox, ox + n))
-        chi = psi[j] - probe * obj[win][None]
-        g = [probe * gy[win][None], probe * gx[win][None]]
+    for j in range(len(offsets)):
+        chi = psi[j] - probe * vo[j][None]
+        g = [probe * vy[j][None], probe * vx[j][None]]
         a = np.array([[float((np.conj(g[r]) * g[c]).real.sum()) for c in range(2)] for r in range(2)])
         b = np.array([float((np.conj(g[r]) * chi).real.sum()) for r in range(2)])
         det = a[0, 0] * a[1, 1] - a[0, 1] * a[1, 0]
@@ -573,6 +640,26 @@ def position_shifts(obj, probe, psi, offsets):
             shifts[j] = np.linalg.solve(a, b)
         energy[j] = a[0, 0] + a[1, 1]
     return shifts, energy
+
+
+def ml_position_shifts(obj, probe, offsets, iobs, mask, eps=DEFAULT_EPS, bg=None, nf=None, frac=None):
+    """Position shifts during ML (Section 4: position optimisation during AP
+    and ML).  Reading: the exit-wave change that ML proposes is minus half the
+    back-propagated gradient wave, chi = -1/2 F^-1(l'(I) F(Phi)) with
+    l' = 1 - Iobs/I (0 at bad pixels), which near the fit equals the AP
+    correction F^-1((s - 1) F(Phi)) to first order (1 - s^2 ~ -2 (s - 1) for
+    s = sqrt(Iobs/I)); the shifts are `position_shifts` of Phi + chi at the
+    current object, probe and windows."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    probe = np.asarray(probe, dtype=np.complex128)
+    phi = exit_waves(obj, probe, offsets, frac)
+    phi_hat = to_detector(phi, nf)
+    inten = np.maximum(model_intensity(phi_hat, bg), eps)
+    dl = 1.0 - np.asarray(iobs, dtype=np.float64) / inten
+    if mask is not None:
+        dl = np.where(np.asarray(mask)[None] != 0, 0.0, dl)
+    chi = -0.5 * from_detector(dl[:, None] * phi_hat, nf)
+    return position_shifts(obj, probe, phi + chi, offsets, frac)
 
 
 def update_positions(pos, pos0, shifts, energy, mult=1.0, max_shift=2.0, min_grad=0.1):
@@ -591,11 +678,12 @@ def update_positions(pos, pos0, shifts, energy, mult=1.0, max_shift=2.0, min_gra
 # Forward model for simulation (Section 4, simulation functions)
 # --------------------------------------------------------------------------
 
-def simulate_intensity(obj, probe, offsets, chunk: int = 64, bg=None, nf=None) -> np.ndarray:
+def simulate_intensity(obj, probe, offsets, chunk: int = 64, bg=None, nf=None, frac=None) -> np.ndarray:
     """Noise-free intensities sum_k |F(P_k O_j)|^2 (+ bg), float64 [J][N][N]:
     far field (FFT order), or near field with Fresnel parameter(s) nf
     (detector pixels in natural order)."""
     out = []
     for s in range(0, len(offsets), chunk):
-        out.append(model_intensity(to_detector(exit_waves(obj, probe, offsets[s:s + chunk]), nf), bg))
+        fr = None if frac is None else np.asarray(frac)[s:s + chunk]
+        out.append(model_intensity(to_detector(exit_waves(obj, probe, offsets[s:s + chunk], fr), nf), bg))
     return np.concatenate(out, axis=0)
