@@ -78,6 +78,7 @@ typedef enum {
 #define PTYCHO_UPDATE_OBJECT     1u
 #define PTYCHO_UPDATE_PROBE      2u
 #define PTYCHO_UPDATE_BACKGROUND 4u   /* AP only; see ptycho_ap_cycle */
+#define PTYCHO_UPDATE_POSITIONS  8u   /* AP and ML, plans with PTYCHO_FLAG_POSITIONS */
 
 /* Descriptor flags.  PTYCHO_FLAG_BACKGROUND reserves workspace for the AP
  * background refinement (S*N*N floats and N*N doubles).
@@ -86,6 +87,10 @@ typedef enum {
  * ptycho_plan_set_near_field before any call that propagates. */
 #define PTYCHO_FLAG_BACKGROUND 1u
 #define PTYCHO_FLAG_NEAR_FIELD 2u
+/* PTYCHO_FLAG_POSITIONS: the plan keeps real (sub-pixel) scan positions on
+ * the device and refines them (ptycho_plan_set_positions); every frame
+ * window may move up to desc->max_shift pixels from its start. */
+#define PTYCHO_FLAG_POSITIONS 4u
 
 /* Problem description.  Supported: N a power of two from 8 to 2048,
  * 1 <= K <= 4, J >= 1, obj_ny >= N, obj_nx >= N. */
@@ -100,7 +105,10 @@ typedef struct {
     float obj_inertia;      /* delta_O: alpha_O = delta_O * max(denO)           */
     float probe_inertia;    /* delta_P: alpha_P = delta_P * max(denP)           */
     float icalc_floor;      /* epsilon: calculated intensity floor              */
-    uint32_t flags;         /* PTYCHO_FLAG_* (BACKGROUND, NEAR_FIELD; OR-ed)    */
+    uint32_t flags;         /* PTYCHO_FLAG_* (BACKGROUND, NEAR_FIELD, POSITIONS) */
+    float max_shift;        /* PTYCHO_FLAG_POSITIONS: largest move of a position
+                               from its start, pixels (the paper's
+                               update_pos_max_shift); ignored otherwise        */
 } ptycho_desc_t;
 
 typedef struct ptycho_plan_s *ptycho_plan_t;
@@ -115,6 +123,18 @@ typedef struct ptycho_plan_s *ptycho_plan_t;
 PTYCHO_API int ptycho_offsets_from_positions(const double *pos_yx_host, int32_t n_frames,
                                   int32_t n, int32_t obj_ny, int32_t obj_nx,
                                   int32_t *offsets_out_host);
+
+/* Sub-pixel windows (host only, no GPU work): the real top-left corner
+ * t = centre + p - N/2 of each position split into offsets_out_host
+ * (int32[J][2], floor(t)) and frac_out_host (double[J][2], t - floor(t) in
+ * [0, 1)), pos_yx_host as for ptycho_offsets_from_positions.  A window at a
+ * fractional corner views the object by bilinear interpolation (refined
+ * positions are real numbers: position optimisation, Section 4).
+ * PTYCHO_E_BOUNDS, writing nothing, if a corner is outside
+ * [0, obj - N] on either axis. */
+PTYCHO_API int ptycho_windows_from_positions(const double *pos_yx_host, int32_t n_frames, int32_t n,
+                                             int32_t obj_ny, int32_t obj_nx, int32_t *offsets_out_host,
+                                             double *frac_out_host);
 
 /* Device workspace needed by a plan for `desc`, in bytes (host only).
  * Section 4: operators compute a stack of frames of the Psi array at once
@@ -212,6 +232,36 @@ PTYCHO_API int ptycho_update_positions(int32_t n_frames, const double *pos_dev, 
                                        const double *shifts_dev, double mult, double max_shift,
                                        double min_grad, double *pos_out_dev, void *stream);
 
+/* Real scan positions of a plan created with PTYCHO_FLAG_POSITIONS (Section 4:
+ * position optimisation during AP and ML, after Odstrcil et al. 2018).
+ * pos_yx_host: double[J][2] as for ptycho_offsets_from_positions; the plan's
+ * offsets must be their windows' integer corners
+ * (ptycho_windows_from_positions), else PTYCHO_E_INVALID; every corner must
+ * stay inside the object when moved by up to desc->max_shift on each axis,
+ * else PTYCHO_E_BOUNDS.  These become the start and the current positions;
+ * from then on every operator of the plan views the object through
+ * sub-pixel windows (bilinear interpolation, the object sums through its
+ * adjoint).  mult and min_grad are the step factor and low-contrast filter
+ * of the position updates (see ptycho_update_positions; finite, min_grad
+ * >= 0).  The tables are uploaded on the plan's stream without waiting. */
+PTYCHO_API int ptycho_plan_set_positions(ptycho_plan_t plan, const double *pos_yx_host, double mult,
+                                         double min_grad);
+
+/* Current positions of a PTYCHO_FLAG_POSITIONS plan into pos_yx_dev
+ * (double[J][2] device, pixels from the object centre), enqueued. */
+PTYCHO_API int ptycho_plan_positions(ptycho_plan_t plan, double *pos_yx_dev);
+
+/* One position-refinement step of a plan with positions set: the shifts of
+ * every frame from the exit waves psi_dev (complex[J][K][N][N], e.g. the
+ * projected ones an AP cycle leaves) against the plan's current windows, as
+ * ptycho_position_shifts, then the update of ptycho_update_positions with
+ * the plan's start positions, max_shift, mult and min_grad, and the new
+ * windows: all on the device, enqueued.  shifts_dev (nullable,
+ * double[J][3]) receives the shifts.  ptycho_ap_cycle and ptycho_ml_cycle
+ * do the same every cycle with PTYCHO_UPDATE_POSITIONS. */
+PTYCHO_API int ptycho_refine_positions(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
+                                       const float *psi_dev, double *shifts_dev);
+
 /* Failure detection: flag_dev (int32[1], device) is set to 1 if any value
  * of the object or probe is NaN or infinite, else 0 (enqueued, so a caller
  * can copy the flag back and read it at its next poll without waiting). */
@@ -241,7 +291,10 @@ PTYCHO_API int ptycho_plan_destroy(ptycho_plan_t plan);
  * update: PTYCHO_UPDATE_OBJECT | PTYCHO_UPDATE_PROBE, and
  * PTYCHO_UPDATE_BACKGROUND to refine the background set with
  * ptycho_plan_set_background (the plan must have PTYCHO_FLAG_BACKGROUND;
- * PTYCHO_E_INVALID otherwise).  obj, probe: in/out.
+ * PTYCHO_E_INVALID otherwise), PTYCHO_UPDATE_POSITIONS to refine the
+ * positions after each cycle's object and probe update, from the projected
+ * exit waves (ptycho_refine_positions; a plan with positions set, and psi
+ * needed).  obj, probe: in/out.
  * psi_dev: complex[J][K][N][N] storage for the projected exit waves, needed
  * (PTYCHO_E_INVALID otherwise) when the probe is updated, since the probe
  * update runs after the object update over all frames; may be NULL for an
@@ -314,7 +367,12 @@ PTYCHO_API int ptycho_ml_state_bytes(ptycho_plan_t plan, size_t *bytes_out);
  * direction (probe block scaled by max(denO)/max(denP)), quadratic line
  * search, step.  state_dev: ptycho_ml_state_bytes() bytes, 256-byte aligned;
  * reset != 0 starts a new conjugate sequence (beta = 0).  llk_hist_dev
- * (nullable, double[n_cycles]) receives the LLK at the start of each cycle. */
+ * (nullable, double[n_cycles]) receives the LLK at the start of each cycle.
+ * update may add PTYCHO_UPDATE_POSITIONS (a plan with positions set): each
+ * cycle's gradient pass also takes the position shifts, with minus half the
+ * back-propagated gradient wave as the exit-wave change (the AP correction
+ * to first order near the fit), at the cycle's start point, and the
+ * positions move after the step. */
 PTYCHO_API int ptycho_ml_cycle(ptycho_plan_t plan, float *obj_dev, float *probe_dev,
                     void *state_dev, int32_t n_cycles, uint32_t update,
                     int32_t reset, double *llk_hist_dev);

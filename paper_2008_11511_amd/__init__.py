@@ -7,7 +7,7 @@ the autograd Function over the hand-written adjoint, and
 `ReconstructionService` (module `serve`) runs on-line reconstructions
 submitted as futures.
 """
-from ._lib import PtychoError, UPDATE_BACKGROUND, UPDATE_OBJECT, UPDATE_PROBE, lib  # noqa: F401
-from .plan import Plan, offsets_from_positions, fft2  # noqa: F401
+from ._lib import PtychoError, UPDATE_BACKGROUND, UPDATE_OBJECT, UPDATE_POSITIONS, UPDATE_PROBE, lib  # noqa: F401
+from .plan import Plan, offsets_from_positions, windows_from_positions, fft2  # noqa: F401
 from .autograd import PoissonLLK, poisson_llk  # noqa: F401
 from .serve import ReconstructionService  # noqa: F401

@@ -19,8 +19,10 @@ STATUS = {0: "PTYCHO_OK", -1: "PTYCHO_E_INVALID", -2: "PTYCHO_E_BOUNDS",
 UPDATE_OBJECT = 1
 UPDATE_PROBE = 2
 UPDATE_BACKGROUND = 4
+UPDATE_POSITIONS = 8
 FLAG_BACKGROUND = 1
 FLAG_NEAR_FIELD = 2
+FLAG_POSITIONS = 4
 
 
 class PtychoError(RuntimeError):
@@ -34,12 +36,14 @@ class Desc(ctypes.Structure):
                 ("n_frames", ctypes.c_int32), ("obj_ny", ctypes.c_int32),
                 ("obj_nx", ctypes.c_int32), ("stack", ctypes.c_int32),
                 ("obj_inertia", ctypes.c_float), ("probe_inertia", ctypes.c_float),
-                ("icalc_floor", ctypes.c_float), ("flags", ctypes.c_uint32)]
+                ("icalc_floor", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("max_shift", ctypes.c_float)]
 
 
 _P = ctypes.c_void_p
 _SIGS = {
     "ptycho_offsets_from_positions": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
+    "ptycho_windows_from_positions": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P],
     "ptycho_workspace_bytes": [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)],
     "ptycho_plan": [ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
     "ptycho_plan_dry_run": [ctypes.POINTER(Desc), _P, ctypes.POINTER(ctypes.c_size_t)],
@@ -49,6 +53,9 @@ _SIGS = {
     "ptycho_position_shifts": [_P, _P, _P, _P, _P],
     "ptycho_update_positions": [ctypes.c_int32, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
                                 _P],
+    "ptycho_plan_set_positions": [_P, _P, ctypes.c_double, ctypes.c_double],
+    "ptycho_plan_positions": [_P, _P],
+    "ptycho_refine_positions": [_P, _P, _P, _P, _P],
     "ptycho_check_finite": [_P, _P, _P, _P],
     "ptycho_plan_stack": [_P, ctypes.POINTER(ctypes.c_int32)],
     "ptycho_plan_destroy": [_P],

@@ -138,6 +138,37 @@ __device__ __forceinline__ int opaque(int v) {
     return v;
 }
 
+// Sub-pixel window view: frame corner (oy, ox) + (fy, fx) with fractions in
+// [0, 1); the view of row y at column x is the bilinear interpolation
+//   (1-fy)(1-fx) O[r0][c] + (1-fy) fx O[r0][c+1] + fy (1-fx) O[r1][c] + fy fx O[r1][c+1]
+// with r0 = oy + y, c = ox + x.  The neighbour row and column are clamped to
+// the object: beyond it their weight is 0 (a corner is at most Ny - N, where
+// its fraction is 0).  With zero fractions the view is O[r0][c] exactly.
+struct ViewRow {
+    size_t i0, i1;               // offsets of object rows r0 and r1 (clamped), at column ox
+    float w00, w01, w10, w11;
+    int xlast;                   // last object column, relative to ox
+};
+__device__ __forceinline__ ViewRow view_row(int Ny, int Nx, int2 o, float2 f, int y) {
+    ViewRow v;
+    const int r0 = o.x + y, r1 = min(r0 + 1, Ny - 1);
+    v.i0 = (size_t)r0 * Nx + o.y;
+    v.i1 = (size_t)r1 * Nx + o.y;
+    v.w00 = (1.0f - f.x) * (1.0f - f.y);
+    v.w01 = (1.0f - f.x) * f.y;
+    v.w10 = f.x * (1.0f - f.y);
+    v.w11 = f.x * f.y;
+    v.xlast = Nx - 1 - o.y;
+    return v;
+}
+// The view of array `base` (object grid) at column x of the row.
+__device__ __forceinline__ float2 view_at(const float2 *base, const ViewRow &v, int x) {
+    const int x1 = min(x + 1, v.xlast);
+    const float2 a = base[v.i0 + x], b = base[v.i0 + x1], c = base[v.i1 + x], d = base[v.i1 + x1];
+    return make_float2(v.w00 * a.x + v.w01 * b.x + v.w10 * c.x + v.w11 * d.x,
+                       v.w00 * a.y + v.w01 * b.y + v.w10 * c.y + v.w11 * d.y);
+}
+
 // Object tile of the atomic-free object gather.
 constexpr int OTILE_Y = 16, OTILE_X = 64;
 
@@ -160,6 +191,7 @@ struct StackArgs {
     float *s2;                   // AP background refinement: s^2 per slot [S][N][N], or null
     const unsigned char *mask;   // [N][N] or null
     const float2 *prop;          // near field: [2][N] Qy(u) / N, Qx(v) / N (FFT order), or null
+    const float2 *frac;          // sub-pixel windows: [J] (fy, fx) of each frame's corner, or null
     float *icalc;                // [J][N][N] (icalc op)
     double *red;                 // per-block partial sums of this launch
     float eps;

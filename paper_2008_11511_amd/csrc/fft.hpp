@@ -24,15 +24,20 @@ namespace ptycho {
 // ---------------------------------------------------------------- complex --
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// The products below name their fused multiply-adds explicitly, so that
+// every kernel that forms a product rounds it the same way whatever the
+// compiler's contraction would choose for the surrounding code: two kernels
+// fed the same values (say an integer window and a sub-pixel window whose
+// fraction is zero) then give the same bits.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 // conj(a) * b
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
-    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+    return make_float2(__builtin_fmaf(a.x, b.x, a.y * b.y), __builtin_fmaf(a.x, b.y, -(a.y * b.x)));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float cnorm(float2 a) { return __builtin_fmaf(a.x, a.x, a.y * a.y); }
 
 // multiply by exp(DIR * i pi / 2): -i for the forward sign, +i for inverse
 template <int DIR>

@@ -22,42 +22,80 @@ __global__ __launch_bounds__(256) void k_bg_finish(float *bg, const double *bsum
         bg[i] = (float)((double)bg[i] * (bsum[i] / J));
 }
 
-// Position refinement (Psi2PosShift): block j accumulates, over frame j's
-// pixels and modes, the 2x2 least-squares system of its position shift,
-// chi = Psi - P O ~ d_y P dO/dy + d_x P dO/dx, with the object gradient by
-// centred differences (one-sided on the object's border), and writes
-// out[j] = (d_y, d_x, S_yy + S_xx).
+// Position refinement (Psi2PosShift): the 2x2 least-squares system of each
+// frame's position shift, chi = dPsi ~ d_y P dO/dy + d_x P dO/dx, with the
+// object gradient by centred differences (one-sided on the object's border)
+// taken at the frame's view (interpolated like the view for sub-pixel
+// windows).  The exit-wave change is chi = Psi - P O_view from projected exit
+// waves (AP), or chi = scale * Psi from a gradient wave (ML, scale = -1/2).
+// Block f CH + c sums the five terms over rows [c R, c R + R) of frame f of
+// the launch; k_pos_shift_finish adds a frame's chunks in order and solves.
 struct PosShiftArgs {
     int N, K, Ny, Nx;
+    int R, CH;                    // rows per chunk, chunks per frame
+    int lgN;                      // log2 N
     const int2 *offs;             // [J] (oy, ox)
+    const float2 *frac;           // [J] sub-pixel fractions, or null
+    const int *order;             // launch frame f -> frame j (order[s0 + f]), or null: j = f
+    int s0;
     const float2 *obj, *probe, *psi;
-    double *out;                  // [J][3]
+    int lw;                       // log2 of psi's tile width (log2 N: row-major)
+    bool by_slot;                 // psi indexed by launch frame f (stack scratch), else by frame j
+    bool ml;                      // chi = chi_scale * psi (else psi - P O_view)
+    float chi_scale;
+    double *part;                 // [J][CH][5], indexed by frame j
 };
 
-__device__ __forceinline__ float2 obj_diff(const float2 *o, int i, int lo_step, int hi_step, bool at_lo,
-                                           bool at_hi) {
-    if (at_lo) return csub(o[i + hi_step], o[i]);
-    if (at_hi) return csub(o[i], o[i - lo_step]);
-    return cscale(csub(o[i + hi_step], o[i - lo_step]), 0.5f);
+// (dO/dy, dO/dx) at object pixel (Y, X): centred inside, one-sided on the
+// border, i.e. (O[hi] - O[lo]) / (hi - lo) with lo, hi the neighbours clamped
+// to the object (branch-free).
+__device__ __forceinline__ void obj_grad(const float2 *o, int Ny, int Nx, int Y, int X, float2 &gy, float2 &gx) {
+    const int ylo = max(Y - 1, 0), yhi = min(Y + 1, Ny - 1), xlo = max(X - 1, 0), xhi = min(X + 1, Nx - 1);
+    const float sy = (yhi - ylo == 2) ? 0.5f : 1.0f, sx = (xhi - xlo == 2) ? 0.5f : 1.0f;
+    const size_t row = (size_t)Y * Nx;
+    gy = cscale(csub(o[(size_t)yhi * Nx + X], o[(size_t)ylo * Nx + X]), sy);
+    gx = cscale(csub(o[row + xhi], o[row + xlo]), sx);
 }
 
-__global__ __launch_bounds__(256) void k_pos_shift(PosShiftArgs a) {
-    const int j = blockIdx.x, N = a.N;
+__global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
+    const int c = blockIdx.x % a.CH, f = blockIdx.x / a.CH, N = a.N;
+    const int j = a.order != nullptr ? a.order[a.s0 + f] : f;
     const int2 o = a.offs[j];
-    const long n2 = (long)N * N;
+    const bool sub = a.frac != nullptr;
+    const float2 fr = sub ? a.frac[j] : make_float2(0.0f, 0.0f);
+    const size_t n2 = (size_t)N * N;
+    const size_t pbase = (size_t)(a.by_slot ? f : j) * a.K * n2;
     double syy = 0.0, sxx = 0.0, sxy = 0.0, by = 0.0, bx = 0.0;
-    for (long idx = threadIdx.x; idx < n2; idx += 256) {
-        const int y = (int)(idx / N), x = (int)(idx % N);
-        const int Y = o.x + y, X = o.y + x;
-        const int i = Y * a.Nx + X;
-        const float2 ov = a.obj[i];
-        const float2 gy = obj_diff(a.obj, i, a.Nx, a.Nx, Y == 0, Y == a.Ny - 1);
-        const float2 gx = obj_diff(a.obj, i, 1, 1, X == 0, X == a.Nx - 1);
+    const int npix = a.R * N;
+    for (int idx = threadIdx.x; idx < npix; idx += 256) {
+        const int y = c * a.R + (idx >> a.lgN), x = idx & (N - 1);
+        float2 ov, gy, gx;
+        if (!sub) {
+            ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
+            obj_grad(a.obj, a.Ny, a.Nx, o.x + y, o.y + x, gy, gx);
+        } else {
+            const float wy[2] = {1.0f - fr.x, fr.x}, wx[2] = {1.0f - fr.y, fr.y};
+            ov = gy = gx = make_float2(0.0f, 0.0f);
+#pragma unroll
+            for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+                for (int bx2 = 0; bx2 < 2; ++bx2) {
+                    const float w = wy[ay] * wx[bx2];
+                    const int Y = min(o.x + y + ay, a.Ny - 1), X = min(o.y + x + bx2, a.Nx - 1);
+                    float2 g1, g2;
+                    obj_grad(a.obj, a.Ny, a.Nx, Y, X, g1, g2);
+                    const float2 v = a.obj[(size_t)Y * a.Nx + X];
+                    ov = make_float2(ov.x + w * v.x, ov.y + w * v.y);
+                    gy = make_float2(gy.x + w * g1.x, gy.y + w * g1.y);
+                    gx = make_float2(gx.x + w * g2.x, gx.y + w * g2.y);
+                }
+        }
+        const size_t pix = tiled_at(y, x, N, a.lw);
         float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
         for (int k = 0; k < a.K; ++k) {
-            const float2 p = a.probe[k * n2 + idx];
-            const float2 ps = a.psi[((size_t)j * a.K + k) * n2 + idx];
-            const float2 chi = csub(ps, cmul(p, ov));
+            const float2 p = a.probe[(size_t)k * n2 + (size_t)y * N + x];
+            const float2 ps = a.psi[pbase + (size_t)k * n2 + pix];
+            const float2 chi = a.ml ? cscale(ps, a.chi_scale) : csub(ps, cmul(p, ov));
             const float2 Gy = cmul(p, gy), Gx = cmul(p, gx);
             fyy += cnorm(Gy);
             fxx += cnorm(Gx);
@@ -77,15 +115,57 @@ __global__ __launch_bounds__(256) void k_pos_shift(PosShiftArgs a) {
     by = block_sum(by);
     bx = block_sum(bx);
     if (threadIdx.x == 0) {
-        const double det = syy * sxx - sxy * sxy;
-        double dy = 0.0, dx = 0.0;
-        if (det > 0.0 && det > 1e-12 * syy * sxx) {
-            dy = (sxx * by - sxy * bx) / det;
-            dx = (syy * bx - sxy * by) / det;
-        }
-        a.out[3 * j] = dy;
-        a.out[3 * j + 1] = dx;
-        a.out[3 * j + 2] = syy + sxx;
+        double *d = a.part + ((size_t)j * a.CH + c) * 5;
+        d[0] = syy;
+        d[1] = sxx;
+        d[2] = sxy;
+        d[3] = by;
+        d[4] = bx;
+    }
+}
+
+// out[j] = (d_y, d_x, S_yy + S_xx) from the chunks of frames order[s0 + f]
+// (or f), f < nf; d = 0 when the 2x2 system is singular.
+__global__ __launch_bounds__(256) void k_pos_shift_finish(const double *part, int CH, const int *order, int s0, int nf,
+                                                          double *out) {
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= nf) return;
+    const int j = order != nullptr ? order[s0 + f] : f;
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < CH; ++c)
+        for (int m = 0; m < 5; ++m) s[m] += part[((size_t)j * CH + c) * 5 + m];
+    const double syy = s[0], sxx = s[1], sxy = s[2], by = s[3], bx = s[4];
+    const double det = syy * sxx - sxy * sxy;
+    double dy = 0.0, dx = 0.0;
+    if (det > 0.0 && det > 1e-12 * syy * sxx) {
+        dy = (sxx * by - sxy * bx) / det;
+        dx = (syy * bx - sxy * by) / det;
+    }
+    out[3 * (size_t)j] = dy;
+    out[3 * (size_t)j + 1] = dx;
+    out[3 * (size_t)j + 2] = syy + sxx;
+}
+
+// Window tables from real corners t (double [J][2]): offs = floor(t) clamped
+// to the object, frac = t - offs in float, 0 at the last corner.
+__global__ __launch_bounds__(256) void k_windows(const double *t, int J, int n, int Ny, int Nx, int2 *offs,
+                                                 float2 *frac) {
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < J; j += gridDim.x * 256) {
+        const double ty = t[2 * (size_t)j], tx = t[2 * (size_t)j + 1];
+        const int oy = min(max((int)floor(ty), 0), Ny - n), ox = min(max((int)floor(tx), 0), Nx - n);
+        offs[j] = make_int2(oy, ox);
+        frac[j] = make_float2((float)fmin(fmax(ty - oy, 0.0), oy == Ny - n ? 0.0 : 1.0),
+                              (float)fmin(fmax(tx - ox, 0.0), ox == Nx - n ? 0.0 : 1.0));
+    }
+}
+
+// Positions relative to the object centre from real corners: p = t - c + N/2.
+__global__ __launch_bounds__(256) void k_corners_to_positions(const double *t, int J, double cy, double cx,
+                                                              double *pos) {
+#pragma clang fp contract(off)
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < J; j += gridDim.x * 256) {
+        pos[2 * (size_t)j] = t[2 * (size_t)j] - cy;
+        pos[2 * (size_t)j + 1] = t[2 * (size_t)j + 1] - cx;
     }
 }
 
@@ -226,6 +306,8 @@ struct ObjTileArgs {
     float *denO;
     float2 *pnum;                 // partial sums [slot][OTILE_Y * OTILE_X]
     float *pden;
+    const int2 *offs;             // sub-pixel windows: frame corners by frame (entry .w) ...
+    const float2 *frac;           // ... and their fractions, or null (integer windows: entries)
 };
 
 __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
@@ -246,6 +328,36 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
     const int N = a.N;
     const size_t fsz = (size_t)N * N;
     const int f0 = a.tptr[blockIdx.x], f1 = a.tptr[blockIdx.x + 1];
+    if (a.frac != nullptr) {
+        // sub-pixel windows: object pixel (py, px) takes w_ab q(py - oy - a, px - ox - b) from every
+        // frame, the adjoint of the bilinear view (the same weights), and w_ab sum_k |P_k|^2 at the
+        // same place for the denominator; the frame's corner comes from the device tables
+        for (int f = f0; f < f1; ++f) {
+            const int jf = a.tent[f].w;
+            const int2 o = a.offs[jf];
+            const float2 fr = a.frac[jf];
+            const float2 *qs = a.q + (size_t)a.tent[f].x * fsz;
+            const float wy[2] = {1.0f - fr.x, fr.x}, wx[2] = {1.0f - fr.y, fr.y};
+#pragma unroll
+            for (int i = 0; i < PY; ++i) {
+                const int y = ty * OTILE_Y + r0 + RSTEP * i - o.x, x = px - o.y;
+#pragma unroll
+                for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+                    for (int bx = 0; bx < 2; ++bx) {
+                        const int yy = y - ay, xx = x - bx;
+                        if ((unsigned)yy < (unsigned)N && (unsigned)xx < (unsigned)N) {
+                            const float w = wy[ay] * wx[bx];
+                            const size_t pix = (size_t)yy * N + xx;
+                            const float2 v = qs[pix];
+                            acc[i].x += w * v.x;
+                            acc[i].y += w * v.y;
+                            den[i] += w * a.pint[pix];
+                        }
+                    }
+            }
+        }
+    } else {
     // FU frames per iteration: all loads are issued before any is summed
     // (the per-pixel order of the sum is unchanged).  Out-of-window pixels
     // and missing frames read a clamped in-window address and are weighted
@@ -278,6 +390,7 @@ __global__ __launch_bounds__(256) void k_gather_obj(ObjTileArgs a) {
                 acc[i].y += m[h][i] * v[h][i].y;
                 den[i] += m[h][i] * d[h][i];
             }
+    }
     }
     const int slot = a.pslot[blockIdx.x];
     if (slot >= 0) {
@@ -335,7 +448,8 @@ __global__ __launch_bounds__(256) void k_obj_chunk_reduce(const int *rtile, cons
 // stored exit waves [J][K][N][N] by frame.  The order is the plan's
 // spatially compact one, so object rows are reused in L2.
 struct ProbeAllArgs {
-    int N, K, q0, nq, Nx;
+    int N, K, q0, nq, Nx, Ny;
+    const float2 *frac;  // sub-pixel windows [J], or null
     int lw;             // log2 of the exit waves' tile width (log2 N: row-major)
     const int2 *offs;
     const int *order;
@@ -362,7 +476,8 @@ __global__ __launch_bounds__(256) void k_gather_probe(ProbeAllArgs a) {
     for (int q = j0; q < j1; ++q) {
         const int j = a.order[a.q0 + q];
         const int2 o = a.offs[j];
-        const float2 ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
+        const float2 ov = a.frac != nullptr ? view_at(a.obj, view_row(a.Ny, a.Nx, o, a.frac[j], y), x)
+                                            : a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
         const float2 *ps = a.psi + (size_t)(FROM_SCR ? q : j) * K * fsz + vpix;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -463,7 +578,8 @@ __global__ __launch_bounds__(256) void k_zero(float4 *p, long n16) {
 
 // psi[j][k] = O_j * P_k for all frames (DM start).
 __global__ __launch_bounds__(256) void k_psi_init(const float2 *obj, const float2 *probe, const int2 *offs,
-                                                  float2 *psi, int N, int K, int Nx, long total) {
+                                                  const float2 *frac, float2 *psi, int N, int K, int Ny, int Nx,
+                                                  long total) {
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
         const long n2 = (long)N * N;
         const int pix = (int)(i % n2);
@@ -472,7 +588,9 @@ __global__ __launch_bounds__(256) void k_psi_init(const float2 *obj, const float
         const int j = (int)(jk / K);
         const int y = pix / N, x = pix % N;
         const int2 o = offs[j];
-        psi[i] = cmul(obj[(size_t)(o.x + y) * Nx + o.y + x], probe[(size_t)k * n2 + pix]);
+        const float2 ov = frac != nullptr ? view_at(obj, view_row(Ny, Nx, o, frac[j], y), x)
+                                          : obj[(size_t)(o.x + y) * Nx + o.y + x];
+        psi[i] = cmul(ov, probe[(size_t)k * n2 + pix]);
     }
 }
 

@@ -41,12 +41,26 @@ static void launch_cols_seq(const StackArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_cols_seq<N, OP, NF>), dim3(cols_blocks<N>(a.S)), dim3(ColGeom<N>::THREADS), lds, s, a);
 }
 
+// Forward row pass of input form MODE: the sub-pixel-window instance when the
+// plan's windows interpolate, the integer one otherwise.
+template <int N, int MODE, bool NF>
+static void launch_rows_fwd(const StackArgs &a, dim3 grid, hipStream_t s) {
+    if (a.frac != nullptr) hipLaunchKernelGGL((k_rows_fwd<N, MODE, NF, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_rows_fwd<N, MODE, NF, false>), grid, dim3(256), 0, s, a);
+}
+
 template <int N, int K, int MODE, bool NF>
 static void launch_rows_inv(const StackArgs &a, bool wq, hipStream_t s) {
     const dim3 grid((unsigned)(((long)a.S * N + InvRowGeom<N>::RQ - 1) / InvRowGeom<N>::RQ));
     const dim3 block(InvRowGeom<N>::TPM * K);
-    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true, NF>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false, NF>), grid, block, 0, s, a);
+    // only the DM epilogue reads the view
+    if (MODE == OUT_DM && a.frac != nullptr) {
+        if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true, NF, MODE == OUT_DM>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false, NF, MODE == OUT_DM>), grid, block, 0, s, a);
+        return;
+    }
+    if (wq) hipLaunchKernelGGL((k_rows_inv<N, K, MODE, true, NF, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_rows_inv<N, K, MODE, false, NF, false>), grid, block, 0, s, a);
 }
 
 // One pass over all stacks: forward rows, column op, inverse rows and the
@@ -80,8 +94,8 @@ static int project_pass_nk(ptycho_plan_s *p, const float *obj, const float *prob
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
-            if (kind == 1) hipLaunchKernelGGL((k_rows_fwd<N, IN_DM, NF>), rg, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI, NF>), rg, dim3(256), 0, s, a);
+            if (kind == 1) launch_rows_fwd<N, IN_DM, NF>(a, rg, s);
+            else launch_rows_fwd<N, IN_PHI, NF>(a, rg, s);
         }
         {
             Timed tm(p, TC_COLS);
@@ -103,7 +117,9 @@ static int project_pass_nk(ptycho_plan_s *p, const float *obj, const float *prob
         }
         LAUNCHCHK();
         int st = PTYCHO_OK;
-        if (acc & ACC_OBJ) st = object_sums(p, sidx);
+        // ML position shifts from the gradient wave left in the scratch
+        if (kind == 2 && p->shifts_in_grad) st = launch_ml_shifts(p, obj, probe, s0, sn);
+        if (!st && (acc & ACC_OBJ)) st = object_sums(p, sidx);
         if (!st && (acc & ACC_PROBE)) st = probe_sums(p, obj, p->scr, s0, sn, true, true);
         if (st) return st;
     }
@@ -144,9 +160,9 @@ static int forward_pass_op(ptycho_plan_s *p, const float *obj, const float *prob
         const dim3 rg(rows_blocks<N>(sn), p->d.n_modes);
         {
             Timed tm(p, TC_ROWS_FWD);
-            if (OP == OP_LS2) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS2, NF>), rg, dim3(256), 0, s, a);
-            else if (ls) hipLaunchKernelGGL((k_rows_fwd<N, IN_LS, NF>), rg, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_rows_fwd<N, IN_PHI, NF>), rg, dim3(256), 0, s, a);
+            if (OP == OP_LS2) launch_rows_fwd<N, IN_LS2, NF>(a, rg, s);
+            else if (ls) launch_rows_fwd<N, IN_LS, NF>(a, rg, s);
+            else launch_rows_fwd<N, IN_PHI, NF>(a, rg, s);
         }
         {
             Timed tm(p, TC_COLS);

@@ -53,7 +53,9 @@ struct Layout {
     size_t nlist_ints, npslots;   // object-gather block/reduce lists, partial slots
     size_t nent_max, nfr_max, nred;
     size_t off_offs, off_order, off_lists, off_ent_fr, off_opart, off_scr, off_q, off_pint, off_numO, off_denO,
-        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, off_s2, off_bsum, off_prop, total;
+        off_numP, off_denP, off_pnum, off_pden, off_part, off_red, off_scal, off_s2, off_bsum, off_prop,
+        off_pspart, off_shift, off_pos, off_pos0, off_frac, total;
+    int pos_chunks;               // row chunks per frame of the position-shift sums
 };
 
 // Per-kernel-class timing with HIP events on the plan's stream.
@@ -90,7 +92,18 @@ struct ptycho_plan_s {
     double *bsum = nullptr;  // [N][N]
     float2 *prop = nullptr;  // [2][N] with PTYCHO_FLAG_NEAR_FIELD
     bool nf_ready = false;   // Fresnel parameters set
+    double *pspart = nullptr;    // position-shift partial sums [J][pos_chunks][5]
+    double *shifts = nullptr;    // [J][3] shifts of the last refinement step
+    // PTYCHO_FLAG_POSITIONS: real window corners t (current and start),
+    // their fractions, the update parameters; pos_ready once set
+    double *pos = nullptr, *pos0 = nullptr;
+    float2 *frac = nullptr;
+    bool pos_ready = false;
+    double pos_mult = 1.0, pos_min_grad = 0.1;
+    bool shifts_in_grad = false; // the gradient pass also takes the ML position shifts
     std::vector<float2> h_prop;
+    std::vector<double> h_pos;   // host copies of the uploaded corners and fractions
+    std::vector<float2> h_frac;
     float *pint, *denO, *denP, *pden, *part;
     double *red, *scal;
     int ntx, nty;
@@ -153,6 +166,9 @@ int probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, int q0, in
                bool accumulate);
 int launch_probe_intensity(ptycho_plan_s *p, const float *probe);
 int launch_bg_accum(ptycho_plan_s *p, int sn, int first);
+// ML position shifts of the stack's slots s0 .. s0+sn from the gradient wave
+// the inverse row pass left in the stack scratch.
+int launch_ml_shifts(ptycho_plan_s *p, const float *obj, const float *probe, int s0, int sn);
 
 // The passes of one frame size N (inst_N.hip).
 struct NPass {

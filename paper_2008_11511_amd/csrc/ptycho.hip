@@ -108,6 +108,15 @@ static int probe_chunks(const ptycho_desc_t &d) {
     return (int)std::min<long>(c, d.n_frames);
 }
 
+// Object margin of a frame's tile coverage: windows of a positions plan move
+// up to max_shift pixels and view one more row and column.
+static int window_margin(const ptycho_desc_t &d) {
+    return (d.flags & PTYCHO_FLAG_POSITIONS) ? (int)std::ceil((double)d.max_shift) + 1 : 0;
+}
+
+// Rows per chunk of the position-shift sums: about 4096 pixels per block.
+static int pos_rows(int n) { return std::max(1, std::min(n, 4096 / n)); }
+
 // Frames per launch.  The stack kernels are bandwidth-bound and do not keep
 // data in cache from one launch to the next, so larger launches (fewer
 // launches, smaller tails) are faster; the scratch is sized to ~2 GiB.
@@ -133,7 +142,8 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.maxb = (int)(((long)L.S * N + cb - 1) / cb);
     L.maxb_ls = (int)(((long)L.S_ls * N + cb - 1) / cb);
     L.maxb_ls2 = (int)(((long)L.S_ls2 * N + cb - 1) / cb);
-    const long ty = (N + OTILE_Y - 1) / OTILE_Y + 1, tx = (N + OTILE_X - 1) / OTILE_X + 1;
+    const int mg = window_margin(d);
+    const long ty = (N + 2 * mg + OTILE_Y - 1) / OTILE_Y + 1, tx = (N + 2 * mg + OTILE_X - 1) / OTILE_X + 1;
     L.nfr_max = (size_t)J * ty * tx;
     const long ntx = (d.obj_nx + OTILE_X - 1) / OTILE_X, nty = (d.obj_ny + OTILE_Y - 1) / OTILE_Y;
     const long ntiles = ntx * nty;
@@ -147,6 +157,7 @@ static Layout layout_for(const ptycho_desc_t &d) {
     L.nred = std::max({(size_t)L.nstacks * L.maxb, (size_t)L.nstacks_ls * L.maxb_ls * 2,
                        (size_t)L.nstacks_ls2 * L.maxb_ls2 * 2});
     L.pchunks = probe_chunks(d);
+    L.pos_chunks = N / pos_rows(N);
     const size_t n2 = (size_t)N * N, no = (size_t)d.obj_ny * d.obj_nx;
     size_t o = 0;
     L.off_offs = o; o = up(o + sizeof(int2) * J);
@@ -173,6 +184,14 @@ static Layout layout_for(const ptycho_desc_t &d) {
     // near field: the transfer-function factors Qy / N, Qx / N
     const bool nfg = (d.flags & PTYCHO_FLAG_NEAR_FIELD) != 0;
     L.off_prop = o; o = up(o + (nfg ? sizeof(float2) * 2 * (size_t)N : 0));
+    // position refinement: shift partials and shifts; real corners and
+    // fractions of a positions plan
+    L.off_pspart = o; o = up(o + sizeof(double) * 5 * (size_t)L.pos_chunks * J);
+    L.off_shift = o; o = up(o + sizeof(double) * 3 * (size_t)J);
+    const bool pst = (d.flags & PTYCHO_FLAG_POSITIONS) != 0;
+    L.off_pos = o; o = up(o + (pst ? sizeof(double) * 2 * (size_t)J : 0));
+    L.off_pos0 = o; o = up(o + (pst ? sizeof(double) * 2 * (size_t)J : 0));
+    L.off_frac = o; o = up(o + (pst ? sizeof(float2) * (size_t)J : 0));
     L.total = o;
     return L;
 }
@@ -188,8 +207,10 @@ static int check_desc(const ptycho_desc_t *d) {
     if (d->stack < 0) return fail(PTYCHO_E_INVALID, "negative stack");
     if (!(d->obj_inertia >= 0.0f) || !(d->probe_inertia >= 0.0f)) return fail(PTYCHO_E_INVALID, "negative inertia");
     if (!(d->icalc_floor > 0.0f)) return fail(PTYCHO_E_INVALID, "icalc_floor must be > 0");
-    if (d->flags & ~(PTYCHO_FLAG_BACKGROUND | PTYCHO_FLAG_NEAR_FIELD))
+    if (d->flags & ~(PTYCHO_FLAG_BACKGROUND | PTYCHO_FLAG_NEAR_FIELD | PTYCHO_FLAG_POSITIONS))
         return fail(PTYCHO_E_INVALID, "unknown descriptor flag");
+    if ((d->flags & PTYCHO_FLAG_POSITIONS) && !(d->max_shift >= 0.0f && d->max_shift <= 0.25f * d->n))
+        return fail(PTYCHO_E_INVALID, "max_shift must be within [0, N/4] pixels");
     return PTYCHO_OK;
 }
 
@@ -210,6 +231,28 @@ extern "C" int ptycho_offsets_from_positions(const double *pos, int32_t J, int32
         tmp[2 * j + 1] = (int32_t)ox;
     }
     std::memcpy(out, tmp.data(), sizeof(int32_t) * tmp.size());
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_windows_from_positions(const double *pos, int32_t J, int32_t n, int32_t ny, int32_t nx,
+                                             int32_t *offsets, double *frac) {
+    if (!pos || !offsets || !frac) return fail(PTYCHO_E_INVALID, "null pointer");
+    if (J < 0 || n < 1 || ny < n || nx < n) return fail(PTYCHO_E_INVALID, "bad sizes");
+    std::vector<int32_t> o((size_t)J * 2);
+    std::vector<double> f((size_t)J * 2);
+    const double c[2] = {ny / 2.0, nx / 2.0};
+    const int lim[2] = {ny - n, nx - n};
+    for (int32_t j = 0; j < J; ++j)
+        for (int ax = 0; ax < 2; ++ax) {
+            const double t = c[ax] + pos[2 * j + ax] - n / 2.0;
+            if (!(t >= 0.0) || !(t <= (double)lim[ax]))
+                return fail(PTYCHO_E_BOUNDS, "scan position window outside the object (frame " + std::to_string(j) + ")");
+            const double fl = std::floor(t);
+            o[2 * j + ax] = (int32_t)fl;
+            f[2 * j + ax] = t - fl;
+        }
+    std::memcpy(offsets, o.data(), sizeof(int32_t) * o.size());
+    std::memcpy(frac, f.data(), sizeof(double) * f.size());
     return PTYCHO_OK;
 }
 
@@ -235,6 +278,7 @@ static uint32_t spread_bits(uint32_t v) {
 static int build_host_tables(ptycho_plan_s *p, const Layout &L, const int32_t *offsets) {
     const ptycho_desc_t *d = &p->d;
     const int J = d->n_frames, N = d->n;
+    const int mg = window_margin(*d);
     // frame order: Morton (Z) order of the window corners, so that every
     // stack covers a compact patch of the object
     p->h_offs.resize(J);
@@ -306,12 +350,15 @@ static int build_host_tables(ptycho_plan_s *p, const Layout &L, const int32_t *o
         const int s0 = sidx * L.S, sn = std::min(L.S, J - s0);
         touched.clear();
         for (int s = 0; s < sn; ++s) {
-            const int2 o = p->h_offs[p->h_order[s0 + s]];
-            for (int ty = o.x / OTILE_Y; ty <= (o.x + N - 1) / OTILE_Y; ++ty)
-                for (int tx = o.y / OTILE_X; tx <= (o.y + N - 1) / OTILE_X; ++tx) {
+            const int jf = p->h_order[s0 + s];
+            const int2 o = p->h_offs[jf];
+            const int y0 = std::max(0, o.x - mg), y1 = std::min(d->obj_ny - 1, o.x + N - 1 + mg);
+            const int x0 = std::max(0, o.y - mg), x1 = std::min(d->obj_nx - 1, o.y + N - 1 + mg);
+            for (int ty = y0 / OTILE_Y; ty <= y1 / OTILE_Y; ++ty)
+                for (int tx = x0 / OTILE_X; tx <= x1 / OTILE_X; ++tx) {
                     auto &v = per_tile[ty * p->ntx + tx];
                     if (v.empty()) touched.push_back(ty * p->ntx + tx);
-                    v.push_back(make_int4(s, o.x, o.y, 0));
+                    v.push_back(make_int4(s, o.x, o.y, jf));
                 }
         }
         std::sort(touched.begin(), touched.end());
@@ -445,6 +492,13 @@ extern "C" int ptycho_plan(const ptycho_desc_t *d, const int32_t *offsets, const
         p->bsum = (double *)(p->ws + L.off_bsum);
     }
     if (d->flags & PTYCHO_FLAG_NEAR_FIELD) p->prop = (float2 *)(p->ws + L.off_prop);
+    p->pspart = (double *)(p->ws + L.off_pspart);
+    p->shifts = (double *)(p->ws + L.off_shift);
+    if (d->flags & PTYCHO_FLAG_POSITIONS) {
+        p->pos = (double *)(p->ws + L.off_pos);
+        p->pos0 = (double *)(p->ws + L.off_pos0);
+        p->frac = (float2 *)(p->ws + L.off_frac);
+    }
     p->ntx = (d->obj_nx + OTILE_X - 1) / OTILE_X;
     p->nty = (d->obj_ny + OTILE_Y - 1) / OTILE_Y;
 
@@ -581,6 +635,10 @@ extern "C" int ptycho_plan_timing_read(ptycho_plan_t p, int32_t cls, double *ms_
 }
 
 // ----------------------------------------------------------------- passes --
+static int launch_shifts(ptycho_plan_s *p, const float *obj, const float *probe, const float2 *psi, int lw,
+                         bool by_slot, const int *order, int s0, int nf, bool ml, double *out);
+static int move_positions(ptycho_plan_s *p);
+
 static int zero_async(void *ptr, size_t bytes, hipStream_t s) {
     // plain fill kernel (no memset nodes, so the work can be graph-captured)
     if (bytes % 16) return fail(PTYCHO_E_INVALID, "internal: zero size");
@@ -609,6 +667,7 @@ StackArgs ptycho::stack_args(ptycho_plan_s *p, int s0, int sn, const float *obj,
     a.bg = p->bg;
     a.mask = p->mask;
     a.prop = p->prop;
+    a.frac = p->pos_ready ? p->frac : nullptr;
     a.eps = p->d.icalc_floor;
     return a;
 }
@@ -642,6 +701,8 @@ int ptycho::object_sums(ptycho_plan_s *p, int sidx) {
     a.denO = p->denO;
     a.pnum = p->opnum;
     a.pden = p->opden;
+    a.offs = p->offs;
+    a.frac = p->pos_ready ? p->frac : nullptr;
     Timed tm(p, TC_GATHER_OBJ);
     hipLaunchKernelGGL(k_gather_obj, dim3(gl.nb), dim3(256), 0, p->stream, a);
     if (gl.nr > 0) {
@@ -665,6 +726,8 @@ int ptycho::probe_sums(ptycho_plan_s *p, const float *obj, const float2 *psi, in
     a.q0 = q0;
     a.nq = nq;
     a.Nx = p->d.obj_nx;
+    a.Ny = p->d.obj_ny;
+    a.frac = p->pos_ready ? p->frac : nullptr;
     a.lw = psi_tile_log2(p, psi);
     a.offs = p->offs;
     a.order = p->order;
@@ -751,7 +814,11 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
     int st = check_prop_ptrs(p, obj, probe);
     if (st) return st;
     if (n_cycles < 0) return fail(PTYCHO_E_INVALID, "negative cycle count");
-    if (upd & ~(kind == 0 ? 7u : 3u)) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    if (upd & ~(kind == 0 ? 15u : 3u)) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    const bool upd_pos = (upd & PTYCHO_UPDATE_POSITIONS) != 0;
+    if (upd_pos && !p->pos_ready)
+        return fail(PTYCHO_E_INVALID, "a position update needs a plan with positions (ptycho_plan_set_positions)");
+    if (upd_pos && !psi) return fail(PTYCHO_E_INVALID, "a position update needs exit-wave storage (psi)");
     const bool upd_bg = (upd & PTYCHO_UPDATE_BACKGROUND) != 0;
     if (upd_bg && !p->bg) return fail(PTYCHO_E_INVALID, "a background update needs a background (set_background)");
     if (upd_bg && !p->s2)
@@ -776,6 +843,12 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
         if (!s2 && (upd & 1u)) s2 = normalize(p, obj, probe, 1u);
         if (!s2 && (upd & 2u)) s2 = probe_sums(p, obj, (const float2 *)psi, 0, p->d.n_frames, false, false);
         if (!s2 && (upd & 2u)) s2 = normalize(p, obj, probe, 2u);
+        // positions: shifts of the projected exit waves against the new
+        // object and probe, then the move
+        if (!s2 && upd_pos)
+            s2 = launch_shifts(p, obj, probe, (const float2 *)psi, ilog2(p->d.n), false, nullptr, 0, p->d.n_frames,
+                               false, p->shifts);
+        if (!s2 && upd_pos) s2 = move_positions(p);
         if (s2) return s2;
     }
     return PTYCHO_OK;
@@ -797,7 +870,8 @@ extern "C" int ptycho_psi_init(ptycho_plan_t p, const float *obj, const float *p
     if (!psi) return fail(PTYCHO_E_INVALID, "null psi");
     const long total = (long)p->d.n_frames * p->d.n_modes * p->d.n * p->d.n;
     hipLaunchKernelGGL(k_psi_init, dim3(grid_for(total)), dim3(256), 0, p->stream, (const float2 *)obj,
-                       (const float2 *)probe, p->offs, (float2 *)psi, p->d.n, p->d.n_modes, p->d.obj_nx, total);
+                       (const float2 *)probe, p->offs, p->pos_ready ? p->frac : nullptr, (float2 *)psi, p->d.n,
+                       p->d.n_modes, p->d.obj_ny, p->d.obj_nx, total);
     LAUNCHCHK();
     return PTYCHO_OK;
 }
@@ -844,25 +918,130 @@ extern "C" int ptycho_llk_model(ptycho_plan_t p, const float *obj, const float *
     return llk_into(p, obj, probe, llk, model);
 }
 
-extern "C" int ptycho_position_shifts(ptycho_plan_t p, const float *obj, const float *probe, const float *psi,
-                                      double *out) {
-    int st = check_plan_ptrs(p, obj, probe);
-    if (st) return st;
-    if (!psi || !out) return fail(PTYCHO_E_INVALID, "null psi or output");
+// Position-shift sums of nf frames (launch frame f -> frame order[s0 + f], or
+// f when order is null) from exit waves psi (AP: projected, chi = psi - P O;
+// ML: a gradient wave, chi = -1/2 psi), then the shifts of those frames into
+// out [J][3].
+static int launch_shifts(ptycho_plan_s *p, const float *obj, const float *probe, const float2 *psi, int lw,
+                         bool by_slot, const int *order, int s0, int nf, bool ml, double *out) {
     PosShiftArgs a{};
     a.N = p->d.n;
     a.K = p->d.n_modes;
     a.Ny = p->d.obj_ny;
     a.Nx = p->d.obj_nx;
+    a.R = pos_rows(a.N);
+    a.CH = p->L.pos_chunks;
+    a.lgN = ilog2(a.N);
     a.offs = p->offs;
+    a.frac = p->pos_ready ? p->frac : nullptr;
+    a.order = order;
+    a.s0 = s0;
     a.obj = (const float2 *)obj;
     a.probe = (const float2 *)probe;
-    a.psi = (const float2 *)psi;
-    a.out = out;
+    a.psi = psi;
+    a.lw = lw;
+    a.by_slot = by_slot;
+    a.ml = ml;
+    a.chi_scale = -0.5f;
+    a.part = p->pspart;
     Timed tm(p, TC_OTHER);
-    hipLaunchKernelGGL(k_pos_shift, dim3(p->d.n_frames), dim3(256), 0, p->stream, a);
+    hipLaunchKernelGGL(k_pos_shift_part, dim3((unsigned)a.CH * (unsigned)nf), dim3(256), 0, p->stream, a);
+    hipLaunchKernelGGL(k_pos_shift_finish, dim3((nf + 255) / 256), dim3(256), 0, p->stream, p->pspart, a.CH, order,
+                       s0, nf, out);
     LAUNCHCHK();
     return PTYCHO_OK;
+}
+
+int ptycho::launch_ml_shifts(ptycho_plan_s *p, const float *obj, const float *probe, int s0, int sn) {
+    return launch_shifts(p, obj, probe, p->scr, ilog2(scr_tile_w(p->d.n)), true, p->order, s0, sn, true, p->shifts);
+}
+
+extern "C" int ptycho_position_shifts(ptycho_plan_t p, const float *obj, const float *probe, const float *psi,
+                                      double *out) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!psi || !out) return fail(PTYCHO_E_INVALID, "null psi or output");
+    return launch_shifts(p, obj, probe, (const float2 *)psi, ilog2(p->d.n), false, nullptr, 0, p->d.n_frames, false,
+                         out);
+}
+
+// The plan's positions move by its last shifts (filter, step, bound), then
+// its window tables follow.
+static int move_positions(ptycho_plan_s *p) {
+    Timed tm(p, TC_OTHER);
+    hipLaunchKernelGGL(k_update_positions, dim3(1), dim3(POSUPD_THREADS), 0, p->stream, p->d.n_frames, p->pos,
+                       p->pos0, p->shifts, p->pos_mult, (double)p->d.max_shift, p->pos_min_grad, p->pos);
+    hipLaunchKernelGGL(k_windows, dim3(grid_for(p->d.n_frames)), dim3(256), 0, p->stream, p->pos, p->d.n_frames,
+                       p->d.n, p->d.obj_ny, p->d.obj_nx, p->offs, p->frac);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_set_positions(ptycho_plan_t p, const double *pos, double mult, double min_grad) {
+    if (!p || !pos) return fail(PTYCHO_E_INVALID, "null pointer");
+    if (!p->pos) return fail(PTYCHO_E_INVALID, "positions need a plan created with PTYCHO_FLAG_POSITIONS");
+    if (!std::isfinite(mult) || !std::isfinite(min_grad) || !(min_grad >= 0.0))
+        return fail(PTYCHO_E_INVALID, "mult and min_grad must be finite, min_grad >= 0");
+    const ptycho_desc_t &d = p->d;
+    const int J = d.n_frames, N = d.n;
+    const double c[2] = {d.obj_ny / 2.0, d.obj_nx / 2.0};
+    const int lim[2] = {d.obj_ny - N, d.obj_nx - N};
+    const double ms = d.max_shift;
+    std::vector<double> t((size_t)J * 2);
+    std::vector<float2> fr(J);
+    for (int j = 0; j < J; ++j) {
+        float f2[2];
+        for (int ax = 0; ax < 2; ++ax) {
+            const double tv = c[ax] + pos[2 * j + ax] - N / 2.0;
+            if (!std::isfinite(tv)) return fail(PTYCHO_E_INVALID, "non-finite position");
+            const int oref = ax == 0 ? p->h_offs[j].x : p->h_offs[j].y;
+            if (std::floor(tv) != (double)oref)
+                return fail(PTYCHO_E_INVALID, "positions do not match the plan's window corners (frame " +
+                                                  std::to_string(j) + ")");
+            if (tv - ms < 0.0 || tv + ms > (double)lim[ax])
+                return fail(PTYCHO_E_BOUNDS, "a window moved by max_shift would leave the object (frame " +
+                                                 std::to_string(j) + ")");
+            t[2 * j + ax] = tv;
+            f2[ax] = (float)(tv - std::floor(tv));
+        }
+        fr[j] = make_float2(f2[0], f2[1]);
+    }
+    p->h_pos.swap(t);
+    p->h_frac.swap(fr);
+    hipError_t e = upload_tables({{p->pos, p->h_pos.data(), sizeof(double) * p->h_pos.size()},
+                                  {p->pos0, p->h_pos.data(), sizeof(double) * p->h_pos.size()},
+                                  {p->frac, p->h_frac.data(), sizeof(float2) * p->h_frac.size()}},
+                                 p->stream);
+    if (e != hipSuccess) return fail(PTYCHO_E_HIP, std::string("position upload: ") + hipGetErrorString(e));
+    p->pos_mult = mult;
+    p->pos_min_grad = min_grad;
+    p->pos_ready = true;
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_plan_positions(ptycho_plan_t p, double *out) {
+    if (!p || !out) return fail(PTYCHO_E_INVALID, "null pointer");
+    if (!p->pos_ready) return fail(PTYCHO_E_INVALID, "the plan has no positions (ptycho_plan_set_positions)");
+    const ptycho_desc_t &d = p->d;
+    hipLaunchKernelGGL(k_corners_to_positions, dim3(grid_for(d.n_frames)), dim3(256), 0, p->stream, p->pos,
+                       d.n_frames, d.obj_ny / 2.0 - d.n / 2.0, d.obj_nx / 2.0 - d.n / 2.0, out);
+    LAUNCHCHK();
+    return PTYCHO_OK;
+}
+
+extern "C" int ptycho_refine_positions(ptycho_plan_t p, const float *obj, const float *probe, const float *psi,
+                                       double *shifts) {
+    int st = check_plan_ptrs(p, obj, probe);
+    if (st) return st;
+    if (!psi) return fail(PTYCHO_E_INVALID, "null psi");
+    if (!p->pos_ready) return fail(PTYCHO_E_INVALID, "the plan has no positions (ptycho_plan_set_positions)");
+    st = launch_shifts(p, obj, probe, (const float2 *)psi, ilog2(p->d.n), false, nullptr, 0, p->d.n_frames, false,
+                       p->shifts);
+    if (!st) st = move_positions(p);
+    if (!st && shifts)
+        HIPCHK(hipMemcpyAsync(shifts, p->shifts, sizeof(double) * 3 * p->d.n_frames, hipMemcpyDeviceToDevice,
+                              p->stream));
+    return st;
 }
 
 extern "C" int ptycho_update_positions(int32_t n_frames, const double *pos, const double *pos0, const double *shifts,
@@ -976,7 +1155,11 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
     if (!state) return fail(PTYCHO_E_INVALID, "null state");
     if (((uintptr_t)state) % ALIGN) return fail(PTYCHO_E_WORKSPACE, "state not 256-byte aligned");
     if (n_cycles < 0) return fail(PTYCHO_E_INVALID, "negative cycle count");
-    if (upd & ~3u) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    if (upd & ~11u) return fail(PTYCHO_E_INVALID, "unknown update flag");
+    const bool upd_pos = (upd & PTYCHO_UPDATE_POSITIONS) != 0;
+    if (upd_pos && !p->pos_ready)
+        return fail(PTYCHO_E_INVALID, "a position update needs a plan with positions (ptycho_plan_set_positions)");
+    upd &= 3u;
     const size_t no = (size_t)p->d.obj_ny * p->d.obj_nx, np = (size_t)p->d.n_modes * p->d.n * p->d.n;
     char *b = (char *)state;
     double *scal = (double *)b;
@@ -1000,7 +1183,9 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
     const long n2 = (long)p->d.n * p->d.n;
     for (int c = 0; c < n_cycles; ++c) {
         // 1. gradient (sums in numO/numP), LLK, denominators
+        p->shifts_in_grad = upd_pos;
         st = grad_pass(p, obj, probe, keep);
+        p->shifts_in_grad = false;
         if (st) return st;
         {
         Timed tm(p, TC_OTHER);
@@ -1019,6 +1204,11 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
         hipLaunchKernelGGL(k_cg_step, dim3(grid_for((long)std::max(no, np))), dim3(256), 0, s, (float2 *)obj, d_o,
                            (long)no, (float2 *)probe, d_p, (long)np, upd, scal);
         LAUNCHCHK();
+        // positions: the shifts the gradient pass took at the cycle's start
+        if (upd_pos) {
+            st = move_positions(p);
+            if (st) return st;
+        }
     }
     return PTYCHO_OK;
 }

@@ -12,7 +12,7 @@ namespace ptycho {
 // Forward row FFT of the stack's exit waves.  Block = RB consecutive rows of
 // the flattened (slot, y) row index of one probe mode (blockIdx.y); thread =
 // (row, t).  The object view is re-read per mode from the caches.
-template <int N, int MODE, bool NF>
+template <int N, int MODE, bool NF, bool SUB>
 __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     using G = RowGeom<N>;
     constexpr int E = G::E, T = G::T, RB = G::RB;
@@ -38,26 +38,30 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
     // (the object and probe rows are read again, from the caches).
     constexpr bool SPLIT = LSM && N >= 2048;
     float2 u[SPLIT ? 1 : SETS][E];
+    // the object view (and the line search's direction view) at column x:
+    // integer windows read the row, sub-pixel windows (SUB) interpolate
+    ViewRow vr{};
+    if constexpr (SUB) vr = view_row(a.Ny, a.Nx, o, a.frac[j], y);
 #pragma unroll
     for (int set = 0; set < SETS; ++set) {
         const int sl = SPLIT ? 0 : set;
-        if (SPLIT || set == 0) {
+        auto fill = [&](auto view) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int x = in_index<N, E, -1>(t, e);
-                const float2 ov = a.obj[orow + x];
+                const float2 ov = view(a.obj, x);
                 const float2 p = prow[x];
                 if constexpr (SPLIT) {
-                    const float2 dv = a.dobj[orow + x], dp = drow[x];
+                    const float2 dv = view(a.dobj, x), dp = drow[x];
                     const int q = (MODE == IN_LS2) ? set + 1 : set;
                     u[0][e] = q == 0 ? cmul(ov, p) : q == 1 ? cadd(cmul(dv, p), cmul(ov, dp)) : cmul(dv, dp);
                 } else if constexpr (MODE == IN_LS2) {
-                    const float2 dv = a.dobj[orow + x];
+                    const float2 dv = view(a.dobj, x);
                     const float2 dp = drow[x];
                     u[0][e] = cadd(cmul(dv, p), cmul(ov, dp));
                     u[1][e] = cmul(dv, dp);
                 } else if constexpr (MODE == IN_LS) {
-                    const float2 dv = a.dobj[orow + x];
+                    const float2 dv = view(a.dobj, x);
                     const float2 dp = drow[x];
                     u[0][e] = cmul(ov, p);
                     u[1][e] = cadd(cmul(dv, p), cmul(ov, dp));
@@ -70,6 +74,10 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
                     u[0][e] = cmul(ov, p);
                 }
             }
+        };
+        if (SPLIT || set == 0) {
+            if constexpr (SUB) fill([&](const float2 *b, int x) { return view_at(b, vr, x); });
+            else fill([&](const float2 *b, int x) { return b[orow + x]; });
         }
         const int tt = SPLIT ? opaque(t) : t;
         fft1d<N, E, -1>(u[sl], tt, L);
@@ -102,7 +110,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
 // the frame's term of the object numerator, to qbuf, so that the object
 // gather reads one plane per frame instead of K exit waves and K probe
 // values.
-template <int N, int K, int MODE, bool WQ, bool NF>
+template <int N, int K, int MODE, bool WQ, bool NF, bool SUB>
 __global__ __launch_bounds__(InvRowGeom<N>::TPM * K) void k_rows_inv(StackArgs a) {
     using G = InvRowGeom<N>;
     constexpr int E = G::E, T = G::T, RQ = G::RQ;
@@ -135,12 +143,14 @@ __global__ __launch_bounds__(InvRowGeom<N>::TPM * K) void k_rows_inv(StackArgs a
         orow = (size_t)(o.x + y) * a.Nx + o.y;
     }
     float2 qk[E];
+    ViewRow vr{};
+    if constexpr (SUB) vr = view_row(a.Ny, a.Nx, a.offs[j], a.frac[j], y);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int x = out_index<N, E, +1>(t, e);
         float2 v = u[e];
         if constexpr (MODE == OUT_DM) {
-            if (active) v = cadd(cmul(a.obj[orow + x], prow[x]), v);
+            if (active) v = cadd(cmul(SUB ? view_at(a.obj, vr, x) : a.obj[orow + x], prow[x]), v);
         }
         if (active) {
             if constexpr (MODE == OUT_SCR) src[scr_at<N>(y, x)] = v;

@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FLAG_BACKGROUND, FLAG_NEAR_FIELD, Desc, check, lib
+from ._lib import FLAG_BACKGROUND, FLAG_NEAR_FIELD, FLAG_POSITIONS, Desc, check, lib
 
 
 def _ptr(t: torch.Tensor) -> int:
@@ -37,6 +37,19 @@ def offsets_from_positions(pos_yx, n: int, obj_shape) -> np.ndarray:
     check(lib().ptycho_offsets_from_positions(pos.ctypes.data, j, int(n), int(obj_shape[0]),
                                               int(obj_shape[1]), out.ctypes.data))
     return out
+
+
+def windows_from_positions(pos_yx, n: int, obj_shape):
+    """Scan positions (pixels from the object centre) -> (int32 window
+    corners [J][2], float64 fractions [J][2]) of sub-pixel windows (host
+    computation inside the library)."""
+    pos = np.ascontiguousarray(pos_yx, dtype=np.float64)
+    j = pos.shape[0]
+    offs = np.empty((j, 2), dtype=np.int32)
+    frac = np.empty((j, 2), dtype=np.float64)
+    check(lib().ptycho_windows_from_positions(pos.ctypes.data, j, int(n), int(obj_shape[0]), int(obj_shape[1]),
+                                              offs.ctypes.data, frac.ctypes.data))
+    return offs, frac
 
 
 def update_positions(pos: torch.Tensor, pos0: torch.Tensor, shifts: torch.Tensor, mult: float = 1.0,
@@ -100,7 +113,7 @@ class Plan:
     def __init__(self, offsets, iobs: torch.Tensor, mask: Optional[torch.Tensor], n_modes: int,
                  obj_shape, stack: int = 0, obj_inertia: float = 1e-2, probe_inertia: float = 1e-2,
                  icalc_floor: float = 1e-20, workspace: Optional[torch.Tensor] = None,
-                 background_update: bool = False, near_field=None):
+                 background_update: bool = False, near_field=None, max_shift: Optional[float] = None):
         offs = np.ascontiguousarray(offsets, dtype=np.int32)
         if offs.ndim != 2 or offs.shape[1] != 2:
             raise ValueError("offsets must be [J][2]")
@@ -117,7 +130,9 @@ class Plan:
         self.desc = Desc(n, self.k, j, self.obj_shape[0], self.obj_shape[1], int(stack),
                          float(obj_inertia), float(probe_inertia), float(icalc_floor),
                          (FLAG_BACKGROUND if background_update else 0) |
-                         (FLAG_NEAR_FIELD if near_field is not None else 0))
+                         (FLAG_NEAR_FIELD if near_field is not None else 0) |
+                         (FLAG_POSITIONS if max_shift is not None else 0),
+                         float(max_shift) if max_shift is not None else 0.0)
         self.background = None
         nbytes = ctypes.c_size_t()
         check(lib().ptycho_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
@@ -145,6 +160,49 @@ class Plan:
         self.near_field = None
         if near_field is not None:
             self.set_near_field(near_field)
+
+    @classmethod
+    def with_positions(cls, pos_yx, iobs: torch.Tensor, mask: Optional[torch.Tensor], n_modes: int, obj_shape,
+                       max_shift: float = 2.0, mult: float = 1.0, min_grad: float = 0.1, **kw) -> "Plan":
+        """A plan on real (sub-pixel) scan positions that it refines on the
+        device (positions within max_shift pixels of their start; see
+        ptycho_plan_set_positions): windows from the positions, then the
+        positions themselves."""
+        offs, _ = windows_from_positions(pos_yx, int(iobs.shape[-1]), obj_shape)
+        plan = cls(offs, iobs, mask, n_modes, obj_shape, max_shift=max_shift, **kw)
+        plan.set_positions(pos_yx, mult, min_grad)
+        return plan
+
+    def set_positions(self, pos_yx, mult: float = 1.0, min_grad: float = 0.1) -> None:
+        """Start (and current) positions of a plan created with max_shift, and
+        the step factor and low-contrast filter of its position updates."""
+        pos = np.ascontiguousarray(pos_yx, dtype=np.float64)
+        if pos.shape != (self.j, 2):
+            raise ValueError(f"positions must be [{self.j}][2]")
+        with torch.cuda.device(self.device):
+            self._enter()
+            check(lib().ptycho_plan_set_positions(self._h, pos.ctypes.data, float(mult), float(min_grad)))
+
+    def positions(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Device float64 [J][2]: the current positions (pixels from the object centre)."""
+        out = torch.empty((self.j, 2), dtype=torch.float64, device=self.device) if out is None else out
+        _need(out, "positions", torch.float64, (self.j, 2), self.device)
+        self._enter()
+        check(lib().ptycho_plan_positions(self._h, _ptr(out)))
+        return out
+
+    def refine(self, obj, probe, psi, shifts: Optional[torch.Tensor] = None):
+        """One position-refinement step on the device from exit waves psi
+        (shifts, update, new windows); `shifts` (float64 [J][3]) receives the
+        shifts when given."""
+        self._op(obj, probe)
+        _need(psi, "psi", torch.complex64, (self.j, self.k, self.n, self.n), self.device)
+        if shifts is not None:
+            _need(shifts, "shifts", torch.float64, (self.j, 3), self.device)
+        self._enter()
+        check(lib().ptycho_refine_positions(self._h, _ptr(obj), _ptr(probe), _ptr(psi),
+                                            _ptr(shifts) if shifts is not None else None))
+        return shifts
 
     # -- helpers ---------------------------------------------------------
     def _enter(self):
@@ -188,7 +246,7 @@ class Plan:
         waves; it is allocated here when the probe is updated and none is
         given."""
         self._op(obj, probe)
-        if psi is None and (update & _lib.UPDATE_PROBE):
+        if psi is None and (update & (_lib.UPDATE_PROBE | _lib.UPDATE_POSITIONS)):
             psi = torch.empty((self.j, self.k, self.n, self.n), dtype=torch.complex64, device=self.device)
         if psi is not None:
             _need(psi, "psi", torch.complex64, (self.j, self.k, self.n, self.n), self.device)

@@ -38,8 +38,9 @@ int main() {
         std::vector<int32_t> offs(2 * (size_t)j, -7);
         EXPECT(ptycho_offsets_from_positions(pos.data(), j, n, ny, nx, offs.data()) == PTYCHO_OK);
         for (int stack : {0, 1, 3, j / 2 + 1, j}) {
-            for (uint32_t flags : {0u, (uint32_t)PTYCHO_FLAG_BACKGROUND}) {
+            for (uint32_t flags : {0u, (uint32_t)PTYCHO_FLAG_BACKGROUND, (uint32_t)PTYCHO_FLAG_POSITIONS}) {
                 ptycho_desc_t d{n, k, j, ny, nx, stack, 0.01f, 0.01f, 1e-20f, flags};
+                d.max_shift = 2.0f;
                 size_t ws = 0, tb = 0;
                 EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_OK && ws > 0 && ws % 256 == 0);
                 EXPECT(ptycho_plan_dry_run(&d, offs.data(), &tb) == PTYCHO_OK && tb > 0);
@@ -63,8 +64,24 @@ int main() {
     size_t ws = 0;
     EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_E_UNSUPPORTED);
     d.n = 64;
-    d.flags = 4;
+    d.flags = 8;
     EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_E_INVALID);
+    d.flags = PTYCHO_FLAG_POSITIONS;
+    d.max_shift = -1.0f;
+    EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_E_INVALID);
+    d.max_shift = 2.0f;
+    EXPECT(ptycho_workspace_bytes(&d, &ws) == PTYCHO_OK);
+    {
+        // sub-pixel windows: corners and fractions, and a corner outside
+        const double p2[4] = {0.25, -3.5, 100.0, 0.0};
+        int32_t wo[4] = {-7, -7, -7, -7};
+        double wf[4] = {-1, -1, -1, -1};
+        EXPECT(ptycho_windows_from_positions(p2, 2, 64, 128, 128, wo, wf) == PTYCHO_E_BOUNDS);
+        EXPECT(wo[0] == -7 && wf[0] == -1);
+        const double p1[4] = {0.25, -3.5, 10.0, 0.0};
+        EXPECT(ptycho_windows_from_positions(p1, 2, 64, 128, 128, wo, wf) == PTYCHO_OK);
+        EXPECT(wo[0] == 32 && wo[1] == 28 && wf[0] == 0.25 && wf[1] == 0.5 && wo[2] == 42 && wf[2] == 0.0);
+    }
     d.flags = PTYCHO_FLAG_NEAR_FIELD | PTYCHO_FLAG_BACKGROUND;
     size_t ws_nf = 0;
     EXPECT(ptycho_workspace_bytes(&d, &ws_nf) == PTYCHO_OK);
