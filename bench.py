@@ -435,7 +435,11 @@ def main():
                          "is 400,100; 0,0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the served mixed workload (0 = skip)")
-    ap.add_argument("--serve-seed", type=int, default=7, help="seed of the arrival trace")
+    ap.add_argument("--serve-seeds", default="7,8,9", help="seeds of the arrival traces (comma-separated)")
+    ap.add_argument("--serve-order", default="srpt", choices=("srpt", "lanes", "fifo"),
+                    help="running order of the service (srpt: least remaining work first, with the service's age "
+                         "cap; lanes: the oldest request beside the shortest others)")
+    ap.add_argument("--serve-running", type=int, default=1, help="requests given new work at a time")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -711,28 +715,36 @@ def main():
     serve = None
     if args.serve_requests > 0:
         from paper_2008_11511_amd.serve import serve_trace
+        seeds = [int(s) for s in args.serve_seeds.split(",") if s]
+        per_seed = {}
+        for seed in seeds:
+            torch.cuda.empty_cache()
+            log(f"serving, seed {seed}: {args.serve_requests} requests at {args.serve_rate} req/s, 30 DM + 20 ML "
+                f"each, order {args.serve_order}, {args.serve_running} running")
+            con, s_con = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=seed,
+                                     order=args.serve_order, max_running=args.serve_running)
+            log(f"continuous: {s_con}")
+            log("serving: same trace, sequential plain solves (one request resident at a time)")
+            seq, s_seq = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=seed,
+                                     sequential=True)
+            log(f"sequential: {s_seq}")
+            same = all(np.array_equal(a.result["obj"], b.result["obj"]) and
+                       np.array_equal(a.result["probe"], b.result["probe"]) for a, b in zip(con, seq))
+            per_seed[seed] = {
+                "continuous": s_con, "sequential": s_seq,
+                "p50_speedup": round(s_seq["p50_latency_s"] / s_con["p50_latency_s"], 3),
+                "mean_speedup": round(s_seq["mean_latency_s"] / s_con["mean_latency_s"], 3),
+                "p99_speedup": round(s_seq["p99_latency_s"] / s_con["p99_latency_s"], 3),
+                "results_identical": bool(same),
+                "mean_final_llk_per_pixel": round(float(np.mean([r.result["llk"] for r in con])), 4)}
+            del con, seq
         torch.cuda.empty_cache()
-        log(f"serving: {args.serve_requests} requests at {args.serve_rate} req/s, 30 DM + 20 ML each, "
-            f"continuous batching")
-        con, s_con = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=args.serve_seed)
-        log(f"continuous: {s_con}")
-        log("serving: same trace, sequential plain solves (one request resident at a time)")
-        seq, s_seq = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=args.serve_seed,
-                                 sequential=True)
-        log(f"sequential: {s_seq}")
-        same = all(np.array_equal(a.result["obj"], b.result["obj"]) and
-                   np.array_equal(a.result["probe"], b.result["probe"]) for a, b in zip(con, seq))
         serve = {"workload": f"{args.serve_requests} requests, Poisson arrivals at {args.serve_rate}/s, frames "
                              f"128/256/512, 200-2000 positions, 1 or 3 modes, 30 DM + 20 ML cycles each",
-                 "continuous": s_con, "sequential": s_seq,
-                 "seed": args.serve_seed,
-                 "p50_speedup": round(s_seq["p50_latency_s"] / s_con["p50_latency_s"], 3),
-                 "mean_speedup": round(s_seq["mean_latency_s"] / s_con["mean_latency_s"], 3),
-                 "p99_speedup": round(s_seq["p99_latency_s"] / s_con["p99_latency_s"], 3),
-                 "results_identical": bool(same),
-                 "mean_final_llk_per_pixel": round(float(np.mean([r.result["llk"] for r in con])), 4)}
-        del con, seq
-        torch.cuda.empty_cache()
+                 "order": args.serve_order, "max_running": args.serve_running, "seeds": per_seed,
+                 "min_speedup": {q: min(v[f"{q}_speedup"] for v in per_seed.values())
+                                 for q in ("p50", "mean", "p99")},
+                 "results_identical": all(v["results_identical"] for v in per_seed.values())}
 
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB

@@ -85,8 +85,8 @@ class Scheduler:
                  sequential: bool = False, clock: Callable[[], float] = time.perf_counter,
                  idle: Callable[[], None] = lambda: time.sleep(2e-4), max_running: Optional[int] = None,
                  order: str = "fifo", age_cap: Optional[float] = None):
-        if order not in ("fifo", "srpt"):
-            raise ValueError("order must be 'fifo' or 'srpt'")
+        if order not in ("fifo", "srpt", "lanes"):
+            raise ValueError("order must be 'fifo', 'srpt' or 'lanes'")
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_active = 1 if sequential else int(max_active)
@@ -96,7 +96,10 @@ class Scheduler:
         # by admission order or by least remaining work; with age_cap, a
         # request that arrived more than age_cap seconds ago goes before all
         # younger ones (oldest first), which bounds how long short requests
-        # can hold back a long one
+        # can hold back a long one.  "lanes": the oldest request always runs
+        # (in the order of sequential solves), and the other running slots
+        # take the least remaining work among the rest, so short requests
+        # overlap the long one on the device instead of waiting for it
         self.max_running = self.max_active if max_running is None else max(1, int(max_running))
         self.order = order
         self.age_cap = age_cap
@@ -197,6 +200,11 @@ class Scheduler:
                         return (0, r.arrival, r.rid)
                     return (1, self.ex.remaining(h), r.admitted, r.rid)
                 running.sort(key=key)
+            elif self.order == "lanes" and running:
+                oldest = min(running, key=lambda e: (e[0].arrival, e[0].rid))
+                rest = sorted((e for e in running if e is not oldest),
+                              key=lambda e: (self.ex.remaining(e[1]), e[0].admitted, e[0].rid))
+                running = [oldest] + rest
             for slot, (r, h, need) in enumerate(running[:self.max_running]):
                 self.ex.advance(h, slot)
             if not progressed:
@@ -288,6 +296,10 @@ class GpuExecutor:
         self.host = {}
         self.setup_stream = torch.cuda.Stream(device=self.dev)
         self.run_streams = []
+        # the most requests seen with chunks enqueued and not yet complete
+        # on the device at the same time (queried from their events)
+        self.max_in_flight = 0
+        self.jobs = {}
 
     # -- host preparation (outside the timed trace) -----------------------
     def prepare(self, req: Request) -> None:
@@ -444,6 +456,7 @@ class GpuExecutor:
         j.events = []
         j.final = None
         j.fresh_ml = True
+        self.jobs[req.rid] = j
         j.setup_s = time.perf_counter() - t_start
         prev, j.setup_parts = t_start, {}
         for label, t in parts:
@@ -557,6 +570,8 @@ class GpuExecutor:
                 ev.record(j.stream)
                 j.events.append(ev)
                 j.last = ev
+                busy = sum(1 for other in self.jobs.values() if any(not e.query() for e in other.events))
+                self.max_in_flight = max(self.max_in_flight, busy)
                 if j.phase == len(j.req.schedule):
                     j.llk = j.plan.llk(j.obj, j.probe, out=j.llk_buf)
                     j.out_obj.copy_(j.obj, non_blocking=True)
@@ -584,6 +599,7 @@ class GpuExecutor:
                 "llk_history": hist, "setup_s": j.setup_s, "setup_parts": j.setup_parts}
 
     def release(self, j: _Job) -> None:
+        self.jobs.pop(j.req.rid, None)
         j.plan.close()
         for name in ("plan", "iobs", "mask", "obj", "probe", "psi", "state", "llk", "llk_buf", "hist"):
             setattr(j, name, None)
@@ -769,5 +785,6 @@ def serve_trace(n_requests: int = 64, rate: float = 2.0, seed: int = 0, hbm_budg
     s["max_active"], s["max_running"], s["order"] = sch.max_active, sch.max_running, sch.order
     s["age_cap_s"] = sch.age_cap
     s["hbm_budget_GB"] = round(hbm_budget / 1e9, 1)
+    s["max_requests_in_flight"] = ex.max_in_flight
     ex.close()
     return reqs, s

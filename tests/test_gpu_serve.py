@@ -36,6 +36,31 @@ def test_results_identical_alone_and_in_the_mix():
         assert np.isfinite(a.result["llk"])
 
 
+def test_results_identical_when_requests_run_concurrently():
+    """Two running lanes (the oldest request and the shortest other one) put
+    two requests' cycles on the device at once; every result is still bitwise
+    its sequential run."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_11511_amd import lib
+    from paper_2008_11511_amd.serve import serve_trace
+    lib()
+    kw = dict(n_requests=8, rate=60.0, seed=9, sizes=(64, 128, 256), min_frames=60, max_frames=200,
+              schedule=(("dm", 6), ("ml", 4)), min_side=320)
+    say("serve: two concurrent lanes")
+    con, s_con = serve_trace(max_active=8, max_running=2, order="lanes", **kw)
+    say("serve: sequential")
+    seq, s_seq = serve_trace(sequential=True, **kw)
+    assert s_con["max_requests_in_flight"] >= 2          # two requests' work was queued on the device at once
+    assert s_seq["max_requests_in_flight"] == 1
+    assert len({(r.wl.n, r.wl.n_modes) for r in con}) >= 3
+    for a, b in zip(con, seq):
+        assert a.rid == b.rid
+        assert np.array_equal(a.result["obj"], b.result["obj"])
+        assert np.array_equal(a.result["probe"], b.result["probe"])
+        assert np.array_equal(a.result["llk_history"], b.result["llk_history"])
+
+
 def _scan(seed, n, k, j, side, mask_frac):
     """A small caller-side reconstruction problem: data from the oracle's
     forward model and a Poisson draw, starts as in the benchmarks."""

@@ -262,3 +262,36 @@ def test_near_field_requests_reserve_the_transfer_function_table():
     assert near_field_of(near.wl) == 0.05 and near_field_of(far.wl) is None
     assert near_field_of(synth.workload("nf1024")) == synth.workload("nf1024").fresnel
     assert near_field_of(synth.workload("dm256")) is None
+
+
+class LaneExecutor(QuantumExecutor):
+    """Records which request each running slot advances."""
+
+    def __init__(self):
+        super().__init__()
+        self.slots = []
+
+    def advance(self, h, slot=0):
+        self.slots.append((slot, h))
+        self.advanced.append(h)
+        self.left[h] = max(0, self.left[h] - 100)
+
+
+def test_lanes_run_the_oldest_request_beside_the_shortest_others():
+    clock = FakeClock()
+    ex = LaneExecutor()
+    long_wl = make_trace(1, rate=1.0, seed=2, max_frames=2000, min_frames=2000)[0].wl
+    short_wl = make_trace(1, rate=1.0, seed=3, max_frames=200, min_frames=200)[0].wl
+    reqs = [Request(0, 0.0, long_wl)] + [Request(i, 0.0, short_wl) for i in range(1, 4)]
+    sch = Scheduler(ex, 10**9, max_active=8, clock=clock, idle=clock.tick, order="lanes", max_running=2)
+    sch.run(reqs)
+    # the oldest request holds lane 0 from the first pass on; the short ones
+    # take lane 1 one after the other while it runs
+    assert ex.slots[0] == (0, 0)
+    lane0 = [h for s, h in ex.slots if s == 0]
+    lane1 = [h for s, h in ex.slots if s == 1]
+    assert set(lane1) == {1, 2, 3}
+    first_long_done = sch.log.index(next(e for e in sch.log if e[0] == "done" and e[1] == 0))
+    assert all(e[1] != 0 for e in sch.log[:first_long_done] if e[0] == "done") and \
+        sum(1 for e in sch.log[:first_long_done] if e[0] == "done") == 3   # the short ones finished beside it
+    assert lane0[:5] == [0] * 5
