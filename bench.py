@@ -219,38 +219,38 @@ def cpu_baseline_all_cores(wl, truth, sample, cycles, workers):
 PROFILE_SPECS = {
     "dm256_dm_cycle": {
         "title": "DM cycle, 1000 frames 256x256, 3 modes (dm256)",
-        "anchors": ["void ptycho::k_cols_joint<256, 3, 5, false>", "void ptycho::k_rows_inv<256, 3, 1, true, false>"],
-        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<256, 1, false>",
+        "anchors": ["void ptycho::k_cols_joint<256, 3, 5, false>", "void ptycho::k_rows_inv<256, 3, 1, true, false, false>"],
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<256, 1, false, false>",
                     "cols": "void ptycho::k_cols_joint<256, 3, 5, false>",
-                    "rows_inv": "void ptycho::k_rows_inv<256, 3, 1, true, false>",
+                    "rows_inv": "void ptycho::k_rows_inv<256, 3, 1, true, false, false>",
                     "gather_obj": "ptycho::k_gather_obj(",
                     "probe_all": "void ptycho::k_gather_probe<3, false>"}},
     "ml256_ml_cycle": {
         "title": "conjugate-gradient ML cycle, 500 frames 256x256, 3 modes (ml256)",
         "anchors": ["void ptycho::k_cols_joint<256, 3, 1, false>", "void ptycho::k_cols_seq<256, 6, false>"],
-        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<256, 0, false>",
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<256, 0, false, false>",
                     "cols": "void ptycho::k_cols_joint<256, 3, 1, false>",
-                    "rows_inv": "void ptycho::k_rows_inv<256, 3, 0, true, false>",
+                    "rows_inv": "void ptycho::k_rows_inv<256, 3, 0, true, false, false>",
                     "gather_obj": "ptycho::k_gather_obj(",
                     "gather_probe": "void ptycho::k_gather_probe<3, true>",
-                    "ls_rows": "void ptycho::k_rows_fwd<256, 4, false>",
+                    "ls_rows": "void ptycho::k_rows_fwd<256, 4, false, false>",
                     "ls_cols": "void ptycho::k_cols_seq<256, 6, false>"}},
     "apdm512_dm_cycle": {
         "title": "AP and DM cycles, 4000 frames 512x512, 4 modes, object 4096x4096 (apdm512)",
         "anchors": ["void ptycho::k_cols_joint<512, 4, 5, false>", "void ptycho::k_cols_joint<512, 4, 0, false>"],
-        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<512, 1, false>",
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<512, 1, false, false>",
                     "cols": "void ptycho::k_cols_joint<512, 4, 5, false>",
-                    "rows_inv": "void ptycho::k_rows_inv<512, 4, 1, true, false>",
+                    "rows_inv": "void ptycho::k_rows_inv<512, 4, 1, true, false, false>",
                     "ap_cols": "void ptycho::k_cols_joint<512, 4, 0, false>",
-                    "ap_rows_inv": "void ptycho::k_rows_inv<512, 4, 2, true, false>",
+                    "ap_rows_inv": "void ptycho::k_rows_inv<512, 4, 2, true, false, false>",
                     "gather_obj": "ptycho::k_gather_obj(",
                     "probe_all": "void ptycho::k_gather_probe<4, false>"}},
     "nf2048_dm_cycle": {
         "title": "near-field DM cycle, 17 frames 2048x2048, 1 mode (nf2048)",
-        "anchors": ["void ptycho::k_cols_joint<2048, 1, 5, true>", "void ptycho::k_rows_inv<2048, 1, 1, true, true>"],
-        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<2048, 1, true>",
+        "anchors": ["void ptycho::k_cols_joint<2048, 1, 5, true>", "void ptycho::k_rows_inv<2048, 1, 1, true, true, false>"],
+        "classes": {"rows_fwd": "void ptycho::k_rows_fwd<2048, 1, true, false>",
                     "cols": "void ptycho::k_cols_joint<2048, 1, 5, true>",
-                    "rows_inv": "void ptycho::k_rows_inv<2048, 1, 1, true, true>",
+                    "rows_inv": "void ptycho::k_rows_inv<2048, 1, 1, true, true, false>",
                     "gather_obj": "ptycho::k_gather_obj(",
                     "probe_all": "void ptycho::k_gather_probe<1, false>"}},
 }
@@ -440,6 +440,8 @@ def main():
                     help="running order of the service (srpt: least remaining work first, with the service's age "
                          "cap; lanes: the oldest request beside the shortest others)")
     ap.add_argument("--serve-running", type=int, default=1, help="requests given new work at a time")
+    ap.add_argument("--serve-age-cap", type=float, default=0.125,
+                    help="seconds after arrival during which a request may be passed by shorter ones (srpt)")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -720,9 +722,10 @@ def main():
         for seed in seeds:
             torch.cuda.empty_cache()
             log(f"serving, seed {seed}: {args.serve_requests} requests at {args.serve_rate} req/s, 30 DM + 20 ML "
-                f"each, order {args.serve_order}, {args.serve_running} running")
+                f"each, order {args.serve_order}, {args.serve_running} running, age cap {args.serve_age_cap} s")
             con, s_con = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=seed,
-                                     order=args.serve_order, max_running=args.serve_running)
+                                     order=args.serve_order, max_running=args.serve_running,
+                                     age_cap=args.serve_age_cap)
             log(f"continuous: {s_con}")
             log("serving: same trace, sequential plain solves (one request resident at a time)")
             seq, s_seq = serve_trace(n_requests=args.serve_requests, rate=args.serve_rate, seed=seed,
@@ -741,7 +744,8 @@ def main():
         torch.cuda.empty_cache()
         serve = {"workload": f"{args.serve_requests} requests, Poisson arrivals at {args.serve_rate}/s, frames "
                              f"128/256/512, 200-2000 positions, 1 or 3 modes, 30 DM + 20 ML cycles each",
-                 "order": args.serve_order, "max_running": args.serve_running, "seeds": per_seed,
+                 "order": args.serve_order, "max_running": args.serve_running,
+                 "age_cap_s": args.serve_age_cap, "seeds": per_seed,
                  "min_speedup": {q: min(v[f"{q}_speedup"] for v in per_seed.values())
                                  for q in ("p50", "mean", "p99")},
                  "results_identical": all(v["results_identical"] for v in per_seed.values())}

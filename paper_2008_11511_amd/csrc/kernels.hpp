@@ -46,68 +46,169 @@ struct PosShiftArgs {
     double *part;                 // [J][CH][5], indexed by frame j
 };
 
-// (dO/dy, dO/dx) at object pixel (Y, X): centred inside, one-sided on the
-// border, i.e. (O[hi] - O[lo]) / (hi - lo) with lo, hi the neighbours clamped
-// to the object (branch-free).
-__device__ __forceinline__ void obj_grad(const float2 *o, int Ny, int Nx, int Y, int X, float2 &gy, float2 &gx) {
-    const int ylo = max(Y - 1, 0), yhi = min(Y + 1, Ny - 1), xlo = max(X - 1, 0), xhi = min(X + 1, Nx - 1);
-    const float sy = (yhi - ylo == 2) ? 0.5f : 1.0f, sx = (xhi - xlo == 2) ? 0.5f : 1.0f;
-    const size_t row = (size_t)Y * Nx;
-    gy = cscale(csub(o[(size_t)yhi * Nx + X], o[(size_t)ylo * Nx + X]), sy);
-    gx = cscale(csub(o[row + xhi], o[row + xlo]), sx);
+// Partial sums of the position-shift systems, one chunk of R rows of one
+// frame per block.  The derivatives of the object are the centred
+// differences inside the object and one-sided ones on its border:
+// (O[hi] - O[lo]) / (hi - lo) with lo, hi the neighbours clamped to the
+// object.
+//
+// One thread walks down one column of the chunk and keeps the object rows
+// its pixels need in registers.  Per step it loads the values X-1 .. X+2 of
+// one new object row Y' (clamped to the object) and forms the row's view
+// along x and that of its x derivative,
+//   H(Y') = sum_b w_b O[Y'][X+b],   D(Y') = sum_b w_b dO/dx[Y'][X+b]
+// (w = (1 - fx, fx); integer windows: one term, w = 1).  A pixel at object
+// row Y then takes everything from rows Y-1 .. Y+2 (v = (1 - fy, fy)):
+//   view  = sum_a v_a H(Y+a)
+//   dO/dx = sum_a v_a D(Y+a)
+//   dO/dy = sum_a v_a (H(hi(Y+a)) - H(lo(Y+a))) / (hi - lo)
+// i.e. the bilinear views of the object and of its two derivatives, with
+// three or four object loads per pixel instead of five per corner.
+struct ShiftRow {
+    float2 h, d;
+};
+// The object values X-1, X, X+1 (and X+2 for sub-pixel windows) of row Y,
+// clamped to the object: loaded one row ahead of their use.
+struct RawRow {
+    float2 a, b, c, e;
+};
+template <bool SUB>
+__device__ __forceinline__ RawRow load_row(const float2 *o, int Nx, int Y, int X) {
+    const float2 *row = o + (size_t)Y * Nx;
+    RawRow r;
+    r.a = row[max(X - 1, 0)];
+    r.b = row[X];
+    r.c = row[min(X + 1, Nx - 1)];
+    r.e = SUB ? row[min(X + 2, Nx - 1)] : make_float2(0.0f, 0.0f);
+    return r;
+}
+template <bool SUB>
+__device__ __forceinline__ ShiftRow make_row(const RawRow &r, int Nx, int X, float wx0, float wx1) {
+    const int xm = max(X - 1, 0), x1 = min(X + 1, Nx - 1);
+    const float2 d0 = cscale(csub(r.c, r.a), (x1 - xm == 2) ? 0.5f : 1.0f);
+    ShiftRow w;
+    if constexpr (!SUB) {
+        w.h = r.b;
+        w.d = d0;
+    } else {
+        // column X1 = x1: neighbours X (or xm on the last column) and X+2
+        const int x2 = min(X + 2, Nx - 1), lo1 = max(x1 - 1, 0);
+        const float2 l1 = (lo1 == X) ? r.b : r.a;
+        const float2 d1 = cscale(csub(r.e, l1), (x2 - lo1 == 2) ? 0.5f : 1.0f);
+        w.h = make_float2(__builtin_fmaf(wx1, r.c.x, wx0 * r.b.x), __builtin_fmaf(wx1, r.c.y, wx0 * r.b.y));
+        w.d = make_float2(__builtin_fmaf(wx1, d1.x, wx0 * d0.x), __builtin_fmaf(wx1, d1.y, wx0 * d0.y));
+    }
+    return w;
 }
 
+template <int K, bool SUB>
 __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
-    const int c = blockIdx.x % a.CH, f = blockIdx.x / a.CH, N = a.N;
+    // the chunks of a frame, and neighbouring frames, on one XCD: their
+    // object rows overlap and are served by that XCD's L2
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int c = b % a.CH, f = b / a.CH, N = a.N;
     const int j = a.order != nullptr ? a.order[a.s0 + f] : f;
     const int2 o = a.offs[j];
-    const bool sub = a.frac != nullptr;
-    const float2 fr = sub ? a.frac[j] : make_float2(0.0f, 0.0f);
+    const float2 fr = SUB ? a.frac[j] : make_float2(0.0f, 0.0f);
+    const float vy0 = 1.0f - fr.x, vy1 = fr.x, wx0 = 1.0f - fr.y, wx1 = fr.y;
     const size_t n2 = (size_t)N * N;
-    const size_t pbase = (size_t)(a.by_slot ? f : j) * a.K * n2;
+    const float2 *psi = a.psi + (size_t)(a.by_slot ? f : j) * K * n2;
+    // the thread's columns: one column of ceil(R / G) rows (G = 256 / N
+    // row groups) up to N = 256, N / 256 columns of R rows beyond
+    const int tid = threadIdx.x;
+    int ncol, rows, x0, ylo;
+    if (N <= 256) {
+        const int G = 256 >> a.lgN, rt = (a.R + G - 1) / G, gi = tid >> a.lgN;
+        x0 = tid & (N - 1);
+        ylo = gi * rt;
+        rows = max(0, min(a.R - ylo, rt));
+        ncol = rows > 0 ? 1 : 0;      // groups past the chunk's rows read nothing
+    } else {
+        ncol = N >> 8;
+        x0 = tid;
+        ylo = 0;
+        rows = a.R;
+    }
+    // the newest object row a pixel at row Y needs: Y + 1, or Y + 2 for
+    // sub-pixel windows
+    constexpr int LEAD = SUB ? 2 : 1;
     double syy = 0.0, sxx = 0.0, sxy = 0.0, by = 0.0, bx = 0.0;
-    const int npix = a.R * N;
-    for (int idx = threadIdx.x; idx < npix; idx += 256) {
-        const int y = c * a.R + (idx >> a.lgN), x = idx & (N - 1);
-        float2 ov, gy, gx;
-        if (!sub) {
-            ov = a.obj[(size_t)(o.x + y) * a.Nx + o.y + x];
-            obj_grad(a.obj, a.Ny, a.Nx, o.x + y, o.y + x, gy, gx);
-        } else {
-            const float wy[2] = {1.0f - fr.x, fr.x}, wx[2] = {1.0f - fr.y, fr.y};
-            ov = gy = gx = make_float2(0.0f, 0.0f);
+    for (int m = 0; m < ncol; ++m) {
+        const int x = x0 + (m << 8);
+        const int X = o.y + x;
+        const int y0 = c * a.R + ylo, ylast_px = y0 + rows - 1;
+        const int Y0 = o.x + y0;
+        const int ylast = a.Ny - 1;
+        // each step loads the next pixel row's exit waves and probe and the
+        // object row after its window, while it works on the current row
+        auto load_px = [&](int y, float2 (&ps)[K], float2 (&pr)[K]) {
+            const size_t pix = tiled_at(y, x, N, a.lw);
 #pragma unroll
-            for (int ay = 0; ay < 2; ++ay)
+            for (int k = 0; k < K; ++k) {
+                ps[k] = ld_stream(psi + (size_t)k * n2 + pix);   // read once: keep L2 for the object
+                pr[k] = a.probe[(size_t)k * n2 + (size_t)y * N + x];
+            }
+        };
+        float2 ps[K], pr[K];
+        load_px(y0, ps, pr);
+        RawRow rn = load_row<SUB>(a.obj, a.Nx, min(Y0 + LEAD, ylast), X);
+        // rows Y-1, Y (and Y+1) of the first pixel, clamped
+        ShiftRow wm = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, max(Y0 - 1, 0), X), a.Nx, X, wx0, wx1);
+        ShiftRow w0 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, Y0, X), a.Nx, X, wx0, wx1);
+        ShiftRow w1{};
+        if constexpr (SUB) w1 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, min(Y0 + 1, ylast), X), a.Nx, X, wx0, wx1);
+        for (int i = 0; i < rows; ++i) {
+            const int y = y0 + i, Y = Y0 + i;
+            // prefetch (the last step loads its own row again, in bounds)
+            float2 ps2[K], pr2[K];
+            load_px(min(y + 1, ylast_px), ps2, pr2);
+            const RawRow rn2 = load_row<SUB>(a.obj, a.Nx, min(Y + 1 + LEAD, ylast), X);
+            const ShiftRow wl = make_row<SUB>(rn, a.Nx, X, wx0, wx1);     // row Y + LEAD
+            const int Ym = max(Y - 1, 0), Y1 = min(Y + 1, ylast), Y2 = min(Y + 2, ylast);
+            float2 ov, gy, gx;
+            if constexpr (SUB) {
+                const float2 gy0 = cscale(csub(w1.h, wm.h), (Y1 - Ym == 2) ? 0.5f : 1.0f);
+                const float2 gy1 = cscale(csub(wl.h, w0.h), (Y2 - Y == 2) ? 0.5f : 1.0f);
+                ov = make_float2(__builtin_fmaf(vy1, w1.h.x, vy0 * w0.h.x), __builtin_fmaf(vy1, w1.h.y, vy0 * w0.h.y));
+                gx = make_float2(__builtin_fmaf(vy1, w1.d.x, vy0 * w0.d.x), __builtin_fmaf(vy1, w1.d.y, vy0 * w0.d.y));
+                gy = make_float2(__builtin_fmaf(vy1, gy1.x, vy0 * gy0.x), __builtin_fmaf(vy1, gy1.y, vy0 * gy0.y));
+            } else {
+                ov = w0.h;
+                gx = w0.d;
+                gy = cscale(csub(wl.h, wm.h), (Y1 - Ym == 2) ? 0.5f : 1.0f);
+            }
+            float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
 #pragma unroll
-                for (int bx2 = 0; bx2 < 2; ++bx2) {
-                    const float w = wy[ay] * wx[bx2];
-                    const int Y = min(o.x + y + ay, a.Ny - 1), X = min(o.y + x + bx2, a.Nx - 1);
-                    float2 g1, g2;
-                    obj_grad(a.obj, a.Ny, a.Nx, Y, X, g1, g2);
-                    const float2 v = a.obj[(size_t)Y * a.Nx + X];
-                    ov = make_float2(ov.x + w * v.x, ov.y + w * v.y);
-                    gy = make_float2(gy.x + w * g1.x, gy.y + w * g1.y);
-                    gx = make_float2(gx.x + w * g2.x, gx.y + w * g2.y);
-                }
+            for (int k = 0; k < K; ++k) {
+                const float2 p = pr[k];
+                const float2 chi = a.ml ? cscale(ps[k], a.chi_scale) : csub(ps[k], cmul(p, ov));
+                const float2 Gy = cmul(p, gy), Gx = cmul(p, gx);
+                fyy += cnorm(Gy);
+                fxx += cnorm(Gx);
+                fxy += cmulc(Gy, Gx).x;
+                fby += cmulc(Gy, chi).x;
+                fbx += cmulc(Gx, chi).x;
+            }
+            syy += fyy;
+            sxx += fxx;
+            sxy += fxy;
+            by += fby;
+            bx += fbx;
+            // slide the window down one row
+            wm = w0;
+            if constexpr (SUB) {
+                w0 = w1;
+                w1 = wl;
+            } else {
+                w0 = wl;
+            }
+            rn = rn2;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                ps[k] = ps2[k];
+                pr[k] = pr2[k];
+            }
         }
-        const size_t pix = tiled_at(y, x, N, a.lw);
-        float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
-        for (int k = 0; k < a.K; ++k) {
-            const float2 p = a.probe[(size_t)k * n2 + (size_t)y * N + x];
-            const float2 ps = a.psi[pbase + (size_t)k * n2 + pix];
-            const float2 chi = a.ml ? cscale(ps, a.chi_scale) : csub(ps, cmul(p, ov));
-            const float2 Gy = cmul(p, gy), Gx = cmul(p, gx);
-            fyy += cnorm(Gy);
-            fxx += cnorm(Gx);
-            fxy += cmulc(Gy, Gx).x;
-            fby += cmulc(Gy, chi).x;
-            fbx += cmulc(Gx, chi).x;
-        }
-        syy += fyy;
-        sxx += fxx;
-        sxy += fxy;
-        by += fby;
-        bx += fbx;
     }
     syy = block_sum(syy);
     sxx = block_sum(sxx);

@@ -945,7 +945,19 @@ static int launch_shifts(ptycho_plan_s *p, const float *obj, const float *probe,
     a.chi_scale = -0.5f;
     a.part = p->pspart;
     Timed tm(p, TC_OTHER);
-    hipLaunchKernelGGL(k_pos_shift_part, dim3((unsigned)a.CH * (unsigned)nf), dim3(256), 0, p->stream, a);
+    const dim3 grid((unsigned)a.CH * (unsigned)nf);
+    const bool sub = a.frac != nullptr;
+    switch (a.K * 2 + (sub ? 1 : 0)) {
+        case 2: hipLaunchKernelGGL((k_pos_shift_part<1, false>), grid, dim3(256), 0, p->stream, a); break;
+        case 3: hipLaunchKernelGGL((k_pos_shift_part<1, true>), grid, dim3(256), 0, p->stream, a); break;
+        case 4: hipLaunchKernelGGL((k_pos_shift_part<2, false>), grid, dim3(256), 0, p->stream, a); break;
+        case 5: hipLaunchKernelGGL((k_pos_shift_part<2, true>), grid, dim3(256), 0, p->stream, a); break;
+        case 6: hipLaunchKernelGGL((k_pos_shift_part<3, false>), grid, dim3(256), 0, p->stream, a); break;
+        case 7: hipLaunchKernelGGL((k_pos_shift_part<3, true>), grid, dim3(256), 0, p->stream, a); break;
+        case 8: hipLaunchKernelGGL((k_pos_shift_part<4, false>), grid, dim3(256), 0, p->stream, a); break;
+        case 9: hipLaunchKernelGGL((k_pos_shift_part<4, true>), grid, dim3(256), 0, p->stream, a); break;
+        default: return fail(PTYCHO_E_INVALID, "internal: modes outside 1..4");
+    }
     hipLaunchKernelGGL(k_pos_shift_finish, dim3((nf + 255) / 256), dim3(256), 0, p->stream, p->pspart, a.CH, order,
                        s0, nf, out);
     LAUNCHCHK();

@@ -73,7 +73,7 @@ def test_rocprof_summary_from_synthetic_csvs(tmp_path):
             w.writerow(header)
             w.writerows(rows)
 
-    k_inv = "void ptycho::k_rows_inv<256, 3, 1, true, false>(ptycho::StackArgs)"
+    k_inv = "void ptycho::k_rows_inv<256, 3, 1, true, false, false>(ptycho::StackArgs)"
     k_obj = "ptycho::k_gather_obj(ptycho::ObjTileArgs)"
     copy = "__amd_rocclr_copyBuffer"
     th = ["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Grid_Size_Y",
@@ -110,4 +110,4 @@ def test_rocprof_summary_from_synthetic_csvs(tmp_path):
     obj = tr["cycles"]["dm256_dm_cycle"]["gather_obj"]
     assert obj["grid"] == 256 and obj["launches"] == 1         # the other plan's gather is outside the window
     text = (out / "dm256_dm_cycle.md").read_text()
-    assert "the command" in text and "k_rows_inv<256, 3, 1, true, false>" in text
+    assert "the command" in text and "k_rows_inv<256, 3, 1, true, false, false>" in text
