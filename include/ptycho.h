@@ -208,7 +208,8 @@ PTYCHO_API int ptycho_plan_set_background(ptycho_plan_t plan, float *bg_dev);
  * out_dev: double[J][3] device, per frame (d_y, d_x, gradient energy
  * S_yy + S_xx) in pixels, frames in scan order.  The caller moves the
  * positions (the paper's filter leaves frames of low gradient energy in
- * place) and builds a plan from the new offsets. */
+ * place) and builds a plan from the new offsets.  probe_dev and psi_dev must
+ * be 16-byte aligned (PTYCHO_E_INVALID otherwise; torch allocations are). */
 PTYCHO_API int ptycho_position_shifts(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                            const float *psi_dev, double *out_dev);
 
@@ -258,7 +259,9 @@ PTYCHO_API int ptycho_plan_positions(ptycho_plan_t plan, double *pos_yx_dev);
  * the plan's start positions, max_shift, mult and min_grad, and the new
  * windows: all on the device, enqueued.  shifts_dev (nullable,
  * double[J][3]) receives the shifts.  ptycho_ap_cycle and ptycho_ml_cycle
- * do the same every cycle with PTYCHO_UPDATE_POSITIONS. */
+ * do the same every cycle with PTYCHO_UPDATE_POSITIONS.  As for
+ * ptycho_position_shifts, probe_dev and psi_dev must be 16-byte aligned
+ * (also in those cycles). */
 PTYCHO_API int ptycho_refine_positions(ptycho_plan_t plan, const float *obj_dev, const float *probe_dev,
                                        const float *psi_dev, double *shifts_dev);
 

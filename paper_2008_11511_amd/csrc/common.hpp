@@ -120,6 +120,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 __device__ __forceinline__ float2 ld_stream(const float2 *p) {
     return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
+// Two adjacent complex values in one 16-byte non-temporal load (p 16-byte
+// aligned).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_stream2(const float2 *p) {
+    const f32x4 v = __builtin_nontemporal_load((const f32x4 *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
 
 // Streaming store: data written once and not read again before much more
 // has passed through the caches: the exit waves, the forward rows' stack and

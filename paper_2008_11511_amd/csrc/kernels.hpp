@@ -52,9 +52,10 @@ struct PosShiftArgs {
 // (O[hi] - O[lo]) / (hi - lo) with lo, hi the neighbours clamped to the
 // object.
 //
-// One thread walks down one column of the chunk and keeps the object rows
-// its pixels need in registers.  Per step it loads the values X-1 .. X+2 of
-// one new object row Y' (clamped to the object) and forms the row's view
+// One thread walks down two adjacent columns (x, x + 1) of its chunk and
+// keeps the object rows its pixels need in registers.  Per row of the walk it
+// loads the object values X-1 .. X+2 (and X+3 for sub-pixel windows) of one
+// new row (clamped to the object) and forms, for both pixels, the row's view
 // along x and that of its x derivative,
 //   H(Y') = sum_b w_b O[Y'][X+b],   D(Y') = sum_b w_b dO/dx[Y'][X+b]
 // (w = (1 - fx, fx); integer windows: one term, w = 1).  A pixel at object
@@ -62,41 +63,47 @@ struct PosShiftArgs {
 //   view  = sum_a v_a H(Y+a)
 //   dO/dx = sum_a v_a D(Y+a)
 //   dO/dy = sum_a v_a (H(hi(Y+a)) - H(lo(Y+a))) / (hi - lo)
-// i.e. the bilinear views of the object and of its two derivatives, with
-// three or four object loads per pixel instead of five per corner.
-struct ShiftRow {
-    float2 h, d;
-};
-// The object values X-1, X, X+1 (and X+2 for sub-pixel windows) of row Y,
-// clamped to the object: loaded one row ahead of their use.
+// i.e. the bilinear views of the object and of its two derivatives.  The two
+// columns' exit waves and probe values arrive in one 16-byte load each.
 struct RawRow {
-    float2 a, b, c, e;
+    float2 v[5];                 // O[Y][clamp(X - 1 + i)]
+};
+struct ShiftRow {
+    float2 h[2], d[2];           // per pixel of the pair
 };
 template <bool SUB>
 __device__ __forceinline__ RawRow load_row(const float2 *o, int Nx, int Y, int X) {
     const float2 *row = o + (size_t)Y * Nx;
     RawRow r;
-    r.a = row[max(X - 1, 0)];
-    r.b = row[X];
-    r.c = row[min(X + 1, Nx - 1)];
-    r.e = SUB ? row[min(X + 2, Nx - 1)] : make_float2(0.0f, 0.0f);
+    r.v[0] = row[max(X - 1, 0)];
+    r.v[1] = row[X];
+    r.v[2] = row[min(X + 1, Nx - 1)];
+    r.v[3] = row[min(X + 2, Nx - 1)];
+    r.v[4] = SUB ? row[min(X + 3, Nx - 1)] : make_float2(0.0f, 0.0f);
     return r;
+}
+// dO/dx at column c, whose clamped neighbours are r.v[i - 1] and r.v[i + 1]
+__device__ __forceinline__ float2 row_dx(const RawRow &r, int i, int c, int Nx) {
+    return cscale(csub(r.v[i + 1], r.v[i - 1]), (min(c + 1, Nx - 1) - max(c - 1, 0) == 2) ? 0.5f : 1.0f);
 }
 template <bool SUB>
 __device__ __forceinline__ ShiftRow make_row(const RawRow &r, int Nx, int X, float wx0, float wx1) {
-    const int xm = max(X - 1, 0), x1 = min(X + 1, Nx - 1);
-    const float2 d0 = cscale(csub(r.c, r.a), (x1 - xm == 2) ? 0.5f : 1.0f);
     ShiftRow w;
-    if constexpr (!SUB) {
-        w.h = r.b;
-        w.d = d0;
-    } else {
-        // column X1 = x1: neighbours X (or xm on the last column) and X+2
-        const int x2 = min(X + 2, Nx - 1), lo1 = max(x1 - 1, 0);
-        const float2 l1 = (lo1 == X) ? r.b : r.a;
-        const float2 d1 = cscale(csub(r.e, l1), (x2 - lo1 == 2) ? 0.5f : 1.0f);
-        w.h = make_float2(__builtin_fmaf(wx1, r.c.x, wx0 * r.b.x), __builtin_fmaf(wx1, r.c.y, wx0 * r.b.y));
-        w.d = make_float2(__builtin_fmaf(wx1, d1.x, wx0 * d0.x), __builtin_fmaf(wx1, d1.y, wx0 * d0.y));
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int i = 1 + p, c = X + p;
+        const float2 d0 = row_dx(r, i, c, Nx);
+        if constexpr (!SUB) {
+            w.h[p] = r.v[i];
+            w.d[p] = d0;
+        } else {
+            // the second column min(c + 1, Nx - 1) weighs fx, which is 0
+            // whenever c is the object's last column
+            const float2 d1 = row_dx(r, i + 1, c + 1, Nx);
+            const float2 b = r.v[i], e = r.v[i + 1];
+            w.h[p] = make_float2(__builtin_fmaf(wx1, e.x, wx0 * b.x), __builtin_fmaf(wx1, e.y, wx0 * b.y));
+            w.d[p] = make_float2(__builtin_fmaf(wx1, d1.x, wx0 * d0.x), __builtin_fmaf(wx1, d1.y, wx0 * d0.y));
+        }
     }
     return w;
 }
@@ -113,19 +120,19 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
     const float vy0 = 1.0f - fr.x, vy1 = fr.x, wx0 = 1.0f - fr.y, wx1 = fr.y;
     const size_t n2 = (size_t)N * N;
     const float2 *psi = a.psi + (size_t)(a.by_slot ? f : j) * K * n2;
-    // the thread's columns: one column of ceil(R / G) rows (G = 256 / N
-    // row groups) up to N = 256, N / 256 columns of R rows beyond
-    const int tid = threadIdx.x;
-    int ncol, rows, x0, ylo;
-    if (N <= 256) {
-        const int G = 256 >> a.lgN, rt = (a.R + G - 1) / G, gi = tid >> a.lgN;
-        x0 = tid & (N - 1);
+    // the thread's column pairs: one pair of ceil(R / G) rows (G = 256 / (N/2)
+    // row groups) up to N = 512, N / 512 pairs of R rows beyond
+    const int tid = threadIdx.x, lgP = a.lgN - 1, NP = N >> 1;
+    int npair, rows, x0, ylo;
+    if (NP <= 256) {
+        const int G = 256 >> lgP, rt = (a.R + G - 1) / G, gi = tid >> lgP;
+        x0 = 2 * (tid & (NP - 1));
         ylo = gi * rt;
         rows = max(0, min(a.R - ylo, rt));
-        ncol = rows > 0 ? 1 : 0;      // groups past the chunk's rows read nothing
+        npair = rows > 0 ? 1 : 0;     // groups past the chunk's rows read nothing
     } else {
-        ncol = N >> 8;
-        x0 = tid;
+        npair = NP >> 8;
+        x0 = 2 * tid;
         ylo = 0;
         rows = a.R;
     }
@@ -133,67 +140,79 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
     // sub-pixel windows
     constexpr int LEAD = SUB ? 2 : 1;
     double syy = 0.0, sxx = 0.0, sxy = 0.0, by = 0.0, bx = 0.0;
-    for (int m = 0; m < ncol; ++m) {
-        const int x = x0 + (m << 8);
+    for (int m = 0; m < npair; ++m) {
+        const int x = x0 + (m << 9);
         const int X = o.y + x;
         const int y0 = c * a.R + ylo, ylast_px = y0 + rows - 1;
         const int Y0 = o.x + y0;
         const int ylast = a.Ny - 1;
         // each step loads the next pixel row's exit waves and probe and the
         // object row after its window, while it works on the current row
-        auto load_px = [&](int y, float2 (&ps)[K], float2 (&pr)[K]) {
+        auto load_px = [&](int y, float4 (&ps)[K], float4 (&pr)[K]) {
             const size_t pix = tiled_at(y, x, N, a.lw);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                ps[k] = ld_stream(psi + (size_t)k * n2 + pix);   // read once: keep L2 for the object
-                pr[k] = a.probe[(size_t)k * n2 + (size_t)y * N + x];
+                // read once: non-temporal, to keep L2 for the object
+                ps[k] = ld_stream2(psi + (size_t)k * n2 + pix);
+                pr[k] = *(const float4 *)(a.probe + (size_t)k * n2 + (size_t)y * N + x);
             }
         };
-        float2 ps[K], pr[K];
+        float4 ps[K], pr[K];
         load_px(y0, ps, pr);
         RawRow rn = load_row<SUB>(a.obj, a.Nx, min(Y0 + LEAD, ylast), X);
-        // rows Y-1, Y (and Y+1) of the first pixel, clamped
+        // rows Y-1, Y (and Y+1) of the first pixel row, clamped
         ShiftRow wm = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, max(Y0 - 1, 0), X), a.Nx, X, wx0, wx1);
         ShiftRow w0 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, Y0, X), a.Nx, X, wx0, wx1);
         ShiftRow w1{};
         if constexpr (SUB) w1 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, min(Y0 + 1, ylast), X), a.Nx, X, wx0, wx1);
+        // fp32 sums over the walk's rows (at most 32 terms), fp64 beyond
+        float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
         for (int i = 0; i < rows; ++i) {
             const int y = y0 + i, Y = Y0 + i;
             // prefetch (the last step loads its own row again, in bounds)
-            float2 ps2[K], pr2[K];
+            float4 ps2[K], pr2[K];
             load_px(min(y + 1, ylast_px), ps2, pr2);
             const RawRow rn2 = load_row<SUB>(a.obj, a.Nx, min(Y + 1 + LEAD, ylast), X);
             const ShiftRow wl = make_row<SUB>(rn, a.Nx, X, wx0, wx1);     // row Y + LEAD
             const int Ym = max(Y - 1, 0), Y1 = min(Y + 1, ylast), Y2 = min(Y + 2, ylast);
-            float2 ov, gy, gx;
-            if constexpr (SUB) {
-                const float2 gy0 = cscale(csub(w1.h, wm.h), (Y1 - Ym == 2) ? 0.5f : 1.0f);
-                const float2 gy1 = cscale(csub(wl.h, w0.h), (Y2 - Y == 2) ? 0.5f : 1.0f);
-                ov = make_float2(__builtin_fmaf(vy1, w1.h.x, vy0 * w0.h.x), __builtin_fmaf(vy1, w1.h.y, vy0 * w0.h.y));
-                gx = make_float2(__builtin_fmaf(vy1, w1.d.x, vy0 * w0.d.x), __builtin_fmaf(vy1, w1.d.y, vy0 * w0.d.y));
-                gy = make_float2(__builtin_fmaf(vy1, gy1.x, vy0 * gy0.x), __builtin_fmaf(vy1, gy1.y, vy0 * gy0.y));
-            } else {
-                ov = w0.h;
-                gx = w0.d;
-                gy = cscale(csub(wl.h, wm.h), (Y1 - Ym == 2) ? 0.5f : 1.0f);
-            }
-            float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
+            const float sy0 = (Y1 - Ym == 2) ? 0.5f : 1.0f, sy1 = (Y2 - Y == 2) ? 0.5f : 1.0f;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float2 p = pr[k];
-                const float2 chi = a.ml ? cscale(ps[k], a.chi_scale) : csub(ps[k], cmul(p, ov));
-                const float2 Gy = cmul(p, gy), Gx = cmul(p, gx);
-                fyy += cnorm(Gy);
-                fxx += cnorm(Gx);
-                fxy += cmulc(Gy, Gx).x;
-                fby += cmulc(Gy, chi).x;
-                fbx += cmulc(Gx, chi).x;
+            for (int p = 0; p < 2; ++p) {
+                float2 ov, gy, gx;
+                if constexpr (SUB) {
+                    const float2 gy0 = cscale(csub(w1.h[p], wm.h[p]), sy0);
+                    const float2 gy1 = cscale(csub(wl.h[p], w0.h[p]), sy1);
+                    ov = make_float2(__builtin_fmaf(vy1, w1.h[p].x, vy0 * w0.h[p].x),
+                                     __builtin_fmaf(vy1, w1.h[p].y, vy0 * w0.h[p].y));
+                    gx = make_float2(__builtin_fmaf(vy1, w1.d[p].x, vy0 * w0.d[p].x),
+                                     __builtin_fmaf(vy1, w1.d[p].y, vy0 * w0.d[p].y));
+                    gy = make_float2(__builtin_fmaf(vy1, gy1.x, vy0 * gy0.x), __builtin_fmaf(vy1, gy1.y, vy0 * gy0.y));
+                } else {
+                    ov = w0.h[p];
+                    gx = w0.d[p];
+                    gy = cscale(csub(wl.h[p], wm.h[p]), sy0);
+                }
+                // the modes enter through Q = sum_k conj(P_k) Psi_k and
+                // P2 = sum_k |P_k|^2: sum_k |P_k g|^2 = P2 |g|^2 and
+                // sum_k conj(P_k g) chi_k = conj(g) c with c = Q - P2 O_view
+                // (AP) or c = scale Q (ML)
+                float2 q = make_float2(0.0f, 0.0f);
+                float p2 = 0.0f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float2 pk = p ? make_float2(pr[k].z, pr[k].w) : make_float2(pr[k].x, pr[k].y);
+                    const float2 sk = p ? make_float2(ps[k].z, ps[k].w) : make_float2(ps[k].x, ps[k].y);
+                    const float2 mk = cmulc(pk, sk);
+                    q = make_float2(q.x + mk.x, q.y + mk.y);
+                    p2 += cnorm(pk);
+                }
+                const float2 cc = a.ml ? cscale(q, a.chi_scale) : csub(q, cscale(ov, p2));
+                fyy += p2 * cnorm(gy);
+                fxx += p2 * cnorm(gx);
+                fxy += p2 * cmulc(gy, gx).x;
+                fby += cmulc(gy, cc).x;
+                fbx += cmulc(gx, cc).x;
             }
-            syy += fyy;
-            sxx += fxx;
-            sxy += fxy;
-            by += fby;
-            bx += fbx;
             // slide the window down one row
             wm = w0;
             if constexpr (SUB) {
@@ -209,6 +228,11 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
                 pr[k] = pr2[k];
             }
         }
+        syy += fyy;
+        sxx += fxx;
+        sxy += fxy;
+        by += fby;
+        bx += fbx;
     }
     syy = block_sum(syy);
     sxx = block_sum(sxx);

@@ -115,7 +115,7 @@ static int window_margin(const ptycho_desc_t &d) {
 }
 
 // Rows per chunk of the position-shift sums: about 4096 pixels per block.
-static int pos_rows(int n) { return std::max(1, std::min(n, 4096 / n)); }
+static int pos_rows(int n) { return std::max(1, std::min(n, 8192 / n)); }
 
 // Frames per launch.  The stack kernels are bandwidth-bound and do not keep
 // data in cache from one launch to the next, so larger launches (fewer
@@ -807,6 +807,14 @@ static int check_prop_ptrs(ptycho_plan_t p, const void *a, const void *b) {
     return st ? st : check_geometry(p);
 }
 
+// The position-shift kernel reads two pixels' exit waves and probe values in
+// one 16-byte load.
+static int check_shift_align(const void *probe, const void *psi) {
+    if (((uintptr_t)probe | (uintptr_t)psi) % 16)
+        return fail(PTYCHO_E_INVALID, "position shifts need 16-byte aligned probe and exit waves");
+    return PTYCHO_OK;
+}
+
 // AP (kind 0) or DM (kind 1) cycles: projection with the per-stack object
 // sums, object normalisation, then the probe sums over all frames with the
 // new object and the probe normalisation.
@@ -819,6 +827,7 @@ static int run_cycles(ptycho_plan_t p, float *obj, float *probe, float *psi, int
     if (upd_pos && !p->pos_ready)
         return fail(PTYCHO_E_INVALID, "a position update needs a plan with positions (ptycho_plan_set_positions)");
     if (upd_pos && !psi) return fail(PTYCHO_E_INVALID, "a position update needs exit-wave storage (psi)");
+    if (upd_pos && (st = check_shift_align(probe, psi))) return st;
     const bool upd_bg = (upd & PTYCHO_UPDATE_BACKGROUND) != 0;
     if (upd_bg && !p->bg) return fail(PTYCHO_E_INVALID, "a background update needs a background (set_background)");
     if (upd_bg && !p->s2)
@@ -973,6 +982,7 @@ extern "C" int ptycho_position_shifts(ptycho_plan_t p, const float *obj, const f
     int st = check_plan_ptrs(p, obj, probe);
     if (st) return st;
     if (!psi || !out) return fail(PTYCHO_E_INVALID, "null psi or output");
+    if ((st = check_shift_align(probe, psi))) return st;
     return launch_shifts(p, obj, probe, (const float2 *)psi, ilog2(p->d.n), false, nullptr, 0, p->d.n_frames, false,
                          out);
 }
@@ -1047,6 +1057,7 @@ extern "C" int ptycho_refine_positions(ptycho_plan_t p, const float *obj, const 
     if (st) return st;
     if (!psi) return fail(PTYCHO_E_INVALID, "null psi");
     if (!p->pos_ready) return fail(PTYCHO_E_INVALID, "the plan has no positions (ptycho_plan_set_positions)");
+    if ((st = check_shift_align(probe, psi))) return st;
     st = launch_shifts(p, obj, probe, (const float2 *)psi, ilog2(p->d.n), false, nullptr, 0, p->d.n_frames, false,
                        p->shifts);
     if (!st) st = move_positions(p);
@@ -1171,6 +1182,7 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
     const bool upd_pos = (upd & PTYCHO_UPDATE_POSITIONS) != 0;
     if (upd_pos && !p->pos_ready)
         return fail(PTYCHO_E_INVALID, "a position update needs a plan with positions (ptycho_plan_set_positions)");
+    if (upd_pos && (st = check_shift_align(probe, nullptr))) return st;
     upd &= 3u;
     const size_t no = (size_t)p->d.obj_ny * p->d.obj_nx, np = (size_t)p->d.n_modes * p->d.n * p->d.n;
     char *b = (char *)state;

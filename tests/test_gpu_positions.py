@@ -196,3 +196,35 @@ def test_positions_stay_within_max_shift_and_the_object(dev):
     assert np.isclose(np.abs(gpos - pos0).max(), 0.75)       # the bound is reached and holds
     oracle.windows_from_positions(gpos, pb.wl.n, pb.wl.obj_shape)     # inside the object
     assert np.isfinite(host(o)).all()
+
+
+def test_position_shifts_refuse_misaligned_arrays_before_any_work(dev):
+    """The shift kernel reads two pixels in one 16-byte load: exit waves or a
+    probe that are only 8-byte aligned are refused by the host checks."""
+    from paper_2008_11511_amd import PtychoError
+    pb, pos_true, pos0, iobs = subpixel_problem(seed_offset=5)
+    wl = pb.wl
+    say("misaligned exit waves and probe are refused")
+    plan = make_positions_plan(pb, iobs, pos0, dev)
+    o, p = t_(pb.obj0, dev, torch.complex64), t_(pb.probe0, dev, torch.complex64)
+    shape = (wl.n_frames, wl.n_modes, wl.n, wl.n)
+    n_psi = int(np.prod(shape))
+    big = torch.zeros(n_psi + 1, dtype=torch.complex64, device=dev)
+    psi_bad = big[1:].view(shape)
+    assert psi_bad.data_ptr() % 16 == 8
+    pos_before = host(plan.positions())
+    with pytest.raises(PtychoError) as e:
+        plan.position_shifts(o, p, psi_bad)
+    assert e.value.code == -1
+    with pytest.raises(PtychoError):
+        plan.refine(o, p, psi_bad)
+    pbig = torch.zeros(p.numel() + 1, dtype=torch.complex64, device=dev)
+    p_bad = pbig[1:].view(p.shape)
+    p_bad.copy_(p)
+    psi_ok = torch.zeros(shape, dtype=torch.complex64, device=dev)
+    with pytest.raises(PtychoError):
+        plan.position_shifts(o, p_bad, psi_ok)
+    np.testing.assert_array_equal(host(plan.positions()), pos_before)     # nothing moved
+    # aligned arrays work
+    out = host(plan.position_shifts(o, p, psi_ok))
+    assert np.isfinite(out).all()
