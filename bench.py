@@ -412,6 +412,48 @@ def traffic_for(cls, cycle="dm256_dm_cycle"):
         return None
 
 
+def fft_bandwidth(torch, dev, sizes=(64, 128, 256, 512, 1024, 2048), array_bytes=1 << 30):
+    """The FFT bandwidth benchmark of the paper's appendix (FFT performance),
+    for the library's batched 2D transform: per size, a batch of about 1 GiB of
+    complex64 frames goes through two forward/inverse pairs in place, four
+    times; the best time counts, with two reads and two writes of the array
+    per 2D transform (one per axis)."""
+    from paper_2008_11511_amd import _lib
+    h = _lib.lib()
+    out = {}
+    for n in sizes:
+        count = max(1, array_bytes // (8 * n * n))
+        x = torch.zeros((count, n, n), dtype=torch.complex64, device=dev)
+        x.real.normal_()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        ptr = x.data_ptr()
+
+        def pairs():
+            for _ in range(2):
+                for direction in (-1, 1):
+                    st = h.ptycho_fft2(n, count, ptr, direction, stream)
+                    if st != 0:
+                        raise _lib.PtychoError(st, h.ptycho_last_error().decode())
+
+        pairs()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pairs()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 4.0)          # ms per 2D transform
+        nbytes = 2 * 2 * 8 * n * n * count
+        gbs = nbytes / (best * 1e-3) / 1e9
+        out[str(n)] = {"frames": count, "ms_per_fft": round(best, 4), "GBs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        del x
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +467,7 @@ def main():
                     help="host processes of the all-cores oracle baseline (at most the CPUs available; 1 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ml", action="store_true")
+    ap.add_argument("--no-fft", action="store_true", help="skip the batched 2D FFT bandwidth figures")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the LLK-fetch, noise-model, background and copy-roof figures")
     ap.add_argument("--large-cycles", default="2,5",
@@ -750,6 +793,12 @@ def main():
                                  for q in ("p50", "mean", "p99")},
                  "results_identical": all(v["results_identical"] for v in per_seed.values())}
 
+    fft = None
+    if not args.no_fft:
+        log("FFT bandwidth: batched unitary 2D FFT, 64..2048 points, 1 GiB per size, best of 4 x 2 pairs")
+        fft = fft_bandwidth(torch, dev)
+        log(f"FFT bandwidth: {json.dumps({n: v['GBs'] for n, v in fft.items()})} GB/s")
+
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
         b = torch.empty_like(a)
@@ -804,6 +853,7 @@ def main():
         "large": large,
         "near_field": near,
         "serve": serve,
+        "fft": fft,
         "cpu_baseline": cpu,
         "paper_context": {"value": 22727, "unit": "frames*cycles/s",
                           "note": "DM 44 ms/cycle, 1000 frames 256x256, 3 probe modes, object 1176x1188, "
