@@ -192,20 +192,21 @@ template <int N>
 static int fft2_n(int32_t count, float *data, int32_t dir, hipStream_t s) {
     const long rows = (long)count * N;
     const int rb = (int)((rows + RowGeom<N>::RB - 1) / RowGeom<N>::RB);
-    const int cbk = (int)((rows + ColGeom<N>::CB - 1) / ColGeom<N>::CB);
-    const size_t lds = sizeof(float2) * ColGeom<N>::LDS_F2;
+    using FG = FftColGeom<N>;
+    const int cbk = (int)((rows + FG::CB - 1) / FG::CB);
+    const size_t lds = sizeof(float2) * FG::LDS_F2;
     const float scale = 1.0f / (float)N;
     if (dir < 0) {
         static const hipError_t attr = set_dyn_lds(k_fft_cols<N, -1>, lds);
         (void)attr;
         hipLaunchKernelGGL((k_fft_rows<N, -1>), dim3(rb), dim3(256), 0, s, (float2 *)data, rows);
-        hipLaunchKernelGGL((k_fft_cols<N, -1>), dim3(cbk), dim3(ColGeom<N>::THREADS), lds, s, (float2 *)data,
+        hipLaunchKernelGGL((k_fft_cols<N, -1>), dim3(cbk), dim3(FG::THREADS), lds, s, (float2 *)data,
                            (long)count, scale);
     } else {
         static const hipError_t attr = set_dyn_lds(k_fft_cols<N, 1>, lds);
         (void)attr;
         hipLaunchKernelGGL((k_fft_rows<N, 1>), dim3(rb), dim3(256), 0, s, (float2 *)data, rows);
-        hipLaunchKernelGGL((k_fft_cols<N, 1>), dim3(cbk), dim3(ColGeom<N>::THREADS), lds, s, (float2 *)data,
+        hipLaunchKernelGGL((k_fft_cols<N, 1>), dim3(cbk), dim3(FG::THREADS), lds, s, (float2 *)data,
                            (long)count, scale);
     }
     LAUNCHCHK();

@@ -499,9 +499,22 @@ __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, long rows) {
     }
 }
 
+// Geometry of the standalone column transform, which reads row-major frames:
+// from 128 points up a block takes 16 adjacent columns (128-byte row
+// segments; 8 at 2048 points), with 16 elements per thread from 1024 points
+// so that the block stays within 1024 threads.
+template <int N>
+struct FftColGeom {
+    static constexpr int E = (N >= 1024) ? 16 : col_e(N), T = N / E;
+    static constexpr int CB = (N >= 2048) ? 8 : (N >= 128) ? 16 : col_cb(N);
+    static constexpr int THREADS = CB * T;
+    static constexpr int LDS_F2 = (FftCfg<N, E>::P > 1) ? N * CB : 1;
+    static_assert(THREADS <= 1024, "one block");
+};
+
 template <int N, int DIR>
-__global__ __launch_bounds__(ColGeom<N>::THREADS) void k_fft_cols(float2 *data, long count, float scale) {
-    using G = ColGeom<N>;
+__global__ __launch_bounds__(FftColGeom<N>::THREADS) void k_fft_cols(float2 *data, long count, float scale) {
+    using G = FftColGeom<N>;
     constexpr int E = G::E, CB = G::CB;
     extern __shared__ float2 lds_dyn[];
     const int tid = threadIdx.x, cl = tid % CB, t = tid / CB;
