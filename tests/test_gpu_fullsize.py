@@ -11,6 +11,9 @@ times (automatic stack size).
   holds at any size).
 * Near field, 17 frames 2048x2048, one probe: one whole DM cycle and the ML
   gradient against the oracle.
+* Sub-pixel positions on the DM scan (1000 frames 256x256, 3 modes): one whole
+  DM cycle, then the position shifts from its outputs, and the ML gradient on
+  the 500-frame scan, against the oracle's bilinear windows.
 """
 import sys
 
@@ -155,3 +158,68 @@ def test_nf2048_full_dm_cycle_and_gradient(dev):
     assert rel_l2(g_psi, rpsi) < 1e-4
     assert rel_l2(d_o, ro) < 1e-4
     assert rel_l2(d_p, rp) < 1e-4
+
+
+def _subpixel_positions(pb, wl, seed):
+    """Real positions whose corners are the scan's integer corners plus a
+    fraction in [0, 1) on each axis (windows well inside the object), and
+    Poisson data simulated at those positions.  Data taken at the integer
+    corners would leave the model far from the data at the sub-pixel ones,
+    where the probe gradient is ill-conditioned: a 1e-7 relative change of
+    the object and probe then moves the oracle's own probe gradient by 3e-4,
+    against 1e-6 with consistent data."""
+    rng = np.random.default_rng(seed)
+    t = pb.offsets.astype(np.float64) + rng.uniform(0.0, 1.0, (wl.n_frames, 2))
+    pos = t - np.array(wl.obj_shape) / 2.0 + wl.n / 2.0
+    offs, frac = oracle.windows_from_positions(pos, wl.n, wl.obj_shape)
+    np.testing.assert_array_equal(offs, pb.offsets)
+    inten = oracle.simulate_intensity(pb.obj_true, pb.probe_true, offs, frac=frac)
+    iobs = synth.poisson_counts(inten, wl.seed).astype(np.float32)
+    return pos, frac, iobs
+
+
+def test_dm256_subpixel_full_cycle_and_shifts(dev):
+    from paper_2008_11511_amd import Plan
+    wl = synth.workload("dm256")
+    pb = make_problem(wl, start="ml")
+    pos, frac, iobs = _subpixel_positions(pb, wl, 11)
+    say("full size DM with sub-pixel windows: 1000 frames 256x256, 3 modes")
+    plan = Plan.with_positions(pos, torch.from_numpy(iobs).to(dev), torch.from_numpy(pb.mask).to(dev), 3,
+                               wl.obj_shape, max_shift=1.0)
+    o = torch.from_numpy(pb.obj0.astype(np.complex64)).to(dev)
+    p = torch.from_numpy(pb.probe0.astype(np.complex64)).to(dev)
+    psi = plan.psi_init(o, p)
+    plan.dm_cycle(o, p, psi, 1, 3)
+    g_psi, g_o, g_p = host(psi), host(o), host(p)
+    psi0 = oracle.psi_init(pb.obj0, pb.probe0, pb.offsets, frac)
+    ro, rp, rpsi = oracle.dm_cycle(pb.obj0, pb.probe0, psi0, pb.offsets, iobs, pb.mask, frac=frac)
+    assert rel_l2(g_psi, rpsi) < 1e-4
+    assert rel_l2(g_o, ro) < 1e-4
+    assert rel_l2(g_p, rp) < 1e-4
+    say("position shifts from the cycle's outputs, same inputs on both sides")
+    got = host(plan.position_shifts(o, p, psi))
+    del psi
+    ref, e_ref = oracle.position_shifts(g_o.astype(np.complex64).astype(np.complex128),
+                                        g_p.astype(np.complex64).astype(np.complex128),
+                                        g_psi.astype(np.complex64).astype(np.complex128), pb.offsets, frac)
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(got[:, :2] - ref).max() <= 1e-3 * scale
+    np.testing.assert_allclose(got[:, 2], e_ref, rtol=1e-4)
+
+
+def test_ml256_subpixel_full_gradient(dev):
+    from paper_2008_11511_amd import Plan
+    wl = synth.workload("ml256")
+    pb = make_problem(wl, start="ml")
+    pos, frac, iobs = _subpixel_positions(pb, wl, 12)
+    say("full size ML gradient with sub-pixel windows: 500 frames 256x256, 3 modes")
+    plan = Plan.with_positions(pos, torch.from_numpy(iobs).to(dev), torch.from_numpy(pb.mask).to(dev), 3,
+                               wl.obj_shape, max_shift=1.0)
+    o = torch.from_numpy(pb.obj0.astype(np.complex64)).to(dev)
+    p = torch.from_numpy(pb.probe0.astype(np.complex64)).to(dev)
+    g_o, g_p, llk = plan.ml_grad(o, p)
+    ro, rp, rl = oracle.ml_grad(pb.obj0, pb.probe0, pb.offsets, iobs, pb.mask, frac=frac)
+    assert rel_l2(host(g_o), ro) < 1e-4
+    assert rel_l2(host(g_p), rp) < 1e-4
+    assert abs(host(llk)[0] - rl) < 1e-4 * abs(rl)
