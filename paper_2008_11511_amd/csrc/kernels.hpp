@@ -719,12 +719,24 @@ __global__ __launch_bounds__(256) void k_psi_init(const float2 *obj, const float
     }
 }
 
-// Sum of `n` partials (fixed order, one block) into out[0] (+= if accumulate).
-__global__ __launch_bounds__(256) void k_sum_partials(const double *red, long n, int stride, double *out,
-                                                      int accumulate) {
-    double v = 0.0;
-    for (long i = threadIdx.x; i < n; i += 256) v += red[i * stride];
-    v = block_sum(v);
+// Sum of `n` partials (fixed order, one block of SUM_THREADS) into out[0]
+// (+= if accumulate).  Each thread keeps four running sums over its
+// elements i = t + SUM_THREADS m, m = 0, 1, 2, 3 taken in turn, so that four
+// loads are in flight per thread; the order depends on n alone.
+constexpr int SUM_THREADS = 1024;
+__global__ __launch_bounds__(SUM_THREADS) void k_sum_partials(const double *red, long n, int stride, double *out,
+                                                              int accumulate) {
+    constexpr long T = SUM_THREADS;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    long i = threadIdx.x;
+    for (; i + 3 * T < n; i += 4 * T) {
+        v0 += red[i * stride];
+        v1 += red[(i + T) * stride];
+        v2 += red[(i + 2 * T) * stride];
+        v3 += red[(i + 3 * T) * stride];
+    }
+    for (; i < n; i += T) v0 += red[i * stride];
+    const double v = block_sum((v0 + v1) + (v2 + v3));
     if (threadIdx.x == 0) out[0] = accumulate ? out[0] + v : v;
 }
 

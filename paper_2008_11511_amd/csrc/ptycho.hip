@@ -114,7 +114,7 @@ static int window_margin(const ptycho_desc_t &d) {
     return (d.flags & PTYCHO_FLAG_POSITIONS) ? (int)std::ceil((double)d.max_shift) + 1 : 0;
 }
 
-// Rows per chunk of the position-shift sums: about 4096 pixels per block.
+// Rows per chunk of the position-shift sums: about 8192 pixels per block.
 static int pos_rows(int n) { return std::max(1, std::min(n, 8192 / n)); }
 
 // Frames per launch.  The stack kernels are bandwidth-bound and do not keep
@@ -904,7 +904,7 @@ static int llk_into(ptycho_plan_t p, const float *obj, const float *probe, doubl
     if (st) return st;
     st = forward_pass(p, OP_LLK, obj, probe, nullptr, nullptr, nullptr, model);
     if (st) return st;
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(SUM_THREADS), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
     hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, p->stream, llk + 1, p->scal + SC_NOBS);
     LAUNCHCHK();
     return PTYCHO_OK;
@@ -1123,7 +1123,7 @@ extern "C" int ptycho_ml_grad(ptycho_plan_t p, const float *obj, const float *pr
     hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(no)), dim3(256), 0, p->stream, (float2 *)g_obj, p->numO, no, 2.0f);
     hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(np)), dim3(256), 0, p->stream, (float2 *)g_probe, p->numP, np, 2.0f);
     if (llk) {
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(SUM_THREADS), 0, p->stream, p->red, (long)p->L.nred, 1, llk, 0);
         hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, p->stream, llk + 1, p->scal + SC_NOBS);
     }
     LAUNCHCHK();
@@ -1140,8 +1140,8 @@ static int ls_pass(ptycho_plan_s *p, const float *obj, const float *probe, const
               : forward_pass(p, OP_LS, obj, probe, dobj, dprobe, nullptr);
     if (st) return st;
     const long n = (long)p->L.nred / 2;
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red, n, 2, coef, 0);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, p->stream, p->red + 1, n, 2, coef + 1, 0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(SUM_THREADS), 0, p->stream, p->red, n, 2, coef, 0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(SUM_THREADS), 0, p->stream, p->red + 1, n, 2, coef + 1, 0);
     LAUNCHCHK();
     return PTYCHO_OK;
 }
@@ -1213,7 +1213,8 @@ extern "C" int ptycho_ml_cycle(ptycho_plan_t p, float *obj, float *probe, void *
         if (st) return st;
         {
         Timed tm(p, TC_OTHER);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, p->red, (long)p->L.nred, 1, scal + CG_LLK, 0);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(SUM_THREADS), 0, s, p->red, (long)p->L.nred, 1,
+                           scal + CG_LLK, 0);
         hipLaunchKernelGGL(k_max_partial, dim3(NPART), dim3(256), 0, s, p->denO, (long)no, p->denP, n2, p->part);
         // 2. inner products for beta, then the new direction
         hipLaunchKernelGGL(k_cg_dots, dim3(CG_NPART), dim3(256), 0, s, p->numO, g_o, (long)no, p->numP, g_p,
@@ -1345,7 +1346,7 @@ extern "C" int ptycho_llk_noalloc(const ptycho_desc_t *d, const int32_t *offsets
     LAUNCHCHK();
     st = np->forward(&p, OP_LLK, obj, probe, nullptr, nullptr, nullptr, LLK_POISSON, nullptr);
     if (st) return st;
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, p.red, (long)L.nred, 1, llk, 0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(SUM_THREADS), 0, s, p.red, (long)L.nred, 1, llk, 0);
     hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, llk + 1, count);
     hipLaunchKernelGGL(k_nan_if_flagged, dim3(1), dim3(1), 0, s, llk, flag);
     LAUNCHCHK();
