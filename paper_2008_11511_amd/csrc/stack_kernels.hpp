@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256) void k_rows_fwd(StackArgs a) {
                     u[2][e] = cmul(dv, dp);
                 } else if constexpr (MODE == IN_DM) {
                     const float2 phi = cmul(ov, p);
-                    const float2 ps = a.psi[(((size_t)j * a.K + k) * N + y) * N + x];
+                    // the old exit waves are read once: non-temporal
+                    const float2 ps = ld_stream(a.psi + (((size_t)j * a.K + k) * N + y) * N + x);
                     u[0][e] = make_float2(2.0f * phi.x - ps.x, 2.0f * phi.y - ps.y);
                 } else {
                     u[0][e] = cmul(ov, p);
@@ -126,7 +127,8 @@ __global__ __launch_bounds__(InvRowGeom<N>::TPM * K) void k_rows_inv(StackArgs a
     float2 *src = a.scr + ((size_t)s * K + k) * N * N;
     float2 u[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = src[scr_at<N>(y, NF ? in_index<N, E, -1>(t, e) : in_index<N, E, +1>(t, e))];
+    for (int e = 0; e < E; ++e)          // read once: non-temporal, the caches keep the views and the probe
+        u[e] = ld_stream(src + scr_at<N>(y, NF ? in_index<N, E, -1>(t, e) : in_index<N, E, +1>(t, e)));
     if constexpr (NF) {
         // Dx^-1: forward transform, the conjugate x factor, inverse below
         fft1d<N, E, -1>(u, t, L);
