@@ -228,3 +228,38 @@ def test_position_shifts_refuse_misaligned_arrays_before_any_work(dev):
     # aligned arrays work
     out = host(plan.position_shifts(o, p, psi_ok))
     assert np.isfinite(out).all()
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 128, 512, 1024, 2048])
+def test_position_shifts_match_oracle_at_every_size(dev, n):
+    """The shift kernel's thread layout changes with N (pairs of columns per
+    thread, row groups below 512 points, several pairs per thread from 1024):
+    integer and sub-pixel windows against the oracle at every supported size,
+    random object, probe and exit waves, windows near the object's border."""
+    from paper_2008_11511_amd import Plan
+    rng = np.random.default_rng(1000 + n)
+    k = 1 if n == 2048 else 2
+    j = 3
+    side = n + 24
+    say(f"position shifts at n={n}, {j} frames, {k} modes")
+    obj = (rng.standard_normal((side, side)) + 1j * rng.standard_normal((side, side))).astype(np.complex64)
+    probe = (rng.standard_normal((k, n, n)) + 1j * rng.standard_normal((k, n, n))).astype(np.complex64)
+    psi = (rng.standard_normal((j, k, n, n)) + 1j * rng.standard_normal((j, k, n, n))).astype(np.complex64)
+    # corners: one near each border (sub-pixel plans need max_shift + 1 pixels of margin)
+    t = np.array([[2.25, 3.5], [side - n - 2.75, 7.125], [11.5, side - n - 2.5]])
+    pos = t - side / 2.0 + n / 2.0
+    offs, frac = oracle.windows_from_positions(pos, n, (side, side))
+    iobs = torch.zeros((j, n, n), dtype=torch.float32, device=dev)
+    o_d, p_d, psi_d = t_(obj, dev, torch.complex64), t_(probe, dev, torch.complex64), t_(psi, dev, torch.complex64)
+    for sub in (False, True):
+        if sub:
+            plan = Plan.with_positions(pos, iobs, None, k, (side, side), max_shift=1.0)
+            ref, e_ref = oracle.position_shifts(obj, probe, psi, offs, frac)
+        else:
+            plan = Plan(offs, iobs, None, k, (side, side))
+            ref, e_ref = oracle.position_shifts(obj, probe, psi, offs)
+        got = host(plan.position_shifts(o_d, p_d, psi_d))
+        scale = max(np.abs(ref).max(), 1e-3)
+        assert np.abs(got[:, :2] - ref).max() <= 1e-3 * scale, (n, sub)
+        np.testing.assert_allclose(got[:, 2], e_ref, rtol=1e-4)
+        plan.close()
