@@ -499,8 +499,8 @@ def main():
         print(json.dumps({"profiles": done}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part of "
-              f"this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the path is not sharded over several GPUs",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

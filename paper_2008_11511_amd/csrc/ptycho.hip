@@ -70,7 +70,7 @@ static bool supported_n(int n) {
 static const NPass *passes_for(int n) {
     for (auto get : g_passes)
         if (get()->n == n) return get();
-    fail(PTYCHO_E_UNSUPPORTED, supported_n(n) ? "frame size not compiled into this build" : "unsupported frame size");
+    fail(PTYCHO_E_UNSUPPORTED, supported_n(n) ? "frame size not compiled into this library" : "unsupported frame size");
     return nullptr;
 }
 
