@@ -630,10 +630,12 @@ class ReconstructionService:
     """
 
     # The default age cap lets a request be passed by shorter ones only during
-    # its first 1/8 s: on the mixed trace this keeps every latency statistic
-    # at or below one-at-a-time solving; a longer cap (say 1 s) halves the
-    # median latency but lets the largest request finish later.
-    def __init__(self, device="cuda:0", hbm_budget: Optional[int] = None, max_active: int = 8,
+    # its first 1/8 s, and at most three requests are admitted (resident) at
+    # once, so that few admissions run beside the request on the device: on
+    # the mixed trace this keeps every latency statistic at or below
+    # one-at-a-time solving; a longer cap (say 1 s) halves the median latency
+    # but lets the largest request finish later.
+    def __init__(self, device="cuda:0", hbm_budget: Optional[int] = None, max_active: int = 3,
                  max_running: int = 1, order: str = "srpt", age_cap: Optional[float] = 0.125,
                  chunk: int = 5):
         import itertools
@@ -763,7 +765,7 @@ def make_trace(n_requests: int, rate: float, seed: int = 0, max_frames: int = 20
 
 
 def serve_trace(n_requests: int = 64, rate: float = 2.0, seed: int = 0, hbm_budget: Optional[int] = None,
-                max_active: int = 8, sequential: bool = False, device="cuda:0", max_frames: int = 2000,
+                max_active: int = 3, sequential: bool = False, device="cuda:0", max_frames: int = 2000,
                 sizes=(128, 256, 512), schedule=SCHEDULE, min_frames: int = 200, min_side: int = 1024,
                 max_running: Optional[int] = 1, order: str = "srpt", age_cap: Optional[float] = 0.125):
     """Run an arrival trace through the service; returns (requests, summary)."""
