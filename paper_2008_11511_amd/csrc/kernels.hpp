@@ -139,7 +139,9 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
     // the newest object row a pixel at row Y needs: Y + 1, or Y + 2 for
     // sub-pixel windows
     constexpr int LEAD = SUB ? 2 : 1;
-    double syy = 0.0, sxx = 0.0, sxy = 0.0, by = 0.0, bx = 0.0;
+    // fp32 sums over the thread's pixels (at most 64 terms at every N),
+    // fp64 from the block sum on
+    float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
     for (int m = 0; m < npair; ++m) {
         const int x = x0 + (m << 9);
         const int X = o.y + x;
@@ -147,7 +149,8 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
         const int Y0 = o.x + y0;
         const int ylast = a.Ny - 1;
         // each step loads the next pixel row's exit waves and probe and the
-        // object row after its window, while it works on the current row
+        // object row after its window while it works on the current row, and
+        // folds the modes of the loaded row as its last act
         auto load_px = [&](int y, float4 (&ps)[K], float4 (&pr)[K]) {
             const size_t pix = tiled_at(y, x, N, a.lw);
 #pragma unroll
@@ -157,16 +160,39 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
                 pr[k] = *(const float4 *)(a.probe + (size_t)k * n2 + (size_t)y * N + x);
             }
         };
-        float4 ps[K], pr[K];
-        load_px(y0, ps, pr);
+        // the modes enter through Q = sum_k conj(P_k) Psi_k and
+        // P2 = sum_k |P_k|^2: sum_k |P_k g|^2 = P2 |g|^2 and
+        // sum_k conj(P_k g) chi_k = conj(g) c with c = Q - P2 O_view (AP) or
+        // c = scale Q (ML); a row is carried to the next step as Q and P2 of
+        // its two pixels, not as its 2 K exit-wave and probe values
+        auto fold = [&](const float4 (&ps)[K], const float4 (&pr)[K], float2 (&q)[2], float (&p2)[2]) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                q[p] = make_float2(0.0f, 0.0f);
+                p2[p] = 0.0f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float2 pk = p ? make_float2(pr[k].z, pr[k].w) : make_float2(pr[k].x, pr[k].y);
+                    const float2 sk = p ? make_float2(ps[k].z, ps[k].w) : make_float2(ps[k].x, ps[k].y);
+                    const float2 mk = cmulc(pk, sk);
+                    q[p] = make_float2(q[p].x + mk.x, q[p].y + mk.y);
+                    p2[p] += cnorm(pk);
+                }
+            }
+        };
+        float2 qc[2];
+        float p2c[2];
+        {
+            float4 ps[K], pr[K];
+            load_px(y0, ps, pr);
+            fold(ps, pr, qc, p2c);
+        }
         RawRow rn = load_row<SUB>(a.obj, a.Nx, min(Y0 + LEAD, ylast), X);
         // rows Y-1, Y (and Y+1) of the first pixel row, clamped
         ShiftRow wm = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, max(Y0 - 1, 0), X), a.Nx, X, wx0, wx1);
         ShiftRow w0 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, Y0, X), a.Nx, X, wx0, wx1);
         ShiftRow w1{};
         if constexpr (SUB) w1 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, min(Y0 + 1, ylast), X), a.Nx, X, wx0, wx1);
-        // fp32 sums over the walk's rows (at most 32 terms), fp64 beyond
-        float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
         for (int i = 0; i < rows; ++i) {
             const int y = y0 + i, Y = Y0 + i;
             // prefetch (the last step loads its own row again, in bounds)
@@ -192,20 +218,8 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
                     gx = w0.d[p];
                     gy = cscale(csub(wl.h[p], wm.h[p]), sy0);
                 }
-                // the modes enter through Q = sum_k conj(P_k) Psi_k and
-                // P2 = sum_k |P_k|^2: sum_k |P_k g|^2 = P2 |g|^2 and
-                // sum_k conj(P_k g) chi_k = conj(g) c with c = Q - P2 O_view
-                // (AP) or c = scale Q (ML)
-                float2 q = make_float2(0.0f, 0.0f);
-                float p2 = 0.0f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float2 pk = p ? make_float2(pr[k].z, pr[k].w) : make_float2(pr[k].x, pr[k].y);
-                    const float2 sk = p ? make_float2(ps[k].z, ps[k].w) : make_float2(ps[k].x, ps[k].y);
-                    const float2 mk = cmulc(pk, sk);
-                    q = make_float2(q.x + mk.x, q.y + mk.y);
-                    p2 += cnorm(pk);
-                }
+                const float2 q = qc[p];
+                const float p2 = p2c[p];
                 const float2 cc = a.ml ? cscale(q, a.chi_scale) : csub(q, cscale(ov, p2));
                 fyy += p2 * cnorm(gy);
                 fxx += p2 * cnorm(gx);
@@ -222,23 +236,14 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
                 w0 = wl;
             }
             rn = rn2;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                ps[k] = ps2[k];
-                pr[k] = pr2[k];
-            }
+            fold(ps2, pr2, qc, p2c);
         }
-        syy += fyy;
-        sxx += fxx;
-        sxy += fxy;
-        by += fby;
-        bx += fbx;
     }
-    syy = block_sum(syy);
-    sxx = block_sum(sxx);
-    sxy = block_sum(sxy);
-    by = block_sum(by);
-    bx = block_sum(bx);
+    const double syy = block_sum((double)fyy);
+    const double sxx = block_sum((double)fxx);
+    const double sxy = block_sum((double)fxy);
+    const double by = block_sum((double)fby);
+    const double bx = block_sum((double)fbx);
     if (threadIdx.x == 0) {
         double *d = a.part + ((size_t)j * a.CH + c) * 5;
         d[0] = syy;

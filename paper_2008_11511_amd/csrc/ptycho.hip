@@ -114,8 +114,8 @@ static int window_margin(const ptycho_desc_t &d) {
     return (d.flags & PTYCHO_FLAG_POSITIONS) ? (int)std::ceil((double)d.max_shift) + 1 : 0;
 }
 
-// Rows per chunk of the position-shift sums: about 8192 pixels per block.
-static int pos_rows(int n) { return std::max(1, std::min(n, 8192 / n)); }
+// Rows per chunk of the position-shift sums: about 16384 pixels per block.
+static int pos_rows(int n) { return std::max(1, std::min(n, 16384 / n)); }
 
 // Frames per launch.  The stack kernels are bandwidth-bound and do not keep
 // data in cache from one launch to the next, so larger launches (fewer
