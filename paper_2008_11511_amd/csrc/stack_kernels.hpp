@@ -480,14 +480,17 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     }
 }
 
-// Plain batched FFT along rows / columns (standalone 2D transform).
+// Plain batched FFT along rows / columns (standalone 2D transform).  Both
+// passes remap their blocks so that each XCD takes a contiguous range: the
+// column blocks that share 128-byte row lines (and neighbouring rows) are then
+// served by one L2 (2048-point frames: 3.9 -> 5.0 TB/s).
 template <int N, int DIR>
 __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, long rows) {
     using G = RowGeom<N>;
     constexpr int E = G::E, T = G::T, RB = G::RB;
     __shared__ float2 lds[G::LDS_F2];
     const int tid = threadIdx.x, rr = tid / T, t = tid % T;
-    const long g = (long)blockIdx.x * RB + rr;
+    const long g = (long)xcd_block(blockIdx.x, gridDim.x) * RB + rr;
     const bool active = g < rows;
     float2 *row = data + (size_t)(active ? g : rows - 1) * N;
     RowLds<N> L(lds, rr);
@@ -520,7 +523,7 @@ __global__ __launch_bounds__(FftColGeom<N>::THREADS) void k_fft_cols(float2 *dat
     constexpr int E = G::E, CB = G::CB;
     extern __shared__ float2 lds_dyn[];
     const int tid = threadIdx.x, cl = tid % CB, t = tid / CB;
-    const long g = (long)blockIdx.x * CB + cl;
+    const long g = (long)xcd_block(blockIdx.x, gridDim.x) * CB + cl;
     const bool active = g < count * N;
     const long gg = active ? g : count * N - 1;
     const long f = gg / N;
