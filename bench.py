@@ -43,6 +43,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# The profiled run of the committed summaries under profiles/ (run from /tmp
+# with TMPDIR=/tmp; $R is the repository root).
+PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof_trace -o run -- python3 $R/bench.py "
+                   "--steps 5 --warmup 1 --ml-steps 3 --no-cpu-baseline --no-extra --no-fft --serve-requests 0 "
+                   "--large-cycles 1,1 --near-cycles 2,2 --calib-copy")
+
+
 def source_sha():
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2008_11511_amd", "csrc", "*"))):
@@ -491,8 +498,10 @@ def main():
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/*.md and profiles/traffic.json from the rocprofv3 output of one bench run "
                          "(kernel trace, FETCH_SIZE, WRITE_SIZE) and exit; no GPU needed")
-    ap.add_argument("--profile-command", default="(not given)",
-                    help="the profiled command, recorded in the summaries")
+    ap.add_argument("--profile-command", default=PROFILE_COMMAND,
+                    help="the profiled command, recorded in the summaries (default: the trace command of the "
+                         "committed summaries; the counter runs replace --kernel-trace --stats by --pmc FETCH_SIZE "
+                         "and --pmc WRITE_SIZE)")
     args = ap.parse_args()
     if args.summarize_rocprof:
         done = summarize_rocprof(*args.summarize_rocprof, command=args.profile_command)
