@@ -37,7 +37,7 @@ struct PosShiftArgs {
     const int2 *offs;             // [J] (oy, ox)
     const float2 *frac;           // [J] sub-pixel fractions, or null
     const int *order;             // launch frame f -> frame j (order[s0 + f]), or null: j = f
-    int s0;
+    int s0, nf;                   // first launch frame, frames in the launch
     const float2 *obj, *probe, *psi;
     int lw;                       // log2 of psi's tile width (log2 N: row-major)
     bool by_slot;                 // psi indexed by launch frame f (stack scratch), else by frame j
@@ -46,14 +46,15 @@ struct PosShiftArgs {
     double *part;                 // [J][CH][5], indexed by frame j
 };
 
-// Partial sums of the position-shift systems, one chunk of R rows of one
-// frame per block.  The derivatives of the object are the centred
+// Partial sums of the position-shift systems, one chunk of R rows of F
+// frames per block (the same pixels of each, so that one probe load serves
+// the F frames).  The derivatives of the object are the centred
 // differences inside the object and one-sided ones on its border:
 // (O[hi] - O[lo]) / (hi - lo) with lo, hi the neighbours clamped to the
 // object.
 //
-// One thread walks down two adjacent columns (x, x + 1) of its chunk and
-// keeps the object rows its pixels need in registers.  Per row of the walk it
+// One thread walks down two adjacent columns (x, x + 1) of its chunk, in each
+// of its F frames, and keeps the object rows its pixels need in registers.  Per row of the walk it
 // loads the object values X-1 .. X+2 (and X+3 for sub-pixel windows) of one
 // new row (clamped to the object) and forms, for both pixels, the row's view
 // along x and that of its x derivative,
@@ -108,18 +109,31 @@ __device__ __forceinline__ ShiftRow make_row(const RawRow &r, int Nx, int X, flo
     return w;
 }
 
-template <int K, bool SUB>
+template <int K, bool SUB, int F>
 __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
     // the chunks of a frame, and neighbouring frames, on one XCD: their
     // object rows overlap and are served by that XCD's L2
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int c = b % a.CH, f = b / a.CH, N = a.N;
-    const int j = a.order != nullptr ? a.order[a.s0 + f] : f;
-    const int2 o = a.offs[j];
-    const float2 fr = SUB ? a.frac[j] : make_float2(0.0f, 0.0f);
-    const float vy0 = 1.0f - fr.x, vy1 = fr.x, wx0 = 1.0f - fr.y, wx1 = fr.y;
+    const int c = b % a.CH, fg = b / a.CH, N = a.N;
     const size_t n2 = (size_t)N * N;
-    const float2 *psi = a.psi + (size_t)(a.by_slot ? f : j) * K * n2;
+    // F frames per block, the same pixels of each: one probe load serves all
+    // F.  A block past the last frame repeats it and drops its sums.
+    int jf[F];
+    int2 of[F];
+    float vy0[F], vy1[F], wx0[F], wx1[F];
+    const float2 *psf[F];
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+        const int f = min(fg * F + i, a.nf - 1);
+        jf[i] = a.order != nullptr ? a.order[a.s0 + f] : f;
+        of[i] = a.offs[jf[i]];
+        const float2 fr = SUB ? a.frac[jf[i]] : make_float2(0.0f, 0.0f);
+        vy0[i] = 1.0f - fr.x;
+        vy1[i] = fr.x;
+        wx0[i] = 1.0f - fr.y;
+        wx1[i] = fr.y;
+        psf[i] = a.psi + (size_t)(a.by_slot ? f : jf[i]) * K * n2;
+    }
     // the thread's column pairs: one pair of ceil(R / G) rows (G = 256 / (N/2)
     // row groups) up to N = 512, N / 512 pairs of R rows beyond
     const int tid = threadIdx.x, lgP = a.lgN - 1, NP = N >> 1;
@@ -139,118 +153,141 @@ __global__ __launch_bounds__(256) void k_pos_shift_part(PosShiftArgs a) {
     // the newest object row a pixel at row Y needs: Y + 1, or Y + 2 for
     // sub-pixel windows
     constexpr int LEAD = SUB ? 2 : 1;
-    // fp32 sums over the thread's pixels (at most 64 terms at every N),
-    // fp64 from the block sum on
-    float fyy = 0.0f, fxx = 0.0f, fxy = 0.0f, fby = 0.0f, fbx = 0.0f;
+    const int ylast = a.Ny - 1;
+    // fp32 sums over the thread's pixels (at most 64 terms per frame at every
+    // N), fp64 from the block sum on
+    float fyy[F], fxx[F], fxy[F], fby[F], fbx[F];
+#pragma unroll
+    for (int i = 0; i < F; ++i) fyy[i] = fxx[i] = fxy[i] = fby[i] = fbx[i] = 0.0f;
     for (int m = 0; m < npair; ++m) {
         const int x = x0 + (m << 9);
-        const int X = o.y + x;
         const int y0 = c * a.R + ylo, ylast_px = y0 + rows - 1;
-        const int Y0 = o.x + y0;
-        const int ylast = a.Ny - 1;
         // each step loads the next pixel row's exit waves and probe and the
-        // object row after its window while it works on the current row, and
-        // folds the modes of the loaded row as its last act
-        auto load_px = [&](int y, float4 (&ps)[K], float4 (&pr)[K]) {
+        // object rows after the windows while it works on the current row,
+        // and folds the modes of the loaded row as its last act
+        auto load_px = [&](int y, float4 (&ps)[F][K], float4 (&pr)[K]) {
             const size_t pix = tiled_at(y, x, N, a.lw);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                // read once: non-temporal, to keep L2 for the object
-                ps[k] = ld_stream2(psi + (size_t)k * n2 + pix);
                 pr[k] = *(const float4 *)(a.probe + (size_t)k * n2 + (size_t)y * N + x);
+#pragma unroll
+                for (int i = 0; i < F; ++i)     // read once: non-temporal, to keep L2 for the object
+                    ps[i][k] = ld_stream2(psf[i] + (size_t)k * n2 + pix);
             }
         };
         // the modes enter through Q = sum_k conj(P_k) Psi_k and
         // P2 = sum_k |P_k|^2: sum_k |P_k g|^2 = P2 |g|^2 and
         // sum_k conj(P_k g) chi_k = conj(g) c with c = Q - P2 O_view (AP) or
         // c = scale Q (ML); a row is carried to the next step as Q and P2 of
-        // its two pixels, not as its 2 K exit-wave and probe values
-        auto fold = [&](const float4 (&ps)[K], const float4 (&pr)[K], float2 (&q)[2], float (&p2)[2]) {
+        // its two pixels, not as its exit-wave and probe values
+        auto fold = [&](const float4 (&ps)[F][K], const float4 (&pr)[K], float2 (&q)[F][2], float (&p2)[2]) {
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                q[p] = make_float2(0.0f, 0.0f);
                 p2[p] = 0.0f;
+#pragma unroll
+                for (int i = 0; i < F; ++i) q[i][p] = make_float2(0.0f, 0.0f);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const float2 pk = p ? make_float2(pr[k].z, pr[k].w) : make_float2(pr[k].x, pr[k].y);
-                    const float2 sk = p ? make_float2(ps[k].z, ps[k].w) : make_float2(ps[k].x, ps[k].y);
-                    const float2 mk = cmulc(pk, sk);
-                    q[p] = make_float2(q[p].x + mk.x, q[p].y + mk.y);
                     p2[p] += cnorm(pk);
+#pragma unroll
+                    for (int i = 0; i < F; ++i) {
+                        const float2 sk = p ? make_float2(ps[i][k].z, ps[i][k].w) : make_float2(ps[i][k].x, ps[i][k].y);
+                        const float2 mk = cmulc(pk, sk);
+                        q[i][p] = make_float2(q[i][p].x + mk.x, q[i][p].y + mk.y);
+                    }
                 }
             }
         };
-        float2 qc[2];
+        float2 qc[F][2];
         float p2c[2];
         {
-            float4 ps[K], pr[K];
+            float4 ps[F][K], pr[K];
             load_px(y0, ps, pr);
             fold(ps, pr, qc, p2c);
         }
-        RawRow rn = load_row<SUB>(a.obj, a.Nx, min(Y0 + LEAD, ylast), X);
-        // rows Y-1, Y (and Y+1) of the first pixel row, clamped
-        ShiftRow wm = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, max(Y0 - 1, 0), X), a.Nx, X, wx0, wx1);
-        ShiftRow w0 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, Y0, X), a.Nx, X, wx0, wx1);
-        ShiftRow w1{};
-        if constexpr (SUB) w1 = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, min(Y0 + 1, ylast), X), a.Nx, X, wx0, wx1);
-        for (int i = 0; i < rows; ++i) {
-            const int y = y0 + i, Y = Y0 + i;
-            // prefetch (the last step loads its own row again, in bounds)
-            float4 ps2[K], pr2[K];
-            load_px(min(y + 1, ylast_px), ps2, pr2);
-            const RawRow rn2 = load_row<SUB>(a.obj, a.Nx, min(Y + 1 + LEAD, ylast), X);
-            const ShiftRow wl = make_row<SUB>(rn, a.Nx, X, wx0, wx1);     // row Y + LEAD
-            const int Ym = max(Y - 1, 0), Y1 = min(Y + 1, ylast), Y2 = min(Y + 2, ylast);
-            const float sy0 = (Y1 - Ym == 2) ? 0.5f : 1.0f, sy1 = (Y2 - Y == 2) ? 0.5f : 1.0f;
+        RawRow rn[F];
+        ShiftRow wm[F], w0[F], w1[F];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                float2 ov, gy, gx;
-                if constexpr (SUB) {
-                    const float2 gy0 = cscale(csub(w1.h[p], wm.h[p]), sy0);
-                    const float2 gy1 = cscale(csub(wl.h[p], w0.h[p]), sy1);
-                    ov = make_float2(__builtin_fmaf(vy1, w1.h[p].x, vy0 * w0.h[p].x),
-                                     __builtin_fmaf(vy1, w1.h[p].y, vy0 * w0.h[p].y));
-                    gx = make_float2(__builtin_fmaf(vy1, w1.d[p].x, vy0 * w0.d[p].x),
-                                     __builtin_fmaf(vy1, w1.d[p].y, vy0 * w0.d[p].y));
-                    gy = make_float2(__builtin_fmaf(vy1, gy1.x, vy0 * gy0.x), __builtin_fmaf(vy1, gy1.y, vy0 * gy0.y));
-                } else {
-                    ov = w0.h[p];
-                    gx = w0.d[p];
-                    gy = cscale(csub(wl.h[p], wm.h[p]), sy0);
+        for (int i = 0; i < F; ++i) {
+            const int X = of[i].y + x, Y0 = of[i].x + y0;
+            rn[i] = load_row<SUB>(a.obj, a.Nx, min(Y0 + LEAD, ylast), X);
+            // rows Y-1, Y (and Y+1) of the first pixel row, clamped
+            wm[i] = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, max(Y0 - 1, 0), X), a.Nx, X, wx0[i], wx1[i]);
+            w0[i] = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, Y0, X), a.Nx, X, wx0[i], wx1[i]);
+            w1[i] = ShiftRow{};
+            if constexpr (SUB)
+                w1[i] = make_row<SUB>(load_row<SUB>(a.obj, a.Nx, min(Y0 + 1, ylast), X), a.Nx, X, wx0[i], wx1[i]);
+        }
+        for (int r = 0; r < rows; ++r) {
+            const int y = y0 + r;
+            // prefetch (the last step loads its own row again, in bounds)
+            float4 ps2[F][K], pr2[K];
+            load_px(min(y + 1, ylast_px), ps2, pr2);
+            RawRow rn2[F];
+#pragma unroll
+            for (int i = 0; i < F; ++i)
+                rn2[i] = load_row<SUB>(a.obj, a.Nx, min(of[i].x + y + 1 + LEAD, ylast), of[i].y + x);
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                const int X = of[i].y + x, Y = of[i].x + y;
+                const ShiftRow wl = make_row<SUB>(rn[i], a.Nx, X, wx0[i], wx1[i]);     // row Y + LEAD
+                const int Ym = max(Y - 1, 0), Y1 = min(Y + 1, ylast), Y2 = min(Y + 2, ylast);
+                const float sy0 = (Y1 - Ym == 2) ? 0.5f : 1.0f, sy1 = (Y2 - Y == 2) ? 0.5f : 1.0f;
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    float2 ov, gy, gx;
+                    if constexpr (SUB) {
+                        const float2 gy0 = cscale(csub(w1[i].h[p], wm[i].h[p]), sy0);
+                        const float2 gy1 = cscale(csub(wl.h[p], w0[i].h[p]), sy1);
+                        ov = make_float2(__builtin_fmaf(vy1[i], w1[i].h[p].x, vy0[i] * w0[i].h[p].x),
+                                         __builtin_fmaf(vy1[i], w1[i].h[p].y, vy0[i] * w0[i].h[p].y));
+                        gx = make_float2(__builtin_fmaf(vy1[i], w1[i].d[p].x, vy0[i] * w0[i].d[p].x),
+                                         __builtin_fmaf(vy1[i], w1[i].d[p].y, vy0[i] * w0[i].d[p].y));
+                        gy = make_float2(__builtin_fmaf(vy1[i], gy1.x, vy0[i] * gy0.x),
+                                         __builtin_fmaf(vy1[i], gy1.y, vy0[i] * gy0.y));
+                    } else {
+                        ov = w0[i].h[p];
+                        gx = w0[i].d[p];
+                        gy = cscale(csub(wl.h[p], wm[i].h[p]), sy0);
+                    }
+                    const float2 q = qc[i][p];
+                    const float p2 = p2c[p];
+                    const float2 cc = a.ml ? cscale(q, a.chi_scale) : csub(q, cscale(ov, p2));
+                    fyy[i] += p2 * cnorm(gy);
+                    fxx[i] += p2 * cnorm(gx);
+                    fxy[i] += p2 * cmulc(gy, gx).x;
+                    fby[i] += cmulc(gy, cc).x;
+                    fbx[i] += cmulc(gx, cc).x;
                 }
-                const float2 q = qc[p];
-                const float p2 = p2c[p];
-                const float2 cc = a.ml ? cscale(q, a.chi_scale) : csub(q, cscale(ov, p2));
-                fyy += p2 * cnorm(gy);
-                fxx += p2 * cnorm(gx);
-                fxy += p2 * cmulc(gy, gx).x;
-                fby += cmulc(gy, cc).x;
-                fbx += cmulc(gx, cc).x;
+                // slide the window down one row
+                wm[i] = w0[i];
+                if constexpr (SUB) {
+                    w0[i] = w1[i];
+                    w1[i] = wl;
+                } else {
+                    w0[i] = wl;
+                }
+                rn[i] = rn2[i];
             }
-            // slide the window down one row
-            wm = w0;
-            if constexpr (SUB) {
-                w0 = w1;
-                w1 = wl;
-            } else {
-                w0 = wl;
-            }
-            rn = rn2;
             fold(ps2, pr2, qc, p2c);
         }
     }
-    const double syy = block_sum((double)fyy);
-    const double sxx = block_sum((double)fxx);
-    const double sxy = block_sum((double)fxy);
-    const double by = block_sum((double)fby);
-    const double bx = block_sum((double)fbx);
-    if (threadIdx.x == 0) {
-        double *d = a.part + ((size_t)j * a.CH + c) * 5;
-        d[0] = syy;
-        d[1] = sxx;
-        d[2] = sxy;
-        d[3] = by;
-        d[4] = bx;
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+        const double syy = block_sum((double)fyy[i]);
+        const double sxx = block_sum((double)fxx[i]);
+        const double sxy = block_sum((double)fxy[i]);
+        const double by = block_sum((double)fby[i]);
+        const double bx = block_sum((double)fbx[i]);
+        if (threadIdx.x == 0 && fg * F + i < a.nf) {
+            double *d = a.part + ((size_t)jf[i] * a.CH + c) * 5;
+            d[0] = syy;
+            d[1] = sxx;
+            d[2] = sxy;
+            d[3] = by;
+            d[4] = bx;
+        }
     }
 }
 
