@@ -356,7 +356,9 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS, (ColMinWaves<N, K, OP, NF>::va
 }
 
 // Column FFTs one mode at a time for the read-only Fourier-space steps:
-// LLK, calculated intensity, and the line-search terms I0, I1, I2.
+// LLK, calculated intensity, and the line-search terms I0, I1, I2.  The
+// transforms' inputs are read once, non-temporally (line search at 500 x
+// 256^2 x 3 modes: ML cycle 2.34 -> 2.31 ms).
 template <int N, int OP, bool NF>
 __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
     using G = ColGeom<N>;
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
             auto load_transform = [&](float2 (&v)[1][E], int set) {
                 const float2 *src = src_of(set, k);
 #pragma unroll
-                for (int e = 0; e < E; ++e) v[0][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
+                for (int e = 0; e < E; ++e) v[0][e] = ld_stream(src + in_index<N, E, -1>(t, e) * ScrTile<N>::W);
                 const int t0 = opaque(t);
                 col_transforms<N, E, -1, 1, false>(v, t0, Ls);
                 if constexpr (NF) {
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(ColGeom<N>::THREADS) void k_cols_seq(StackArgs a) {
         for (int set = 0; set < SETS; ++set) {
             const float2 *src = src_of(set, k);
 #pragma unroll
-            for (int e = 0; e < E; ++e) u[set][e] = src[in_index<N, E, -1>(t, e) * ScrTile<N>::W];
+            for (int e = 0; e < E; ++e) u[set][e] = ld_stream(src + in_index<N, E, -1>(t, e) * ScrTile<N>::W);
         }
         col_transforms<N, E, -1, SETS, ONE_BUF>(u, t, Ls);
         if constexpr (NF) {
