@@ -140,7 +140,7 @@ PTYCHO_API int ptycho_windows_from_positions(const double *pos_yx_host, int32_t 
  * Section 4: operators compute a stack of frames of the Psi array at once
  * and loop over the stacks to cover every frame (the paper's stacks hold 16
  * to 128 frames, larger ones being faster); the workspace holds that stack
- * (desc->stack frames, 0 = the largest whose scratch fits about 2 GiB), the
+ * (desc->stack frames, 0 = the largest whose scratch fits 32 GiB), the
  * plan's index tables, the overlap-update sums and the reduction partials.
  * PTYCHO_E_INVALID / PTYCHO_E_UNSUPPORTED for a bad descriptor. */
 PTYCHO_API int ptycho_workspace_bytes(const ptycho_desc_t *desc, size_t *bytes_out);

