@@ -213,3 +213,24 @@ def test_positions_plan_descriptor_and_arguments_are_checked():
     assert h.ptycho_plan_set_positions(None, fake, 1.0, 0.1) == -1
     assert h.ptycho_plan_positions(None, fake) == -1
     assert h.ptycho_refine_positions(None, fake, fake, fake, None) == -1
+
+
+def test_automatic_stack_takes_up_to_32_gib_of_scratch():
+    """The automatic stack is the largest whose scratch fits 32 GiB: a
+    4000-frame scan of 512^2 frames with 4 modes (32 GiB of frame-modes) runs
+    as one stack, a scan three times longer is split, and an explicit stack
+    of 256 frames needs far less workspace."""
+    h = _lib.lib()
+    per = 4 * 512 * 512 * 8
+    one = ctypes.c_size_t()
+    d = _desc(n=512, n_modes=4, n_frames=4000, obj_ny=4096, obj_nx=4096)
+    assert h.ptycho_workspace_bytes(ctypes.byref(d), ctypes.byref(one)) == 0
+    assert one.value >= 4000 * per                 # the whole scan's scratch
+    big = ctypes.c_size_t()
+    d = _desc(n=512, n_modes=4, n_frames=12000, obj_ny=8192, obj_nx=8192)
+    assert h.ptycho_workspace_bytes(ctypes.byref(d), ctypes.byref(big)) == 0
+    assert (32 << 30) <= big.value < 12000 * per   # capped: several stacks
+    small = ctypes.c_size_t()
+    d = _desc(n=512, n_modes=4, n_frames=4000, obj_ny=4096, obj_nx=4096, stack=256)
+    assert h.ptycho_workspace_bytes(ctypes.byref(d), ctypes.byref(small)) == 0
+    assert 256 * per <= small.value < 1000 * per
